@@ -1,0 +1,456 @@
+/*
+ * FP64 brute-force reference ("oracle") for tile-based 3D Gaussian Splatting
+ * with either the truncated exponential kernel g(x) = exp(-x/2) or the
+ * ReLU-activated polynomial kernels f_N(x) = max(sum_i c_i x^i, 0) of
+ * "From ex(p) to poly: Gaussian Splatting with Polynomial Kernels"
+ * (Mueller, Winter, Steinberger).
+ *
+ * TEST INFRASTRUCTURE ONLY. The test suite, the smoke check and the CPU
+ * baseline leg of the benchmark are the only code that loads this library.
+ * The GPU product path shares no code, header, table or constant with it.
+ *
+ * What is computed, in the paper's order:
+ *   - projection of each splat to the image plane and its screen-space
+ *     covariance (Sec. 2, Eq. 1, the EWA splatting of the 3DGS formulation);
+ *   - Mip-Splatting-like anti-aliasing: a value v added to the diagonal of
+ *     the projected covariance, opacity scaled by sqrt(|S'| / |S' + vI|)
+ *     (Sec. 3.4, Eqs. 7-9 show the ratio holds for any kernel);
+ *   - the bounding radius r = k * sqrt(lambda_max) (Sec. 2.1) with k from
+ *     3 sigma, the universal polynomial root (Eq. 5 / App. B with eps = 0),
+ *     the opacity-dependent polynomial root (Eq. 4 / App. B), or the
+ *     opacity-aware exponential bound (Eq. 3);
+ *   - front-to-back alpha compositing of depth-ordered splats per pixel with
+ *     the kernel of Eq. 2 (and the first-root cut of Eq. 6 for order 2).
+ *
+ * Every pixel is tested against every splat in depth order; no tile list is
+ * built. The tile rectangle enters only as the membership predicate "the
+ * pixel's tile lies in the splat's rectangle", since that rectangle is what
+ * decides which splats a tile-based rasterizer ever evaluates for a pixel.
+ *
+ * Roots are found by a plain scan plus bisection, never by the closed forms,
+ * so the closed forms of Eq. 3-5 and App. B can be checked against it.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { ORC_KERNEL_EXP = 0, ORC_KERNEL_POLY = 1 };
+enum {
+  ORC_RADIUS_SIGMA3 = 0,
+  ORC_RADIUS_POLY_UNIVERSAL = 1,
+  ORC_RADIUS_POLY_OPACITY = 2,
+  ORC_RADIUS_EXP_OPACITY = 3
+};
+
+/* per-splat flag bits */
+enum { ORC_SPLAT_EDGE_NEAR = 1, ORC_SPLAT_CULL_NEAR = 2 };
+/* per-pixel flag bits */
+enum { ORC_PIX_ALPHA_NEAR = 1, ORC_PIX_T_NEAR = 2, ORC_PIX_EDGE_NEAR = 4 };
+
+typedef struct {
+  int32_t kind;        /* ORC_KERNEL_* */
+  int32_t order;       /* polynomial order 1..3 */
+  int32_t radius_mode; /* ORC_RADIUS_* */
+  int32_t tile;        /* tile edge in pixels */
+  double c[4];         /* polynomial coefficients c_0..c_3 (unused ones 0) */
+  double eps;          /* contribution threshold, 1/255 in 3DGS */
+  double alpha_max;    /* alpha clamp */
+  double t_min;        /* early-termination transmittance */
+  double aa_v;         /* anti-aliasing variance added to the diagonal, px^2 */
+  double near_z;       /* near plane */
+  double radius_pad;   /* radius multiplier (>= 1) making every rectangle conservative */
+  double bg[3];        /* background colour */
+  double alpha_band;   /* |alpha - eps| below this flags a pixel */
+  double t_band_rel;   /* |T' - t_min| below t_min * this flags a pixel */
+} orc_cfg;
+
+typedef struct {
+  double R[9];  /* world -> camera rotation, row-major */
+  double t[3];  /* world -> camera translation */
+  double fx, fy, cx, cy;
+  int32_t width, height;
+} orc_cam;
+
+/* ------------------------------------------------------------------ */
+/* kernel functions (Eq. 2, Eq. 6)                                      */
+/* ------------------------------------------------------------------ */
+
+/* p(x) = c_0 + c_1 x + c_2 x^2 + c_3 x^3, written as the plain sum. */
+double orc_poly(const double *c, int order, double x) {
+  double s = 0.0, xp = 1.0;
+  for (int i = 0; i <= order; ++i) {
+    s += c[i] * xp;
+    xp *= x;
+  }
+  return s;
+}
+
+/* Smallest x >= 0 with p(x) = target: App. B bounds each splat by the first
+ * real positive root of the shifted polynomial. Scans [0, xmax] in steps of h for the first sign change of
+ * p(x) - target, then bisects to full double precision and returns the upper
+ * end of the final bracket, so p(root) - target <= 0 holds as evaluated. Returns -1 when
+ * p(0) < target (no non-negative solution in the decreasing branch) or when
+ * no sign change is found up to xmax. */
+double orc_first_root(const double *c, int order, double target) {
+  double f0 = orc_poly(c, order, 0.0) - target;
+  if (f0 < 0.0) return -1.0;
+  if (f0 == 0.0) return 0.0;
+  const double h = 1.0 / 1024.0, xmax = 4096.0;
+  double a = 0.0;
+  for (;;) {
+    double b = a + h;
+    if (b > xmax) return -1.0;
+    double fb = orc_poly(c, order, b) - target;
+    if (fb <= 0.0) {
+      if (fb == 0.0) return b;
+      double lo = a, hi = b;
+      for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double fm = orc_poly(c, order, mid) - target;
+        if (fm > 0.0) lo = mid; else hi = mid;
+      }
+      return hi; /* the smallest double found with p(x) - target <= 0 */
+    }
+    a = b;
+  }
+}
+
+/* the kernel k(Q) applied to the quadric value Q */
+double orc_kernel(const orc_cfg *cfg, double x0, double Q) {
+  if (cfg->kind == ORC_KERNEL_EXP) return exp(-0.5 * Q);
+  /* Eq. 6: order 2 uses the polynomial only before its first root */
+  if (cfg->order == 2 && Q >= x0) return 0.0;
+  double p = orc_poly(cfg->c, cfg->order, Q);
+  return p > 0.0 ? p : 0.0;
+}
+
+/* k(Q) for an array of quadric values */
+void orc_kernel_many(const orc_cfg *cfg, int64_t m, const double *Q, double *out) {
+  double x0 = (cfg->kind == ORC_KERNEL_POLY) ? orc_first_root(cfg->c, cfg->order, 0.0) : 0.0;
+  for (int64_t i = 0; i < m; ++i) out[i] = orc_kernel(cfg, x0, Q[i]);
+}
+
+/* ------------------------------------------------------------------ */
+/* real spherical harmonics up to degree 3, orthonormal on the sphere  */
+/* ------------------------------------------------------------------ */
+
+/* Y_k(d) for k = 0..(deg+1)^2-1 at the unit direction (x, y, z), in the
+ * ordering and sign convention used by 3DGS colour coefficients
+ * (m = -l..l within each band, Condon-Shortley phase on odd m). */
+void orc_sh_basis(int deg, double x, double y, double z, double *Y) {
+  const double PI = 3.14159265358979323846;
+  Y[0] = sqrt(1.0 / (4.0 * PI));
+  if (deg < 1) return;
+  double k1 = sqrt(3.0 / (4.0 * PI));
+  Y[1] = -k1 * y;
+  Y[2] = k1 * z;
+  Y[3] = -k1 * x;
+  if (deg < 2) return;
+  double k2a = sqrt(15.0 / (4.0 * PI));
+  double k2b = sqrt(5.0 / (16.0 * PI));
+  double k2c = sqrt(15.0 / (16.0 * PI));
+  Y[4] = k2a * x * y;
+  Y[5] = -k2a * y * z;
+  Y[6] = k2b * (2.0 * z * z - x * x - y * y);
+  Y[7] = -k2a * x * z;
+  Y[8] = k2c * (x * x - y * y);
+  if (deg < 3) return;
+  double k3a = sqrt(35.0 / (32.0 * PI));
+  double k3b = sqrt(105.0 / (4.0 * PI));
+  double k3c = sqrt(21.0 / (32.0 * PI));
+  double k3d = sqrt(7.0 / (16.0 * PI));
+  double k3e = sqrt(105.0 / (16.0 * PI));
+  Y[9] = -k3a * y * (3.0 * x * x - y * y);
+  Y[10] = k3b * x * y * z;
+  Y[11] = -k3c * y * (4.0 * z * z - x * x - y * y);
+  Y[12] = k3d * z * (2.0 * z * z - 3.0 * x * x - 3.0 * y * y);
+  Y[13] = -k3c * x * (4.0 * z * z - x * x - y * y);
+  Y[14] = k3e * z * (x * x - y * y);
+  Y[15] = -k3a * x * (x * x - 3.0 * y * y);
+}
+
+/* ------------------------------------------------------------------ */
+/* projection of one splat                                              */
+/* ------------------------------------------------------------------ */
+
+static int near_integer(double e) { return fabs(e - nearbyint(e)) < 1e-9; }
+
+static long clamp_floor(double e, long lo, long hi) {
+  if (!(e >= (double)lo)) return lo; /* also catches NaN */
+  if (e >= (double)hi + 1.0) return hi;
+  long f = (long)floor(e);
+  if (f < lo) f = lo;
+  if (f > hi) f = hi;
+  return f;
+}
+
+/* Projects n splats. Inputs (double; the single-precision scene converts
+ * exactly) are the scene in activated form: scales are
+ * standard deviations, quats are (w, x, y, z) and need not be normalised,
+ * opacity in [0, 1], sh is [n][(deg+1)^2][3].
+ * Outputs (per splat): means2d[2], conic[3] = upper triangle (a, b, c) of
+ * the inverse of the anti-aliased covariance, opac = anti-aliased opacity,
+ * rgb[3], depth (camera z), depth32 (z rounded to float), radius (pixels),
+ * rect[4] = inclusive tile rectangle (x_lo, y_lo, x_hi, y_hi) or
+ * (0, 0, -1, -1) when empty, tiles = tiles in the rectangle, flags. */
+void orc_project(const orc_cfg *cfg, const orc_cam *cam, int64_t n,
+                 const double *means3d, const double *scales, const double *quats,
+                 const double *opacity, const double *sh, int32_t sh_degree,
+                 double *means2d, double *conic, double *opac, double *rgb,
+                 double *depth, float *depth32, double *radius, int32_t *rect,
+                 int64_t *tiles, uint8_t *flags) {
+  const int T = cfg->tile;
+  const long gx = (cam->width + T - 1) / T, gy = (cam->height + T - 1) / T;
+  const int nsh = (sh_degree + 1) * (sh_degree + 1);
+  const double x0 = (cfg->kind == ORC_KERNEL_POLY || cfg->radius_mode == ORC_RADIUS_POLY_UNIVERSAL ||
+                     cfg->radius_mode == ORC_RADIUS_POLY_OPACITY)
+                        ? orc_first_root(cfg->c, cfg->order, 0.0)
+                        : 0.0;
+  const double *Rc = cam->R;
+  /* camera centre in world space: -R^T t */
+  double campos[3];
+  for (int i = 0; i < 3; ++i)
+    campos[i] = -(Rc[0 * 3 + i] * cam->t[0] + Rc[1 * 3 + i] * cam->t[1] + Rc[2 * 3 + i] * cam->t[2]);
+
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double m[3] = {means3d[3 * i], means3d[3 * i + 1], means3d[3 * i + 2]};
+    double tc[3];
+    for (int r = 0; r < 3; ++r)
+      tc[r] = Rc[3 * r + 0] * m[0] + Rc[3 * r + 1] * m[1] + Rc[3 * r + 2] * m[2] + cam->t[r];
+
+    means2d[2 * i] = means2d[2 * i + 1] = 0.0;
+    conic[3 * i] = conic[3 * i + 1] = conic[3 * i + 2] = 0.0;
+    opac[i] = 0.0;
+    rgb[3 * i] = rgb[3 * i + 1] = rgb[3 * i + 2] = 0.0;
+    depth[i] = tc[2];
+    depth32[i] = (float)tc[2];
+    radius[i] = 0.0;
+    rect[4 * i] = 0; rect[4 * i + 1] = 0; rect[4 * i + 2] = -1; rect[4 * i + 3] = -1;
+    tiles[i] = 0;
+    flags[i] = 0;
+
+    if (tc[2] < cfg->near_z) continue;
+
+    /* 3D covariance: Sigma = R(q) diag(s)^2 R(q)^T */
+    double qw = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
+    double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+    double Rq[3][3] = {
+        {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
+        {2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)},
+        {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
+    double s2[3] = {scales[3 * i] * scales[3 * i], scales[3 * i + 1] * scales[3 * i + 1],
+                    scales[3 * i + 2] * scales[3 * i + 2]};
+    double Sig[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += Rq[a][k] * s2[k] * Rq[b][k];
+        Sig[a][b] = acc;
+      }
+
+    /* EWA: Sigma' = J W Sigma W^T J^T, J the Jacobian of the perspective map
+     * at the camera-space mean, with x/z and y/z clamped to 1.3 tan(fov/2). */
+    double tz = tc[2];
+    double limx = 1.3 * (cam->width / (2.0 * cam->fx));
+    double limy = 1.3 * (cam->height / (2.0 * cam->fy));
+    double txz = tc[0] / tz, tyz = tc[1] / tz;
+    if (txz < -limx) txz = -limx;
+    if (txz > limx) txz = limx;
+    if (tyz < -limy) tyz = -limy;
+    if (tyz > limy) tyz = limy;
+    double J[2][3] = {{cam->fx / tz, 0.0, -cam->fx * txz / tz},
+                      {0.0, cam->fy / tz, -cam->fy * tyz / tz}};
+    double TW[2][3];
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += J[a][k] * Rc[3 * k + b];
+        TW[a][b] = acc;
+      }
+    double S2[2][2];
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k)
+          for (int l = 0; l < 3; ++l) acc += TW[a][k] * Sig[k][l] * TW[b][l];
+        S2[a][b] = acc;
+      }
+    double sxy = 0.5 * (S2[0][1] + S2[1][0]);
+
+    /* anti-aliasing (Sec. 3.4) */
+    double det0 = S2[0][0] * S2[1][1] - sxy * sxy;
+    double A00 = S2[0][0] + cfg->aa_v, A11 = S2[1][1] + cfg->aa_v;
+    double deta = A00 * A11 - sxy * sxy;
+    if (!(deta > 0.0)) continue;
+    double ratio = det0 / deta;
+    double o = opacity[i] * sqrt(ratio > 0.0 ? ratio : 0.0);
+
+    double u = cam->fx * tc[0] / tz + cam->cx;
+    double v = cam->fy * tc[1] / tz + cam->cy;
+
+    /* bounding radius, r = k sqrt(lambda_max) (Sec. 2.1 and Sec. 3.2) */
+    double mid = 0.5 * (A00 + A11);
+    double disc = mid * mid - deta;
+    double lmax = mid + sqrt(disc > 0.0 ? disc : 0.0);
+    double k;
+    int cull = 0, cull_near = 0;
+    switch (cfg->radius_mode) {
+      case ORC_RADIUS_SIGMA3:
+        k = 3.0;
+        break;
+      case ORC_RADIUS_POLY_UNIVERSAL:
+        k = sqrt(x0);
+        break;
+      case ORC_RADIUS_POLY_OPACITY: {
+        /* opacity-dependent: first root of o p(x) = eps, i.e. p(x) = eps / o */
+        double target = cfg->eps / o;
+        double c0 = cfg->c[0];
+        cull_near = fabs(o * c0 - cfg->eps) <= 1e-9 * cfg->eps;
+        double xr = (o > 0.0) ? orc_first_root(cfg->c, cfg->order, target) : -1.0;
+        if (xr < 0.0) { cull = 1; k = 0.0; } else k = sqrt(xr);
+        break;
+      }
+      default: { /* ORC_RADIUS_EXP_OPACITY: the Mahalanobis radius where o exp(-x/2) = eps */
+        cull_near = fabs(o - cfg->eps) <= 1e-9 * cfg->eps;
+        if (!(o >= cfg->eps)) { cull = 1; k = 0.0; } else k = sqrt(2.0 * log(o / cfg->eps));
+        break;
+      }
+    }
+    if (cull_near) flags[i] |= ORC_SPLAT_CULL_NEAR;
+    if (cull) continue;
+    double r = k * sqrt(lmax) * cfg->radius_pad;
+
+    double ex0 = (u - r) / T, ex1 = (u + r) / T, ey0 = (v - r) / T, ey1 = (v + r) / T;
+    if (near_integer(ex0) || near_integer(ex1) || near_integer(ey0) || near_integer(ey1))
+      flags[i] |= ORC_SPLAT_EDGE_NEAR;
+    long xlo = clamp_floor(ex0, 0, gx), xhi = clamp_floor(ex1, -1, gx - 1);
+    long ylo = clamp_floor(ey0, 0, gy), yhi = clamp_floor(ey1, -1, gy - 1);
+    long nt = (xhi >= xlo && yhi >= ylo) ? (xhi - xlo + 1) * (yhi - ylo + 1) : 0;
+
+    means2d[2 * i] = u;
+    means2d[2 * i + 1] = v;
+    conic[3 * i] = A11 / deta;
+    conic[3 * i + 1] = -sxy / deta;
+    conic[3 * i + 2] = A00 / deta;
+    opac[i] = o;
+    radius[i] = r;
+    /* an empty rectangle is stored as (0, 0, -1, -1), except for a splat whose
+     * edge sits on a tile boundary: there the clamped bounds are kept so the
+     * renderer can flag the pixels next to that edge */
+    if (nt > 0 || (flags[i] & ORC_SPLAT_EDGE_NEAR)) {
+      rect[4 * i] = (int32_t)xlo; rect[4 * i + 1] = (int32_t)ylo;
+      rect[4 * i + 2] = (int32_t)xhi; rect[4 * i + 3] = (int32_t)yhi;
+    }
+    tiles[i] = nt;
+
+    /* view-dependent colour, direction from the camera centre to the mean */
+    double d[3] = {m[0] - campos[0], m[1] - campos[1], m[2] - campos[2]};
+    double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double Y[16];
+    orc_sh_basis(sh_degree, d[0] / dn, d[1] / dn, d[2] / dn, Y);
+    for (int ch = 0; ch < 3; ++ch) {
+      double acc = 0.0;
+      for (int kk = 0; kk < nsh; ++kk) acc += Y[kk] * sh[(i * nsh + kk) * 3 + ch];
+      acc += 0.5;
+      rgb[3 * i + ch] = acc > 0.0 ? acc : 0.0;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* depth order                                                          */
+/* ------------------------------------------------------------------ */
+
+typedef struct { float d; int64_t i; } orc_order_item;
+
+static int order_cmp(const void *a, const void *b) {
+  const orc_order_item *x = (const orc_order_item *)a, *y = (const orc_order_item *)b;
+  if (x->d < y->d) return -1;
+  if (x->d > y->d) return 1;
+  return (x->i < y->i) ? -1 : (x->i > y->i);
+}
+
+/* Splat order for compositing: ascending depth32, ties broken by index. */
+void orc_depth_order(int64_t n, const float *depth32, int64_t *order_out) {
+  orc_order_item *it = (orc_order_item *)malloc(sizeof(orc_order_item) * (size_t)(n > 0 ? n : 1));
+  for (int64_t i = 0; i < n; ++i) { it[i].d = depth32[i]; it[i].i = i; }
+  qsort(it, (size_t)n, sizeof(orc_order_item), order_cmp);
+  for (int64_t i = 0; i < n; ++i) order_out[i] = it[i].i;
+  free(it);
+}
+
+/* ------------------------------------------------------------------ */
+/* compositing                                                          */
+/* ------------------------------------------------------------------ */
+
+/* Renders npix pixels given by integer coordinates px[2*j], px[2*j+1].
+ * The splat records are the projection outputs (any precision the caller
+ * chooses to round them to, held here as doubles); order is the depth order.
+ * Per pixel: colour[3], final transmittance, number of blended splats,
+ * number of evaluated splats (candidates up to and including a terminating
+ * one), 1 + list position of the last blended splat (0 if none), and flags
+ * for decisions that sit too close to a threshold to be reproduced by a
+ * single-precision evaluation. splat_flags may be NULL. */
+void orc_render_pixels(const orc_cfg *cfg, int64_t n, const int64_t *order,
+                       const double *means2d, const double *conic, const double *opac,
+                       const double *rgb, const int32_t *rect, const uint8_t *splat_flags,
+                       int64_t npix, const int32_t *px, double *color, double *final_T,
+                       int32_t *n_contrib, int32_t *n_eval, int32_t *last_contrib,
+                       uint8_t *pix_flags) {
+  const int T = cfg->tile;
+  const double x0 = (cfg->kind == ORC_KERNEL_POLY) ? orc_first_root(cfg->c, cfg->order, 0.0) : 0.0;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t j = 0; j < npix; ++j) {
+    int x = px[2 * j], y = px[2 * j + 1];
+    int tx = x / T, ty = y / T;
+    double cx = x + 0.5, cy = y + 0.5;
+    double Tr = 1.0, C[3] = {0.0, 0.0, 0.0};
+    int32_t ncon = 0, nev = 0, last = 0;
+    uint8_t fl = 0;
+    for (int64_t s = 0; s < n; ++s) {
+      int64_t i = order[s];
+      const int32_t *rc = rect + 4 * i;
+      if (splat_flags && (splat_flags[i] & ORC_SPLAT_EDGE_NEAR)) {
+        /* a rectangle edge this close to a tile boundary may land on either side */
+        if (tx >= rc[0] - 1 && tx <= rc[2] + 1 && ty >= rc[1] - 1 && ty <= rc[3] + 1 &&
+            (tx <= rc[0] || tx >= rc[2] || ty <= rc[1] || ty >= rc[3]))
+          fl |= ORC_PIX_EDGE_NEAR;
+      }
+      if (!(tx >= rc[0] && tx <= rc[2] && ty >= rc[1] && ty <= rc[3])) continue;
+      ++nev;
+      double dx = cx - means2d[2 * i], dy = cy - means2d[2 * i + 1];
+      double Q = conic[3 * i] * dx * dx + 2.0 * conic[3 * i + 1] * dx * dy + conic[3 * i + 2] * dy * dy;
+      double a = opac[i] * orc_kernel(cfg, x0, Q);
+      if (a > cfg->alpha_max) a = cfg->alpha_max;
+      if (fabs(a - cfg->eps) <= cfg->alpha_band) fl |= ORC_PIX_ALPHA_NEAR;
+      if (a < cfg->eps) continue;
+      double Tn = Tr * (1.0 - a);
+      if (fabs(Tn - cfg->t_min) <= cfg->t_band_rel * cfg->t_min) fl |= ORC_PIX_T_NEAR;
+      if (Tn < cfg->t_min) break;
+      for (int ch = 0; ch < 3; ++ch) C[ch] += rgb[3 * i + ch] * a * Tr;
+      Tr = Tn;
+      ++ncon;
+      last = nev;
+    }
+    for (int ch = 0; ch < 3; ++ch) color[3 * j + ch] = C[ch] + Tr * cfg->bg[ch];
+    final_T[j] = Tr;
+    n_contrib[j] = ncon;
+    n_eval[j] = nev;
+    last_contrib[j] = last;
+    pix_flags[j] = fl;
+  }
+}
+
+/* number of threads OpenMP will use */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  extern int omp_get_max_threads(void);
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,209 @@
+"""Throughput of the polynomial-kernel splatting path on one MI355X.
+
+Workload: 1,000,000 splats (64 anisotropic clusters in a 20-unit box, log-scales
+N(-4.5, 1), opacity logits N(0, 2), SH degree 3), one 1920x1080 camera at
+distance 30 with a 60 degree field of view. A step is one full frame:
+gs_preprocess -> gs_bin_sort -> gs_rasterize_fwd, inputs resident in HBM.
+
+Headline: poly order 1 with the opacity-dependent radius (Eq. 4); the same
+frame with the exponential kernel and 3-sigma culling is timed on the same GPU
+for comparison. Prints one JSON line (see the repository's benchmark contract).
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s and splat-pixel evals/s, poly-1 vs exp kernel, 1M splats 1080p, err≤2e-4"
+
+# Algorithmic VALU lane-operations of the blend (one op per add, multiply,
+# FMA, min/max, compare or exp), the count the kernel is measured against:
+#   every evaluated (pixel, splat) pair: dx, dy (2), quadric a dx^2 + 2b dx dy
+#   + c dy^2 (5), kernel (poly-1: 1 FMA; exp: add + exp = 2; poly-2: 3;
+#   poly-3: 4), alpha clamp (1), eps test (1);
+#   every blended pair in addition: 1 - alpha, T' (2), t_min test (1),
+#   alpha T (1), colour FMAs (3).
+OPS_EVAL = {"poly1": 10, "exp": 11, "poly2": 12, "poly3": 13}
+OPS_BLEND = 7
+# MI355X vector ALU issue peak without packed FP32: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz = 39.3e12 lane-ops/s (the 157.3 TFLOP/s FP32 figure counts
+# packed FMA as 4 flops; packed FP32 is disabled in this build).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--only", default=None, help="time one configuration: poly1|exp")
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha1()
+    with open(os.path.join(ROOT, "paper_2603_18707_amd", "csrc", "rasterize.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:12]
+
+
+def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup):
+    """Times `steps` frames; per-stage HIP events inside the same timed loop."""
+    r = render.Rasterizer(render.kernel_spec(kind, order, radius))
+    stream = torch.cuda.current_stream()
+    # warm-up frames also size the key capacity (host readback happens here only)
+    for _ in range(max(warmup, 1)):
+        out = r.render(scene, cam)
+    torch.cuda.synchronize()
+    K = int(out["binned"]["num_keys"].item())
+    r.capacity = int(K * 1.05) + 4096
+    r.bin_sort(out["proj"], cam)  # re-size buffers for the final capacity outside the timed loop
+    torch.cuda.synchronize()
+
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for s in range(steps):
+        e = ev[s]
+        e[0].record(stream)
+        proj = r.preprocess(scene, cam)
+        e[1].record(stream)
+        b = r.bin_sort(proj, cam)
+        e[2].record(stream)
+        r.rasterize(proj, b, cam)
+        e[3].record(stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    assert int(b["overflow"].item()) == 0
+    total_ms = start.elapsed_time(stop)
+    st = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])] for e in ev])
+
+    # untimed frame with the evaluation counter
+    full = r.rasterize(proj, b, cam, want_eval=True)
+    torch.cuda.synchronize()
+    E = int(full["n_eval"].sum().item())
+    B = int(full["n_contrib"].sum().item())
+    return dict(ms=total_ms / steps, stage_ms=st.mean(axis=0).tolist(), blend_ms=float(st[:, 2].mean()),
+                K=int(b["num_keys"].item()), E=E, B=B, image=full["image"].clone(), rast=r)
+
+
+def cpu_baseline(scene_np, cam, gpu_image, target_s):
+    """The FP64 oracle on a bounded pixel sample of the same frame (poly-1, opacity radius)."""
+    from oracle import core as ocore
+
+    c = (0.773, -0.773 / 4.386)
+    cfg = ocore.Cfg(kind=ocore.KERNEL_POLY, order=1, radius_mode=ocore.RADIUS_POLY_OPACITY, coeffs=c,
+                    alpha_band=2e-6)
+    t0 = time.perf_counter()
+    proj = ocore.project(scene_np, cam, cfg)
+    rec = ocore.round_records(proj)
+    order = ocore.depth_order(proj["depth32"])
+    t_setup = time.perf_counter() - t0
+    W, H = int(cam.width), int(cam.height)
+    from paper_2603_18707_amd import scenes
+    probe = scenes.sample_pixels(W, H, 256, seed=77)
+    t0 = time.perf_counter()
+    ocore.render_pixels(rec, cfg, probe, order)
+    per_px = (time.perf_counter() - t0) / probe.shape[0]
+    m = int(min(W * H, max(256, (target_s - t_setup) / max(per_px, 1e-9))))
+    pix = scenes.sample_pixels(W, H, m, seed=78)
+    t0 = time.perf_counter()
+    res = ocore.render_pixels(rec, cfg, pix, order)
+    t_px = time.perf_counter() - t0
+    full_s = t_setup + t_px * (W * H) / m
+    g = gpu_image[:, pix[:, 1], pix[:, 0]].T
+    good = res["flags"] == 0
+    err = float(np.abs(g - res["color"]).max(axis=1)[good].max())
+    return dict(value=W * H / full_s / 1e6, unit="Mpix/s", cores=ocore.num_threads(), kind="oracle",
+                sample=f"{m} of {W * H} pixels of the poly-1/opacity frame after a full FP64 projection of "
+                       f"all splats; full-frame time extrapolated {full_s:.1f} s",
+                seconds=round(t_setup + t_px, 2)), err, int((~good).sum()), m
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2603_18707_amd import _lib, render, scenes
+
+    _lib.lib()
+    torch.cuda.set_device(0)
+    print(f"[bench] {_lib.gs_version()} on {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
+    scene_np, cam = scenes.workload_scene()
+    scene = render.to_device(scene_np)
+    W, H = cam.width, cam.height
+    configs = [("poly1", "poly", 1, "opacity"), ("exp", "exp", 1, "sigma3")]
+    if a.only:
+        configs = [c for c in configs if c[0] == a.only]
+    res = {}
+    for name, kind, order, radius in configs:
+        res[name] = time_config(torch, render, scene, cam, kind, order, radius, a.steps, a.warmup)
+        r = res[name]
+        print(f"[bench] {name}: {r['ms']:.3f} ms/frame (pre {r['stage_ms'][0]:.3f}, sort {r['stage_ms'][1]:.3f},"
+              f" blend {r['stage_ms'][2]:.3f}) K={r['K']} E={r['E']}", file=sys.stderr, flush=True)
+
+    head = res[configs[0][0]]
+    ms = head["ms"]
+    mpix = W * H / (ms * 1e-3) / 1e6
+    evals = head["E"] / (ms * 1e-3)
+    hname = configs[0][0]
+    ops = head["E"] * OPS_EVAL[hname] + head["B"] * OPS_BLEND
+    achieved = ops / (head["blend_ms"] * 1e-3) / 1e12
+
+    traffic = None
+    prof = os.path.join(ROOT, "profiles", "blend_poly1_scene1m_1080p_counters.json")
+    if os.path.exists(prof):
+        with open(prof) as f:
+            pc = json.load(f)
+        if pc.get("kernel_source_sha1") == kernel_source_hash():
+            traffic = pc.get("hbm_bytes_per_launch")
+
+    out = {
+        "metric": METRIC, "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "1M splats (64 clusters, SH3), 1920x1080, poly-1 kernel, opacity-dependent radius",
+                   "splats": scene.n, "width": W, "height": H, "kernel": "poly1", "radius": "opacity"},
+        "splat_pixel_evals_per_s": round(evals, 1),
+        "keys": head["K"], "evals": head["E"], "blended": head["B"],
+        "stage_ms": {"preprocess": round(head["stage_ms"][0], 4), "bin_sort": round(head["stage_ms"][1], 4),
+                     "blend": round(head["stage_ms"][2], 4)},
+        "roofline": {"bound": "alu", "kernel": "blend_fwd<poly1>", "achieved": round(achieved, 3),
+                     "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s",
+                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic},
+    }
+    if "exp" in res and hname != "exp":
+        e = res["exp"]
+        out["exp_sigma3"] = {"ms_per_step": round(e["ms"], 4), "Mpix_per_s": round(W * H / (e["ms"] * 1e-3) / 1e6, 2),
+                             "splat_pixel_evals_per_s": round(e["E"] / (e["ms"] * 1e-3), 1), "keys": e["K"],
+                             "evals": e["E"],
+                             "stage_ms": {"preprocess": round(e["stage_ms"][0], 4),
+                                          "bin_sort": round(e["stage_ms"][1], 4),
+                                          "blend": round(e["stage_ms"][2], 4)}}
+        out["speedup_vs_exp_sigma3"] = round(e["ms"] / ms, 4)
+    if not a.no_cpu and hname == "poly1":
+        print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
+        cb, err, nflag, m = cpu_baseline(scene_np, cam, head["image"].cpu().numpy(), a.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["max_abs_err_vs_oracle"] = err
+        out["oracle_flagged_pixels"] = f"{nflag} of {m}"
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

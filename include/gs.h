@@ -1,0 +1,249 @@
+/*
+ * gs.h -- C ABI of libgs, a gfx950 (MI355X) rasterizer for 3D Gaussian
+ * Splatting with the truncated exponential kernel g(x) = exp(-x/2) or the
+ * ReLU-activated polynomial kernels f_N(x) = max(sum_i c_i x^i, 0), N = 1..3,
+ * and the tighter culling radii they allow, after "From ex(p) to poly:
+ * Gaussian Splatting with Polynomial Kernels" (Mueller, Winter, Steinberger).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers to caller-owned, contiguous buffers
+ *    in the layouts stated below (row-major, float = IEEE binary32). The
+ *    library never allocates, frees or retains them.
+ *  - Struct arguments (gs_camera, gs_kernel, gs_params) are HOST pointers;
+ *    they are read during the call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Entry
+ *    points only enqueue work on it and return; results are valid once the
+ *    stream reaches them. Nothing synchronises with the host.
+ *  - Every argument is checked on the host before any HIP call. A bad argument
+ *    returns GS_EINVAL (GS_EUNSUPPORTED for a valid but unsupported setting)
+ *    and enqueues nothing. A failed launch returns GS_EHIP. gs_last_error()
+ *    describes the last failure on the calling thread.
+ *  - Inputs are never written. Outputs are written in full for every splat,
+ *    pixel or tile in range, so they need no clearing beforehand.
+ *  - Splat and key indices are 32-bit: n < 2^31 splats, key_capacity < 2^32.
+ *  - Calls that share buffers must be ordered on one stream by the caller.
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GS_OK = 0,
+  GS_EINVAL = -1,        /* bad argument, nothing enqueued */
+  GS_EUNSUPPORTED = -2,  /* valid but unsupported setting, nothing enqueued */
+  GS_ECAPACITY = -3,     /* reserved for callers that read the overflow flag */
+  GS_EHIP = -4           /* a HIP runtime call or launch failed */
+} gs_status;
+
+/* Kernel applied to the screen-space quadric Q(v) = (v - mu')^T S'^-1 (v - mu')
+ * (Sec. 2, Eq. 1). EXP: g(Q) = exp(-Q/2) (Sec. 3). POLY: f_N(Q) =
+ * max(sum_{i<=N} c_i Q^i, 0) (Sec. 3, Eq. 2); for N = 2 the polynomial is used
+ * only for Q below its first positive root x_0 and is 0 beyond (Sec. 3.3,
+ * Eq. 6), since the fitted parabola rises again. */
+typedef enum { GS_KERNEL_EXP = 0, GS_KERNEL_POLY = 1 } gs_kernel_kind;
+
+/* Bounding radius r = k * sqrt(lambda_max(S')) of a projected splat, with
+ * lambda_max the larger eigenvalue of its anti-aliased 2D covariance
+ * (Sec. 2.1). The multiplier k is
+ *   SIGMA3:          3 (the 3DGS square bound, Sec. 2.1);
+ *   POLY_UNIVERSAL:  sqrt(x_0), x_0 the first positive root of the polynomial,
+ *                    the same for every splat (Sec. 3.2, Eq. 5; App. B with
+ *                    eps = 0);
+ *   POLY_OPACITY:    sqrt(x_e), x_e the first positive root of
+ *                    o' p(x) = eps for the splat's opacity o' (Sec. 3.2, Eq. 4;
+ *                    App. B); splats with o' c_0 < eps are culled;
+ *   EXP_OPACITY:     sqrt(2 ln(o'/eps)), where o' exp(-x/2) falls to eps
+ *                    (Sec. 3.2, Eq. 3); splats with o' < eps are culled.
+ * POLY_* modes take the polynomial of the gs_kernel even when kind is EXP:
+ * that pairs the exponential with the polynomial's tighter culling, the
+ * setting the paper shows to produce blocky artefacts (Sec. 5.2, Fig. 3a). */
+typedef enum {
+  GS_RADIUS_SIGMA3 = 0,
+  GS_RADIUS_POLY_UNIVERSAL = 1,
+  GS_RADIUS_POLY_OPACITY = 2,
+  GS_RADIUS_EXP_OPACITY = 3
+} gs_radius_mode;
+
+typedef struct {
+  int32_t kind;        /* gs_kernel_kind */
+  int32_t order;       /* polynomial order N in 1..3 (read for POLY and for POLY_* radii) */
+  int32_t radius_mode; /* gs_radius_mode */
+  int32_t reserved;    /* must be 0 */
+  double coeffs[4];    /* c_0..c_3; entries above `order` are ignored. The polynomial must
+                          satisfy c_0 > 0 and decrease on [0, x_0] (true for the paper's
+                          fits); otherwise GS_EUNSUPPORTED. */
+} gs_kernel;
+
+typedef struct {
+  float eps;        /* contribution threshold: alpha < eps is skipped (1/255, Sec. 3.1) */
+  float alpha_max;  /* alpha is clamped to this (0.99) */
+  float t_min;      /* a pixel stops before the splat that takes T below this (1e-4) */
+  float aa_v;       /* anti-aliasing: added to the diagonal of the 2D covariance, px^2 (0.3) */
+  float near_z;     /* splats with camera z below this are culled (0.2) */
+  float radius_pad; /* r is multiplied by this (>= 1; 1 + 2^-20 keeps rectangles conservative) */
+  float bg[3];      /* background colour added as T * bg */
+  int32_t tile;     /* tile edge in pixels; only 16 is supported */
+} gs_params;
+
+typedef struct {
+  float viewmat[16]; /* world -> camera, row-major 4x4; camera x right, y down, z forward.
+                        The rotation block must be orthonormal; the last row is ignored. */
+  float fx, fy;      /* focal lengths in pixels */
+  float cx, cy;      /* principal point in pixels; pixel (i, j) has its centre at (i+0.5, j+0.5) */
+  int32_t width, height; /* image size, 1..32768 each */
+} gs_camera;
+
+/* ---------------------------------------------------------------------- */
+/* host-only helpers (no HIP calls)                                        */
+/* ---------------------------------------------------------------------- */
+
+const char *gs_version(void);
+
+/* Message for the last non-GS_OK status returned on the calling thread. */
+const char *gs_last_error(void);
+
+/* Fills `out` with the library's coefficient table for (kind, order,
+ * radius_mode). Order 1 uses Sec. 3.1's printed first-order pair (intercept
+ * 0.773, root 4.386); orders 2 and 3 use the library's own L1 fit on
+ * [0, 2 ln 255] (Sec. 3.1 fitting; Sec. 3.3). */
+gs_status gs_kernel_default(int32_t kind, int32_t order, int32_t radius_mode, gs_kernel *out);
+
+/* First positive root x_0 of the kernel's polynomial (App. B closed forms:
+ * linear, quadratic formula, Cardano), after the checks gs_preprocess makes. */
+gs_status gs_kernel_root(const gs_kernel *kernel, double *x0_out);
+
+/* eps 1/255, alpha_max 0.99, t_min 1e-4, aa_v 0.3, near_z 0.2,
+ * radius_pad 1 + 2^-20, bg 0, tile 16. */
+gs_status gs_params_default(gs_params *out);
+
+/* ---------------------------------------------------------------------- */
+/* forward path                                                            */
+/* ---------------------------------------------------------------------- */
+
+/* Per-splat projection (Sec. 2 Eq. 1; Sec. 2.1; Sec. 3.2 Eqs. 3-5; Sec. 3.4;
+ * App. B). For each splat i < n:
+ *   camera-space mean t = W mu + tw; depth[i] = t.z rounded to float;
+ *   culled when t.z < near_z;
+ *   S = R(q) diag(s)^2 R(q)^T; S' = J W S W^T J^T with J the Jacobian of the
+ *   perspective map at t (x/z and y/z clamped to 1.3 tan of the half field of
+ *   view); anti-aliasing S_a = S' + aa_v I, o' = o sqrt(|S'| / |S_a|);
+ *   conic = S_a^-1; mean2d = (fx t.x/t.z + cx, fy t.y/t.z + cy);
+ *   r = k sqrt(lambda_max(S_a)) * radius_pad (k per gs_radius_mode);
+ *   rect = inclusive tile rectangle (x_lo, y_lo, x_hi, y_hi) with
+ *   x_lo = clamp(floor((u - r)/tile), 0, gx), x_hi = clamp(floor((u + r)/tile), -1, gx - 1)
+ *   and likewise in y, stored as (0, 0, -1, -1) when empty;
+ *   tiles_touched = tiles in rect;
+ *   rgb = max(sum_k Y_k(d) sh_k + 0.5, 0) with real SH of degree sh_degree at
+ *   d = normalize(mu - camera centre).
+ * Geometry up to the rectangle is computed in double precision, so depth and
+ * rectangles are reproducible; the record is rounded to float on output.
+ * Culled splats get zero means2d, conic_opacity and rgb, rect (0,0,-1,-1)
+ * and tiles_touched 0 (depth is still written).
+ *
+ * in : means3d [n,3], scales [n,3] (standard deviations), quats [n,4]
+ *      (w,x,y,z, need not be normalised), opacities [n] in [0,1],
+ *      sh [n,(sh_degree+1)^2,3], sh_degree in 0..3.
+ * out: means2d [n,2], conic_opacity [n,4] = (a, b, c, o') with conic
+ *      [[a, b], [b, c]], rgb [n,3], depth [n], rect [n,4] int32,
+ *      tiles_touched [n] uint32.
+ * n = 0 is a valid no-op. */
+gs_status gs_preprocess(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
+                        const float *means3d, const float *scales, const float *quats, const float *opacities,
+                        const float *sh, int32_t sh_degree, float *means2d, float *conic_opacity, float *rgb,
+                        float *depth, int32_t *rect, uint32_t *tiles_touched, void *stream);
+
+/* Bytes of device workspace gs_bin_sort needs for n splats, a key capacity
+ * and a tile count. */
+gs_status gs_bin_sort_workspace(int64_t n, int64_t key_capacity, int32_t num_tiles, size_t *bytes);
+
+/* Tile binning (Sec. 2.1; the tile partitioning the paper's CUDA renderers
+ * share, Sec. 4.2): every splat is duplicated once per tile of its rect with
+ * the 64-bit key (tile_id << 32) | bits(depth) (tile_id = ty * grid_w + tx,
+ * rows of the rect in order, depth's float bits, depths being positive for
+ * every splat with tiles), the value being the splat index. The key list is
+ * sorted stably, so equal keys keep splat-index order and the result is
+ * unique; ranges[t] = (first, last + 1) of tile t's keys, (0, 0) if none.
+ *
+ * in : depth [n], rect [n,4], tiles_touched [n] (gs_preprocess outputs),
+ *      grid_w x grid_h tiles, key_capacity = length of keys and vals.
+ * out: keys [key_capacity] uint64 and vals [key_capacity] uint32 (first
+ *      *num_keys entries valid), ranges [grid_w * grid_h, 2] uint32,
+ *      num_keys (device int64) = K, the total number of copies,
+ *      overflow (device int32) = 1 when K > key_capacity, else 0. On overflow
+ *      no key is written and every range is (0, 0); the caller reads
+ *      *num_keys and calls again with a larger capacity.
+ * workspace: device buffer of at least gs_bin_sort_workspace() bytes,
+ *      contents undefined before and after. */
+gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles_touched,
+                      int32_t grid_w, int32_t grid_h, int64_t key_capacity, void *workspace,
+                      size_t workspace_bytes, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
+                      int64_t *num_keys, int32_t *overflow, void *stream);
+
+/* Front-to-back blending per pixel (Sec. 2, Eq. 1 and the alpha compositing
+ * it feeds; the kernel of Sec. 3 Eq. 2 / Eq. 6 or exp). For each pixel, over
+ * its tile's sorted list: Q = d^T conic d with d = pixel centre - mean2d;
+ * alpha = min(alpha_max, o' k(Q)); skipped if alpha < eps; T' = T (1 - alpha);
+ * the pixel stops, without blending, at the first splat with T' < t_min;
+ * otherwise C += rgb alpha T and T = T'. image = C + T bg.
+ *
+ * in : means2d, conic_opacity, rgb (gs_preprocess), vals and ranges
+ *      (gs_bin_sort), n = number of splats the values index.
+ * out: image [3,H,W] planar, final_T [H,W], n_contrib [H,W] = splats
+ *      blended, last_contrib [H,W] = 1 + list position (within the tile)
+ *      of the last blended splat, 0 if none (the backward pass starts there),
+ *      n_eval [H,W] (may be NULL) = list entries evaluated, including the one
+ *      that stopped the pixel. */
+gs_status gs_rasterize_fwd(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
+                           const float *means2d, const float *conic_opacity, const float *rgb,
+                           const uint32_t *vals, const uint32_t *ranges, float *image, float *final_T,
+                           uint32_t *n_contrib, uint32_t *last_contrib, uint32_t *n_eval, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* backward path (the derivative of the ReLU-polynomial kernel the paper   */
+/* adds to optimise scenes with it, Sec. 4.3)                              */
+/* ---------------------------------------------------------------------- */
+
+/* Adjoint of gs_rasterize_fwd. Per pixel, back to front from final_T and
+ * last_contrib, recovering T before each splat by division by (1 - alpha)
+ * (no per-pair state is stored). Included pairs have alpha >= eps > 0, so a
+ * polynomial kernel is on its smooth branch there and the ReLU kink never
+ * enters; a clamped alpha (alpha_max) has zero derivative.
+ * in : the forward's inputs and outputs, dL_dimage [3,H,W].
+ * out: dL_dmeans2d [n,2], dL_dconic_opacity [n,4] (gradient w.r.t. a, b, c
+ *      and o' of conic_opacity; b is the off-diagonal entry, counted once),
+ *      dL_drgb [n,3]. The outputs are zeroed, then accumulated. */
+gs_status gs_rasterize_bwd(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
+                           const float *means2d, const float *conic_opacity, const float *rgb,
+                           const uint32_t *vals, const uint32_t *ranges, const float *final_T,
+                           const uint32_t *last_contrib, const float *dL_dimage, float *dL_dmeans2d,
+                           float *dL_dconic_opacity, float *dL_drgb, void *stream);
+
+/* Adjoint of gs_preprocess: chains the 2D gradients through the anti-aliasing
+ * factor, the conic inverse, EWA, the rotation and scale and the spherical
+ * harmonics to the scene parameters. Splats with tiles_touched = 0 get zero
+ * gradients. The rectangle is piecewise constant and carries none.
+ * in : gs_preprocess's inputs, its tiles_touched output, and the outputs of
+ *      gs_rasterize_bwd.
+ * out: dL_dmeans3d [n,3], dL_dscales [n,3], dL_dquats [n,4] (w.r.t. the
+ *      unnormalised input), dL_dopacities [n], dL_dsh [n,(d+1)^2,3];
+ *      every entry is written. */
+gs_status gs_preprocess_bwd(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
+                            const float *means3d, const float *scales, const float *quats,
+                            const float *opacities, const float *sh, int32_t sh_degree,
+                            const uint32_t *tiles_touched, const float *dL_dmeans2d,
+                            const float *dL_dconic_opacity, const float *dL_drgb, float *dL_dmeans3d,
+                            float *dL_dscales, float *dL_dquats, float *dL_dopacities, float *dL_dsh,
+                            void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

@@ -1,0 +1,351 @@
+// extern "C" entry points of libgs: host-side argument checks, kernel
+// resolution (coefficients, first root, radius multiplier) and launches.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "gs_coeffs.h"
+#include "gs_internal.h"
+
+namespace gs {
+
+static thread_local char g_err[512] = "";
+
+gs_status fail(gs_status s, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+gs_status check_hip(hipError_t e, const char *what) {
+  if (e == hipSuccess) return GS_OK;
+  return fail(GS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+namespace {
+
+double peval(const double *c, int order, double x) {
+  double s = c[order];
+  for (int i = order - 1; i >= 0; --i) s = s * x + c[i];
+  return s;
+}
+
+double pderiv(const double *c, int order, double x) {
+  double s = order * c[order];
+  for (int i = order - 1; i >= 1; --i) s = s * x + i * c[i];
+  return s;
+}
+
+// first positive root of p by the closed forms of App. B, Newton-polished
+double closed_root(const double *c, int order) {
+  double x;
+  if (order == 1) {
+    x = -c[0] / c[1];
+  } else if (order == 2) {
+    const double disc = c[1] * c[1] - 4.0 * c[0] * c[2];
+    if (disc < 0.0) return -1.0;
+    x = 2.0 * c[0] / (-c[1] + std::sqrt(disc));
+  } else {
+    const double d0 = c[2] * c[2] - 3.0 * c[3] * c[1];
+    const double d1 = 2.0 * c[2] * c[2] * c[2] - 9.0 * c[3] * c[2] * c[1] + 27.0 * c[3] * c[3] * c[0];
+    const double s = d1 * d1 - 4.0 * d0 * d0 * d0;
+    const double sq = std::sqrt(s > 0.0 ? s : 0.0);
+    const double C = std::cbrt(d1 >= 0.0 ? 0.5 * (d1 + sq) : 0.5 * (d1 - sq));
+    x = -(c[2] + C + d0 / C) / (3.0 * c[3]);
+  }
+  for (int it = 0; it < 3; ++it) {
+    const double fp = pderiv(c, order, x);
+    if (fp != 0.0) x -= peval(c, order, x) / fp;
+  }
+  return x;
+}
+
+bool finite_pos(float v) { return std::isfinite(v) && v > 0.0f; }
+
+gs_status check_params(const gs_params *p) {
+  if (!p) return fail(GS_EINVAL, "params is NULL");
+  if (p->tile != 16) return fail(GS_EUNSUPPORTED, "tile = %d: only 16x16 tiles are supported", p->tile);
+  if (!finite_pos(p->eps) || !(p->eps < 1.0f)) return fail(GS_EINVAL, "eps must be in (0, 1)");
+  if (!finite_pos(p->alpha_max) || p->alpha_max > 1.0f) return fail(GS_EINVAL, "alpha_max must be in (0, 1]");
+  if (!(p->t_min >= 0.0f && p->t_min < 1.0f)) return fail(GS_EINVAL, "t_min must be in [0, 1)");
+  if (!(p->aa_v >= 0.0f) || !std::isfinite(p->aa_v)) return fail(GS_EINVAL, "aa_v must be finite and >= 0");
+  if (!finite_pos(p->near_z)) return fail(GS_EINVAL, "near_z must be finite and > 0");
+  if (!(p->radius_pad >= 1.0f) || !std::isfinite(p->radius_pad)) return fail(GS_EINVAL, "radius_pad must be >= 1");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(p->bg[i])) return fail(GS_EINVAL, "bg must be finite");
+  return GS_OK;
+}
+
+gs_status check_camera(const gs_camera *c) {
+  if (!c) return fail(GS_EINVAL, "camera is NULL");
+  if (c->width < 1 || c->height < 1 || c->width > 32768 || c->height > 32768)
+    return fail(GS_EINVAL, "image size %dx%d outside 1..32768", c->width, c->height);
+  if (!finite_pos(c->fx) || !finite_pos(c->fy)) return fail(GS_EINVAL, "focal lengths must be finite and > 0");
+  if (!std::isfinite(c->cx) || !std::isfinite(c->cy)) return fail(GS_EINVAL, "principal point must be finite");
+  for (int i = 0; i < 12; ++i)
+    if (!std::isfinite(c->viewmat[i])) return fail(GS_EINVAL, "viewmat must be finite");
+  return GS_OK;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+gs_status resolve_kernel(const gs_kernel *k, Resolved *r) {
+  if (!k) return fail(GS_EINVAL, "kernel is NULL");
+  if (k->kind != GS_KERNEL_EXP && k->kind != GS_KERNEL_POLY) return fail(GS_EINVAL, "kernel kind %d", k->kind);
+  if (k->radius_mode < GS_RADIUS_SIGMA3 || k->radius_mode > GS_RADIUS_EXP_OPACITY)
+    return fail(GS_EINVAL, "radius_mode %d", k->radius_mode);
+  if (k->reserved != 0) return fail(GS_EINVAL, "reserved field must be 0");
+  std::memset(r, 0, sizeof(*r));
+  r->kind = k->kind;
+  r->radius_mode = k->radius_mode;
+  r->order = k->order;
+  const bool needs_poly = k->kind == GS_KERNEL_POLY || k->radius_mode == GS_RADIUS_POLY_UNIVERSAL ||
+                          k->radius_mode == GS_RADIUS_POLY_OPACITY;
+  if (!needs_poly) {
+    r->order = 1;
+    return GS_OK;
+  }
+  if (k->order < 1 || k->order > 3) return fail(GS_EINVAL, "polynomial order %d outside 1..3", k->order);
+  for (int i = 0; i <= k->order; ++i) {
+    if (!std::isfinite(k->coeffs[i])) return fail(GS_EINVAL, "coefficient c_%d is not finite", i);
+    r->c[i] = k->coeffs[i];
+  }
+  const double *c = r->c;
+  const int N = k->order;
+  if (!(c[0] > 0.0)) return fail(GS_EUNSUPPORTED, "c_0 must be > 0");
+  if (c[N] == 0.0) return fail(GS_EUNSUPPORTED, "leading coefficient c_%d is 0; use a lower order", N);
+  if (N == 3 && !(c[2] * c[2] < 3.0 * c[1] * c[3]))
+    return fail(GS_EUNSUPPORTED, "cubic kernel must be strictly monotone (one real root)");
+  const double x0 = closed_root(c, N);
+  if (!(x0 > 0.0) || !std::isfinite(x0)) return fail(GS_EUNSUPPORTED, "polynomial has no positive root");
+  // p must decrease on [0, x0] so that every opacity bound is the unique root there:
+  // p' has degree <= 2, so check both ends and an interior vertex
+  bool dec = pderiv(c, N, 0.0) < 0.0 && pderiv(c, N, x0) < 0.0;
+  if (N == 3) {
+    const double xv = -c[2] / (3.0 * c[3]);
+    if (xv > 0.0 && xv < x0) dec = dec && pderiv(c, N, xv) < 0.0;
+  }
+  if (!dec) return fail(GS_EUNSUPPORTED, "polynomial must decrease on [0, x0]");
+  r->x0 = x0;
+  return GS_OK;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" {
+
+const char *gs_version(void) { return "libgs 0.1 (gfx950)"; }
+
+const char *gs_last_error(void) { return g_err; }
+
+gs_status gs_kernel_default(int32_t kind, int32_t order, int32_t radius_mode, gs_kernel *out) {
+  if (!out) return fail(GS_EINVAL, "out is NULL");
+  if (order < 1 || order > 3) return fail(GS_EINVAL, "order %d outside 1..3", order);
+  std::memset(out, 0, sizeof(*out));
+  out->kind = kind;
+  out->order = order;
+  out->radius_mode = radius_mode;
+  if (order == 1) {
+    // Sec. 3.1: intercept 0.773, root at 4.386 (the printed labels read as swapped)
+    out->coeffs[0] = 0.773;
+    out->coeffs[1] = -0.773 / 4.386;
+  } else {
+    const double *t = order == 2 ? GS_FIT_ORDER2 : GS_FIT_ORDER3;
+    for (int i = 0; i < 4; ++i) out->coeffs[i] = t[i];
+  }
+  Resolved r;
+  return resolve_kernel(out, &r);
+}
+
+gs_status gs_kernel_root(const gs_kernel *kernel, double *x0_out) {
+  if (!x0_out) return fail(GS_EINVAL, "x0_out is NULL");
+  Resolved r;
+  gs_status st = resolve_kernel(kernel, &r);
+  if (st != GS_OK) return st;
+  *x0_out = r.x0;
+  return GS_OK;
+}
+
+gs_status gs_params_default(gs_params *out) {
+  if (!out) return fail(GS_EINVAL, "out is NULL");
+  out->eps = 1.0f / 255.0f;
+  out->alpha_max = 0.99f;
+  out->t_min = 1e-4f;
+  out->aa_v = 0.3f;
+  out->near_z = 0.2f;
+  out->radius_pad = 1.0f + 1.0f / 1048576.0f;
+  out->bg[0] = out->bg[1] = out->bg[2] = 0.0f;
+  out->tile = 16;
+  return GS_OK;
+}
+
+gs_status gs_preprocess(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
+                        const float *means3d, const float *scales, const float *quats, const float *opacities,
+                        const float *sh, int32_t sh_degree, float *means2d, float *conic_opacity, float *rgb,
+                        float *depth, int32_t *rect, uint32_t *tiles_touched, void *stream) {
+  gs_status st;
+  if ((st = check_camera(cam)) != GS_OK || (st = check_params(params)) != GS_OK) return st;
+  Resolved r;
+  if ((st = resolve_kernel(kernel, &r)) != GS_OK) return st;
+  if (n < 0 || n >= (1ll << 31)) return fail(GS_EINVAL, "n = %lld outside [0, 2^31)", (long long)n);
+  if (sh_degree < 0 || sh_degree > 3) return fail(GS_EINVAL, "sh_degree %d outside 0..3", sh_degree);
+  if (n == 0) return GS_OK;
+  if (!means3d || !scales || !quats || !opacities || !sh || !means2d || !conic_opacity || !rgb || !depth || !rect ||
+      !tiles_touched)
+    return fail(GS_EINVAL, "NULL array argument");
+  if (!aligned(means2d, 8) || !aligned(conic_opacity, 16) || !aligned(rect, 16))
+    return fail(GS_EINVAL, "means2d needs 8-byte, conic_opacity and rect 16-byte alignment");
+  PreParams p;
+  std::memset(&p, 0, sizeof(p));
+  make_cam(cam, params->tile, &p.cam);
+  p.radius_mode = r.radius_mode;
+  p.order = r.order;
+  p.sh_degree = sh_degree;
+  p.tile = params->tile;
+  for (int i = 0; i < 4; ++i) p.c[i] = r.c[i];
+  p.k_universal = std::sqrt(r.x0);
+  p.eps = params->eps;
+  p.aa_v = params->aa_v;
+  p.near_z = params->near_z;
+  p.pad = params->radius_pad;
+  PreOut o{means2d, conic_opacity, rgb, depth, rect, tiles_touched};
+  return check_hip(launch_preprocess(p, n, means3d, scales, quats, opacities, sh, o, (hipStream_t)stream),
+                   "gs_preprocess launch");
+}
+
+gs_status gs_bin_sort_workspace(int64_t n, int64_t key_capacity, int32_t num_tiles, size_t *bytes) {
+  if (!bytes) return fail(GS_EINVAL, "bytes is NULL");
+  if (n < 0 || n >= (1ll << 31)) return fail(GS_EINVAL, "n outside [0, 2^31)");
+  if (key_capacity < 0 || key_capacity >= (1ll << 32)) return fail(GS_EINVAL, "key_capacity outside [0, 2^32)");
+  if (num_tiles < 1) return fail(GS_EINVAL, "num_tiles must be >= 1");
+  *bytes = binsort_workspace_bytes(n, key_capacity, num_tiles);
+  return GS_OK;
+}
+
+gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles_touched,
+                      int32_t grid_w, int32_t grid_h, int64_t key_capacity, void *workspace, size_t workspace_bytes,
+                      uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *num_keys, int32_t *overflow,
+                      void *stream) {
+  if (grid_w < 1 || grid_h < 1 || (int64_t)grid_w * grid_h > (1ll << 30))
+    return fail(GS_EINVAL, "tile grid %dx%d invalid", grid_w, grid_h);
+  size_t need = 0;
+  gs_status st = gs_bin_sort_workspace(n, key_capacity, grid_w * grid_h, &need);
+  if (st != GS_OK) return st;
+  if (!workspace || workspace_bytes < need)
+    return fail(GS_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
+  if (!ranges || !num_keys || !overflow) return fail(GS_EINVAL, "NULL output argument");
+  if (key_capacity > 0 && (!keys || !vals)) return fail(GS_EINVAL, "NULL keys or vals");
+  if (n > 0 && (!depth || !rect || !tiles_touched)) return fail(GS_EINVAL, "NULL input argument");
+  if (!aligned(workspace, 256) || (rect && !aligned(rect, 16)) || (keys && !aligned(keys, 8)))
+    return fail(GS_EINVAL, "workspace needs 256-byte, rect 16-byte, keys 8-byte alignment");
+  return check_hip(launch_binsort(n, depth, rect, tiles_touched, grid_w, grid_h, key_capacity, workspace,
+                                  workspace_bytes, keys, vals, ranges, num_keys, overflow, (hipStream_t)stream),
+                   "gs_bin_sort launch");
+}
+
+static gs_status make_blend(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params,
+                            BlendParams *b) {
+  gs_status st;
+  if ((st = check_camera(cam)) != GS_OK || (st = check_params(params)) != GS_OK) return st;
+  Resolved r;
+  if ((st = resolve_kernel(kernel, &r)) != GS_OK) return st;
+  std::memset(b, 0, sizeof(*b));
+  b->W = cam->width;
+  b->H = cam->height;
+  b->gx = (cam->width + params->tile - 1) / params->tile;
+  b->gy = (cam->height + params->tile - 1) / params->tile;
+  b->blend = blend_kind(r);
+  for (int i = 0; i < 4; ++i) b->c[i] = (float)r.c[i];
+  b->x0 = (float)r.x0;
+  b->eps = params->eps;
+  b->alpha_max = params->alpha_max;
+  b->t_min = params->t_min;
+  for (int i = 0; i < 3; ++i) b->bg[i] = params->bg[i];
+  return GS_OK;
+}
+
+gs_status gs_rasterize_fwd(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
+                           const float *means2d, const float *conic_opacity, const float *rgb,
+                           const uint32_t *vals, const uint32_t *ranges, float *image, float *final_T,
+                           uint32_t *n_contrib, uint32_t *last_contrib, uint32_t *n_eval, void *stream) {
+  BlendParams b;
+  gs_status st = make_blend(cam, kernel, params, &b);
+  if (st != GS_OK) return st;
+  if (n < 0 || n >= (1ll << 31)) return fail(GS_EINVAL, "n outside [0, 2^31)");
+  b.n = (uint32_t)n;
+  if (!ranges || !image || !final_T || !n_contrib || !last_contrib) return fail(GS_EINVAL, "NULL argument");
+  if (n > 0 && (!means2d || !conic_opacity || !rgb || !vals)) return fail(GS_EINVAL, "NULL splat argument");
+  if ((means2d && !aligned(means2d, 8)) || (conic_opacity && !aligned(conic_opacity, 16)))
+    return fail(GS_EINVAL, "means2d needs 8-byte, conic_opacity 16-byte alignment");
+  BlendOut o{image, final_T, n_contrib, last_contrib, n_eval};
+  return check_hip(launch_blend_fwd(b, means2d, conic_opacity, rgb, vals, ranges, o, (hipStream_t)stream),
+                   "gs_rasterize_fwd launch");
+}
+
+gs_status gs_rasterize_bwd(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
+                           const float *means2d, const float *conic_opacity, const float *rgb,
+                           const uint32_t *vals, const uint32_t *ranges, const float *final_T,
+                           const uint32_t *last_contrib, const float *dL_dimage, float *dL_dmeans2d,
+                           float *dL_dconic_opacity, float *dL_drgb, void *stream) {
+  BlendParams b;
+  gs_status st = make_blend(cam, kernel, params, &b);
+  if (st != GS_OK) return st;
+  if (n < 0 || n >= (1ll << 31)) return fail(GS_EINVAL, "n outside [0, 2^31)");
+  b.n = (uint32_t)n;
+  if (!ranges || !final_T || !last_contrib || !dL_dimage) return fail(GS_EINVAL, "NULL argument");
+  if (n > 0 && (!means2d || !conic_opacity || !rgb || !vals || !dL_dmeans2d || !dL_dconic_opacity || !dL_drgb))
+    return fail(GS_EINVAL, "NULL splat argument");
+  if ((means2d && !aligned(means2d, 8)) || (conic_opacity && !aligned(conic_opacity, 16)) ||
+      (dL_dmeans2d && !aligned(dL_dmeans2d, 8)) || (dL_dconic_opacity && !aligned(dL_dconic_opacity, 16)))
+    return fail(GS_EINVAL, "2D records need 8 (means) and 16 (conic_opacity) byte alignment");
+  return check_hip(launch_blend_bwd(b, n, means2d, conic_opacity, rgb, vals, ranges, final_T, last_contrib,
+                                    dL_dimage, dL_dmeans2d, dL_dconic_opacity, dL_drgb, (hipStream_t)stream),
+                   "gs_rasterize_bwd launch");
+}
+
+gs_status gs_preprocess_bwd(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
+                            const float *means3d, const float *scales, const float *quats,
+                            const float *opacities, const float *sh, int32_t sh_degree,
+                            const uint32_t *tiles_touched, const float *dL_dmeans2d,
+                            const float *dL_dconic_opacity, const float *dL_drgb, float *dL_dmeans3d,
+                            float *dL_dscales, float *dL_dquats, float *dL_dopacities, float *dL_dsh,
+                            void *stream) {
+  gs_status st;
+  if ((st = check_camera(cam)) != GS_OK || (st = check_params(params)) != GS_OK) return st;
+  Resolved r;
+  if ((st = resolve_kernel(kernel, &r)) != GS_OK) return st;
+  if (n < 0 || n >= (1ll << 31)) return fail(GS_EINVAL, "n outside [0, 2^31)");
+  if (sh_degree < 0 || sh_degree > 3) return fail(GS_EINVAL, "sh_degree %d outside 0..3", sh_degree);
+  if (n == 0) return GS_OK;
+  if (!means3d || !scales || !quats || !opacities || !sh || !tiles_touched || !dL_dmeans2d || !dL_dconic_opacity ||
+      !dL_drgb || !dL_dmeans3d || !dL_dscales || !dL_dquats || !dL_dopacities || !dL_dsh)
+    return fail(GS_EINVAL, "NULL array argument");
+  if (!aligned(dL_dmeans2d, 8) || !aligned(dL_dconic_opacity, 16))
+    return fail(GS_EINVAL, "2D gradients need 8 (means) and 16 (conic_opacity) byte alignment");
+  PreParams p;
+  std::memset(&p, 0, sizeof(p));
+  make_cam(cam, params->tile, &p.cam);
+  p.radius_mode = r.radius_mode;
+  p.order = r.order;
+  p.sh_degree = sh_degree;
+  p.tile = params->tile;
+  for (int i = 0; i < 4; ++i) p.c[i] = r.c[i];
+  p.k_universal = std::sqrt(r.x0);
+  p.eps = params->eps;
+  p.aa_v = params->aa_v;
+  p.near_z = params->near_z;
+  p.pad = params->radius_pad;
+  return check_hip(launch_preprocess_bwd(p, n, means3d, scales, quats, opacities, sh, tiles_touched, dL_dmeans2d,
+                                         dL_dconic_opacity, dL_drgb, dL_dmeans3d, dL_dscales, dL_dquats,
+                                         dL_dopacities, dL_dsh, (hipStream_t)stream),
+                   "gs_preprocess_bwd launch");
+}
+
+}  // extern "C"

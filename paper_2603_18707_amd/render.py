@@ -1,0 +1,127 @@
+"""Frame-level driver over the C ABI: buffers, key capacity and the three stages.
+
+PyTorch supplies device memory and the stream; every stage is one of libgs's
+HIP entry points (gs_preprocess -> gs_bin_sort -> gs_rasterize_fwd).
+"""
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+TILE = 16
+
+
+@dataclass
+class DeviceScene:
+    means3d: torch.Tensor
+    scales: torch.Tensor
+    quats: torch.Tensor
+    opacities: torch.Tensor
+    sh: torch.Tensor
+    sh_degree: int
+
+    @property
+    def n(self) -> int:
+        return int(self.means3d.shape[0])
+
+
+def to_device(scene, device="cuda") -> DeviceScene:
+    f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+    return DeviceScene(f(scene.means3d), f(scene.scales), f(scene.quats), f(scene.opacities), f(scene.sh),
+                       int(scene.sh_degree))
+
+
+def kernel_spec(kind: str, order: int = 1, radius: str = "opacity", coeffs=None) -> L.GsKernel:
+    """kind 'exp' or 'poly'; radius 'sigma3', 'universal', 'opacity' (polynomial
+    root at eps / o') or 'exp_opacity' (exp's own opacity bound)."""
+    k = {"exp": L.KERNEL_EXP, "poly": L.KERNEL_POLY}[kind]
+    r = {"sigma3": L.RADIUS_SIGMA3, "universal": L.RADIUS_POLY_UNIVERSAL, "opacity": L.RADIUS_POLY_OPACITY,
+         "exp_opacity": L.RADIUS_EXP_OPACITY}[radius]
+    return L.make_kernel(k, order, r, coeffs)
+
+
+def grid_of(cam):
+    return (int(cam.width) + TILE - 1) // TILE, (int(cam.height) + TILE - 1) // TILE
+
+
+class Rasterizer:
+    """Renders frames of one kernel configuration; keeps its buffers and the
+    key capacity between frames (the capacity grows when a frame overflows)."""
+
+    def __init__(self, kernel: L.GsKernel, params: L.GsParams = None, device="cuda", capacity: int = 0):
+        self.kernel = kernel
+        self.params = params if params is not None else L.gs_params_default()
+        self.device = torch.device(device)
+        self.capacity = int(capacity)
+        self._bufs = {}
+
+    # -- buffers ---------------------------------------------------------
+    def _buf(self, name, shape, dtype):
+        t = self._bufs.get(name)
+        numel = int(np.prod(shape))
+        if t is None or t.numel() < numel or t.dtype != dtype:
+            t = torch.empty(max(numel, 1), dtype=dtype, device=self.device)
+            self._bufs[name] = t
+        return t[:numel].view(*shape) if len(shape) else t[:1]
+
+    # -- stages ----------------------------------------------------------
+    def preprocess(self, scene: DeviceScene, cam, stream=None) -> dict:
+        n = scene.n
+        out = dict(means2d=self._buf("means2d", (n, 2), torch.float32),
+                   conic_opacity=self._buf("conic_opacity", (n, 4), torch.float32),
+                   rgb=self._buf("rgb", (n, 3), torch.float32),
+                   depth=self._buf("depth", (n,), torch.float32),
+                   rect=self._buf("rect", (n, 4), torch.int32),
+                   tiles=self._buf("tiles", (n,), torch.int32))
+        L.gs_preprocess(L.make_camera(cam), self.kernel, self.params, n, scene.means3d, scene.scales, scene.quats,
+                        scene.opacities, scene.sh, scene.sh_degree, out["means2d"], out["conic_opacity"],
+                        out["rgb"], out["depth"], out["rect"], out["tiles"], stream)
+        out["n"] = n
+        return out
+
+    def bin_sort(self, proj: dict, cam, capacity: int = None, stream=None) -> dict:
+        n = proj["n"]
+        gw, gh = grid_of(cam)
+        cap = self.capacity if capacity is None else int(capacity)
+        ws_bytes = L.gs_bin_sort_workspace(n, cap, gw * gh)
+        ws = self._buf("ws", ((ws_bytes + 255) // 256 * 256,), torch.uint8)
+        out = dict(keys=self._buf("keys", (max(cap, 1),), torch.int64),
+                   vals=self._buf("vals", (max(cap, 1),), torch.int32),
+                   ranges=self._buf("ranges", (gw * gh, 2), torch.int32),
+                   num_keys=self._buf("num_keys", (1,), torch.int64),
+                   overflow=self._buf("overflow", (1,), torch.int32))
+        L.gs_bin_sort(n, proj["depth"], proj["rect"], proj["tiles"], gw, gh, cap, ws, ws.numel(), out["keys"],
+                      out["vals"], out["ranges"], out["num_keys"], out["overflow"], stream)
+        out["capacity"] = cap
+        return out
+
+    def bin_sort_fit(self, proj: dict, cam, stream=None) -> dict:
+        """bin_sort, growing the capacity and retrying when the keys overflow
+        (reads two device scalars back: use outside timed or captured regions)."""
+        b = self.bin_sort(proj, cam, stream=stream)
+        if int(b["overflow"].item()):
+            K = int(b["num_keys"].item())
+            self.capacity = int(K * 1.125) + 1024
+            b = self.bin_sort(proj, cam, stream=stream)
+            assert not int(b["overflow"].item())
+        return b
+
+    def rasterize(self, proj: dict, binned: dict, cam, want_eval: bool = False, stream=None) -> dict:
+        W, H = int(cam.width), int(cam.height)
+        out = dict(image=self._buf("image", (3, H, W), torch.float32),
+                   final_T=self._buf("final_T", (H, W), torch.float32),
+                   n_contrib=self._buf("n_contrib", (H, W), torch.int32),
+                   last_contrib=self._buf("last_contrib", (H, W), torch.int32),
+                   n_eval=self._buf("n_eval", (H, W), torch.int32) if want_eval else None)
+        L.gs_rasterize_fwd(L.make_camera(cam), self.kernel, self.params, proj["n"], proj["means2d"],
+                           proj["conic_opacity"], proj["rgb"], binned["vals"], binned["ranges"], out["image"],
+                           out["final_T"], out["n_contrib"], out["last_contrib"], out["n_eval"], stream)
+        return out
+
+    def render(self, scene: DeviceScene, cam, want_eval: bool = False, stream=None) -> dict:
+        proj = self.preprocess(scene, cam, stream)
+        binned = self.bin_sort_fit(proj, cam, stream)
+        img = self.rasterize(proj, binned, cam, want_eval, stream)
+        return dict(proj=proj, binned=binned, **img)

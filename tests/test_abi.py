@@ -1,0 +1,117 @@
+"""The C-ABI library loads, exports every symbol include/gs.h declares, and
+rejects bad arguments on the host before touching the GPU. No GPU needed."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2603_18707_amd import _lib as L
+from tests.helpers import GOLDEN, ROOT
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = L.lib()
+    names = _declared()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.EXPORTS)
+    assert "gfx950" in L.gs_version()
+
+
+def test_default_coefficients():
+    k1 = L.gs_kernel_default(L.KERNEL_POLY, 1, L.RADIUS_POLY_OPACITY)
+    assert k1.coeffs[0] == 0.773 and abs(L.gs_kernel_root(k1) - 4.386) < 1e-12
+    for order in (2, 3):
+        k = L.gs_kernel_default(L.KERNEL_POLY, order, L.RADIUS_POLY_OPACITY)
+        g = GOLDEN[f"fit{order}"]
+        # the library's own fit agrees with the reference's independent fit
+        assert np.allclose(list(k.coeffs)[:order + 1], g["c"][:order + 1], atol=5e-5)
+        assert abs(L.gs_kernel_root(k) - g["x0"]) < 1e-3
+
+
+def test_root_of_explicit_coefficients():
+    for name in ("paper1", "fit1", "fit2", "fit3"):
+        g = GOLDEN[name]
+        k = L.make_kernel(L.KERNEL_POLY, g["order"], L.RADIUS_POLY_UNIVERSAL, g["c"])
+        assert L.gs_kernel_root(k) == pytest.approx(g["x0"], rel=1e-13)
+
+
+def _expect(status, fn, *a):
+    with pytest.raises(L.GsError) as e:
+        fn(*a)
+    assert e.value.status == status
+    return str(e.value)
+
+
+def test_kernel_validation():
+    k = L.make_kernel(L.KERNEL_POLY, 4, L.RADIUS_SIGMA3, (0.7, -0.1))
+    _expect(L.GS_EINVAL, L.gs_kernel_root, k)
+    k = L.make_kernel(7, 1, L.RADIUS_SIGMA3, (0.7, -0.1))
+    _expect(L.GS_EINVAL, L.gs_kernel_root, k)
+    k = L.make_kernel(L.KERNEL_POLY, 1, 9, (0.7, -0.1))
+    _expect(L.GS_EINVAL, L.gs_kernel_root, k)
+    k = L.make_kernel(L.KERNEL_POLY, 1, 0, (0.7, 0.1))      # increasing: no positive root
+    _expect(L.GS_EUNSUPPORTED, L.gs_kernel_root, k)
+    k = L.make_kernel(L.KERNEL_POLY, 3, 0, (1.0, -3.0, 3.0, -1.0))   # (1-x)^3: not strictly monotone
+    _expect(L.GS_EUNSUPPORTED, L.gs_kernel_root, k)
+    k = L.make_kernel(L.KERNEL_POLY, 1, 0, (0.7, -0.1))
+    k.reserved = 1
+    _expect(L.GS_EINVAL, L.gs_kernel_root, k)
+
+
+class _Cam:
+    viewmat = np.eye(4, dtype=np.float32)
+    fx = fy = 100.0
+    cx = cy = 32.0
+    width = height = 64
+
+
+def test_device_calls_reject_bad_arguments_on_host():
+    cam = L.make_camera(_Cam())
+    k = L.gs_kernel_default(L.KERNEL_POLY, 1, L.RADIUS_POLY_OPACITY)
+    p = L.gs_params_default()
+    null8 = [None] * 5
+    out6 = [None] * 6
+    # NULL arrays with n > 0
+    _expect(L.GS_EINVAL, L.gs_preprocess, cam, k, p, 10, *null8, 0, *out6)
+    # bad n / sh degree / tile / params / camera
+    _expect(L.GS_EINVAL, L.gs_preprocess, cam, k, p, -1, *null8, 0, *out6)
+    _expect(L.GS_EINVAL, L.gs_preprocess, cam, k, p, 0, *null8, 4, *out6)
+    p2 = L.gs_params_default()
+    p2.tile = 8
+    _expect(L.GS_EUNSUPPORTED, L.gs_preprocess, cam, k, p2, 0, *null8, 0, *out6)
+    p2 = L.gs_params_default()
+    p2.near_z = 0.0
+    _expect(L.GS_EINVAL, L.gs_preprocess, cam, k, p2, 0, *null8, 0, *out6)
+    c2 = L.make_camera(_Cam())
+    c2.width = 0
+    _expect(L.GS_EINVAL, L.gs_preprocess, c2, k, p, 0, *null8, 0, *out6)
+    # misaligned outputs
+    _expect(L.GS_EINVAL, L.gs_preprocess, cam, k, p, 1, 16, 16, 16, 16, 16, 0, 16, 20, 16, 16, 16, 16)
+    # n = 0 is a no-op that enqueues nothing
+    L.gs_preprocess(cam, k, p, 0, *null8, 0, *out6)
+    # bin sort: workspace too small, capacity too large, grid invalid
+    _expect(L.GS_EINVAL, L.gs_bin_sort, 10, 256, 256, 256, 4, 4, 100, 256, 10, 256, 256, 256, 256, 256)
+    _expect(L.GS_EINVAL, L.gs_bin_sort_workspace, 10, 1 << 33, 16)
+    _expect(L.GS_EINVAL, L.gs_bin_sort, 10, 256, 256, 256, 0, 4, 100, 256, 1 << 30, 256, 256, 256, 256, 256)
+    # rasterize: NULL outputs
+    _expect(L.GS_EINVAL, L.gs_rasterize_fwd, cam, k, p, 0, None, None, None, None, None, None, None, None, None)
+    msg = _expect(L.GS_EINVAL, L.gs_rasterize_bwd, cam, k, p, 5, None, None, None, None, 256, 256, 256, 256,
+                  None, None, None)
+    assert "NULL" in msg
+
+
+def test_workspace_grows_with_sizes():
+    a = L.gs_bin_sort_workspace(1000, 10000, 64)
+    b = L.gs_bin_sort_workspace(1000, 20000, 64)
+    c = L.gs_bin_sort_workspace(2000, 10000, 64)
+    assert 0 < a < b and a < c

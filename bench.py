@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--only", default=None, help="time one configuration: poly1|exp")
+    ap.add_argument("--blend-threads", type=int, default=0, help="64|128|256; 0 = autotune")
     return ap.parse_args()
 
 
@@ -58,8 +59,10 @@ def kernel_source_hash():
     return h.hexdigest()[:12]
 
 
-def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup):
-    """Times `steps` frames; per-stage HIP events inside the same timed loop."""
+def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, threads=0):
+    """Times `steps` frames; per-stage HIP events inside the same timed loop.
+    threads = 0 lets the autotuner pick the blend launch shape during warm-up."""
+    from paper_2603_18707_amd import autotune
     r = render.Rasterizer(render.kernel_spec(kind, order, radius))
     stream = torch.cuda.current_stream()
     # warm-up frames also size the key capacity (host readback happens here only)
@@ -68,7 +71,13 @@ def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup):
     torch.cuda.synchronize()
     K = int(out["binned"]["num_keys"].item())
     r.capacity = int(K * 1.05) + 4096
-    r.bin_sort(out["proj"], cam)  # re-size buffers for the final capacity outside the timed loop
+    b0 = r.bin_sort(out["proj"], cam)  # re-size buffers for the final capacity outside the timed loop
+    torch.cuda.synchronize()
+    tuned = None
+    if threads:
+        r.params.blend_threads = threads
+    else:
+        tuned = autotune.tune_blend(r, out["proj"], b0, cam)
     torch.cuda.synchronize()
 
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
@@ -96,7 +105,8 @@ def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup):
     E = int(full["n_eval"].sum().item())
     B = int(full["n_contrib"].sum().item())
     return dict(ms=total_ms / steps, stage_ms=st.mean(axis=0).tolist(), blend_ms=float(st[:, 2].mean()),
-                K=int(b["num_keys"].item()), E=E, B=B, image=full["image"].clone(), rast=r)
+                K=int(b["num_keys"].item()), E=E, B=B, image=full["image"].clone(), rast=r,
+                threads=int(r.params.blend_threads), tuned=tuned)
 
 
 def cpu_baseline(scene_np, cam, gpu_image, target_s):
@@ -152,10 +162,11 @@ def main():
         configs = [c for c in configs if c[0] == a.only]
     res = {}
     for name, kind, order, radius in configs:
-        res[name] = time_config(torch, render, scene, cam, kind, order, radius, a.steps, a.warmup)
+        res[name] = time_config(torch, render, scene, cam, kind, order, radius, a.steps, a.warmup, a.blend_threads)
         r = res[name]
         print(f"[bench] {name}: {r['ms']:.3f} ms/frame (pre {r['stage_ms'][0]:.3f}, sort {r['stage_ms'][1]:.3f},"
-              f" blend {r['stage_ms'][2]:.3f}) K={r['K']} E={r['E']}", file=sys.stderr, flush=True)
+              f" blend {r['stage_ms'][2]:.3f}) K={r['K']} E={r['E']} threads={r['threads']} tuned={r['tuned']}",
+              file=sys.stderr, flush=True)
 
     head = res[configs[0][0]]
     ms = head["ms"]
@@ -178,7 +189,8 @@ def main():
         "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "1M splats (64 clusters, SH3), 1920x1080, poly-1 kernel, opacity-dependent radius",
-                   "splats": scene.n, "width": W, "height": H, "kernel": "poly1", "radius": "opacity"},
+                   "splats": scene.n, "width": W, "height": H, "kernel": "poly1", "radius": "opacity",
+                   "blend_threads": head["threads"]},
         "splat_pixel_evals_per_s": round(evals, 1),
         "keys": head["K"], "evals": head["E"], "blended": head["B"],
         "stage_ms": {"preprocess": round(head["stage_ms"][0], 4), "bin_sort": round(head["stage_ms"][1], 4),
@@ -189,7 +201,7 @@ def main():
     }
     if "exp" in res and hname != "exp":
         e = res["exp"]
-        out["exp_sigma3"] = {"ms_per_step": round(e["ms"], 4), "Mpix_per_s": round(W * H / (e["ms"] * 1e-3) / 1e6, 2),
+        out["exp_sigma3"] = {"ms_per_step": round(e["ms"], 4), "blend_threads": e["threads"], "Mpix_per_s": round(W * H / (e["ms"] * 1e-3) / 1e6, 2),
                              "splat_pixel_evals_per_s": round(e["E"] / (e["ms"] * 1e-3), 1), "keys": e["K"],
                              "evals": e["E"],
                              "stage_ms": {"preprocess": round(e["stage_ms"][0], 4),

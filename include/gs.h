@@ -90,6 +90,9 @@ typedef struct {
   float radius_pad; /* r is multiplied by this (>= 1; 1 + 2^-20 keeps rectangles conservative) */
   float bg[3];      /* background colour added as T * bg */
   int32_t tile;     /* tile edge in pixels; only 16 is supported */
+  int32_t blend_threads; /* launch shape of the blend: threads per 16x16 tile, 64, 128 or 256
+                            (4, 2 or 1 pixels per thread); 0 = the library's default. Results
+                            do not depend on it. */
 } gs_params;
 
 typedef struct {
@@ -120,7 +123,7 @@ gs_status gs_kernel_default(int32_t kind, int32_t order, int32_t radius_mode, gs
 gs_status gs_kernel_root(const gs_kernel *kernel, double *x0_out);
 
 /* eps 1/255, alpha_max 0.99, t_min 1e-4, aa_v 0.3, near_z 0.2,
- * radius_pad 1 + 2^-20, bg 0, tile 16. */
+ * radius_pad 1 + 2^-20, bg 0, tile 16, blend_threads 0. */
 gs_status gs_params_default(gs_params *out);
 
 /* ---------------------------------------------------------------------- */

@@ -1,18 +1,475 @@
-// Adjoint of blending and of the projection (placeholder until implemented).
+// Adjoint of blending (gs_rasterize_bwd) and of the projection (gs_preprocess_bwd).
+//
+// Blending adjoint: one wave per 16x16 tile, four pixels per lane, the same
+// lane layout, staged record and inclusion test as the forward, so every
+// (pixel, splat) decision matches the forward's. The tile's list is walked
+// back to front from the last blended position of any pixel. Per pixel the
+// transmittance before a splat is recovered as T_i = T_{i+1} / (1 - alpha_i)
+// from the stored final T, and the colour behind it follows the recurrence
+// S_{i-1} = alpha_i c_i + (1 - alpha_i) S_i, so nothing per pair is stored.
+// With g = dL/dC:
+//   dL/dc_i     = alpha_i T_i g
+//   dL/dalpha_i = T_i (c_i - S_i) . g - T_final / (1 - alpha_i) (bg . g)
+// and alpha = min(alpha_max, o' k(Q)) gives dL/do' and dL/dQ (zero when the
+// clamp is active); Q = d^T conic d gives the conic and mean gradients. An
+// included pair has alpha >= eps > 0, so a polynomial kernel is strictly
+// positive there: the ReLU kink never enters. Per splat the nine partial
+// gradients are summed over the lane's pixels, reduced across the wave, and
+// added to global memory by one lane.
+//
+// Projection adjoint: one thread per splat in double precision, the chain
+// rule through the SH colour, the opacity factor sqrt(|S'| / |S' + vI|), the
+// conic inverse, EWA (with the Jacobian's clamp), the camera transform, the
+// rotation-scale factorisation and the quaternion normalisation.
+#include <cmath>
+
+#include "blend_common.h"
 #include "gs_internal.h"
 
 namespace gs {
 
-hipError_t launch_blend_bwd(const BlendParams &, int64_t, const float *, const float *, const float *,
-                            const uint32_t *, const uint32_t *, const float *, const uint32_t *, const float *,
-                            float *, float *, float *, hipStream_t) {
-  return hipErrorNotSupported;
+namespace {
+
+__global__ void zero_f32(float *p, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) p[i] = 0.0f;
 }
 
-hipError_t launch_preprocess_bwd(const PreParams &, int64_t, const float *, const float *, const float *,
-                                 const float *, const float *, const uint32_t *, const float *, const float *,
-                                 const float *, float *, float *, float *, float *, float *, hipStream_t) {
-  return hipErrorNotSupported;
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// derivative of the polynomial at Q
+__device__ inline float dpoly(const BlendParams &p, int order, float Q) {
+  if (order == 1) return p.c[1];
+  if (order == 2) return fmaf(2.0f * p.c[2], Q, p.c[1]);
+  return fmaf(fmaf(3.0f * p.c[3], Q, 2.0f * p.c[2]), Q, p.c[1]);
+}
+
+__device__ inline float poly(const BlendParams &p, int order, float Q) {
+  if (order == 1) return fmaf(p.c[1], Q, p.c[0]);
+  if (order == 2) return fmaf(fmaf(p.c[2], Q, p.c[1]), Q, p.c[0]);
+  return fmaf(fmaf(fmaf(p.c[3], Q, p.c[2]), Q, p.c[1]), Q, p.c[0]);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__restrict__ means2d,
+                                                  const float *__restrict__ conic_opacity,
+                                                  const float *__restrict__ rgb, const uint32_t *__restrict__ vals,
+                                                  const uint32_t *__restrict__ ranges,
+                                                  const float *__restrict__ final_T,
+                                                  const uint32_t *__restrict__ last_contrib,
+                                                  const float *__restrict__ dL_dimage, float *__restrict__ dmeans2d,
+                                                  float *__restrict__ dconic, float *__restrict__ drgb) {
+  __shared__ float4 L0[WAVE], L1[WAVE], L2[WAVE];
+  __shared__ uint32_t Lid[WAVE];
+  constexpr int ORDER = KIND == BLEND_POLY2 ? 2 : (KIND == BLEND_POLY3 ? 3 : 1);
+  const int ntiles = p.gx * p.gy;
+  const int tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  const int lane = threadIdx.x;
+  const int tx = tile % p.gx, ty = tile / p.gx;
+  const int px = tx * TS + (lane & (TS - 1));
+  const int py0 = ty * TS + (lane >> 4);
+  const float fx = (float)px + 0.5f;
+  const size_t plane = (size_t)p.W * p.H;
+  float fy[PIX], T[PIX], Tf[PIX], S0[PIX], S1[PIX], S2[PIX], g0[PIX], g1[PIX], g2[PIX], bgg[PIX];
+  uint32_t lastc[PIX];
+  uint32_t maxlast = 0;
+#pragma unroll
+  for (int k = 0; k < PIX; ++k) {
+    const int py = py0 + 4 * k;
+    fy[k] = (float)py + 0.5f;
+    S0[k] = S1[k] = S2[k] = 0.0f;
+    if (px < p.W && py < p.H) {
+      const size_t pix = (size_t)py * p.W + px;
+      Tf[k] = final_T[pix];
+      lastc[k] = last_contrib[pix];
+      g0[k] = dL_dimage[pix];
+      g1[k] = dL_dimage[plane + pix];
+      g2[k] = dL_dimage[2 * plane + pix];
+    } else {
+      Tf[k] = 1.0f;
+      lastc[k] = 0u;
+      g0[k] = g1[k] = g2[k] = 0.0f;
+    }
+    T[k] = Tf[k];
+    bgg[k] = p.bg[0] * g0[k] + p.bg[1] * g1[k] + p.bg[2] * g2[k];
+    maxlast = max(maxlast, lastc[k]);
+  }
+  // the wave starts at the last blended position of any of its pixels
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, o, 64));
+
+  const uint32_t start = ranges[2 * tile];
+  // positions are 1-based within the tile: pos = index - start + 1
+  for (int64_t hi = (int64_t)maxlast; hi > 0; hi -= WAVE) {
+    const int64_t lo = hi - WAVE > 0 ? hi - WAVE : 0;
+    const int cnt = (int)(hi - lo);
+    // stage positions lo+1 .. hi (list indices start+lo .. start+hi-1); lane j holds position lo+1+j
+    if (lane < cnt) {
+      uint32_t id = vals[start + lo + lane];
+      if (id >= p.n) id = 0;  // never taken for a list built by gs_bin_sort over these n splats
+      const float2 m = reinterpret_cast<const float2 *>(means2d)[id];
+      const float4 co = reinterpret_cast<const float4 *>(conic_opacity)[id];
+      const float3 c = make_float3(rgb[3 * id], rgb[3 * id + 1], rgb[3 * id + 2]);
+      float4 a0, a1, a2;
+      fold<KIND>(m, co, c, p, a0, a1, a2);
+      L0[lane] = a0;
+      L1[lane] = a1;
+      L2[lane] = a2;
+      Lid[lane] = id;
+    }
+    __syncthreads();
+    for (int j = cnt - 1; j >= 0; --j) {
+      const uint32_t pos = (uint32_t)(lo + 1 + j);
+      const float4 r0 = L0[j];
+      const float4 r1 = L1[j];
+      const float dx = fx - r0.x;
+      const float adx = r0.z * dx;
+      const float R0 = fmaf(-adx, dx, r1.y);
+      const float P = r0.w * dx;
+      float t[PIX];
+#pragma unroll
+      for (int k = 0; k < PIX; ++k) {
+        const float dy = fy[k] - r0.y;
+        t[k] = fmaf(-dy, fmaf(r1.x, dy, P), R0);
+      }
+      bool inc[PIX];
+      bool anyinc = false;
+#pragma unroll
+      for (int k = 0; k < PIX; ++k) {
+        inc[k] = t[k] >= 0.0f && pos <= lastc[k];
+        anyinc = anyinc || inc[k];
+      }
+      if (__ballot(anyinc) == 0ull) continue;
+      const float4 r2 = L2[j];
+      const float o = r1.w;
+      float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
+#pragma unroll
+      for (int k = 0; k < PIX; ++k) {
+        if (!inc[k]) continue;
+        const float a = alpha_from<KIND>(t[k], r1, p);
+        const float oma = 1.0f - a;
+        T[k] = T[k] / oma;  // transmittance before this splat
+        const float w = a * T[k];
+        gr = fmaf(w, g0[k], gr);
+        gg = fmaf(w, g1[k], gg);
+        gbl = fmaf(w, g2[k], gbl);
+        const float dLda = T[k] * ((r2.x - S0[k]) * g0[k] + (r2.y - S1[k]) * g1[k] + (r2.z - S2[k]) * g2[k]) -
+                           Tf[k] / oma * bgg[k];
+        S0[k] = fmaf(a, r2.x - S0[k], S0[k]);
+        S1[k] = fmaf(a, r2.y - S1[k], S1[k]);
+        S2[k] = fmaf(a, r2.z - S2[k], S2[k]);
+        // alpha = o' k(Q) unless clamped
+        const float dy = fy[k] - r0.y;
+        const float Q = fmaf(dx, fmaf(r0.z, dx, r0.w * dy), r1.x * dy * dy);
+        float kq, dk;
+        if (KIND == BLEND_EXP) {
+          kq = __expf(-0.5f * Q);
+          dk = -0.5f * kq;
+        } else {
+          kq = poly(p, ORDER, Q);
+          dk = dpoly(p, ORDER, Q);
+        }
+        if (o * kq > p.alpha_max) continue;
+        go = fmaf(dLda, kq, go);
+        const float dLdQ = dLda * o * dk;
+        ga = fmaf(dLdQ, dx * dx, ga);
+        gb = fmaf(dLdQ, 2.0f * dx * dy, gb);
+        gc = fmaf(dLdQ, dy * dy, gc);
+        // Q depends on the mean through d = pixel - mean
+        gu = fmaf(dLdQ, -(2.0f * r0.z * dx + r0.w * dy), gu);
+        gv = fmaf(dLdQ, -(r0.w * dx + 2.0f * r1.x * dy), gv);
+      }
+      gu = wave_sum(gu);
+      gv = wave_sum(gv);
+      ga = wave_sum(ga);
+      gb = wave_sum(gb);
+      gc = wave_sum(gc);
+      go = wave_sum(go);
+      gr = wave_sum(gr);
+      gg = wave_sum(gg);
+      gbl = wave_sum(gbl);
+      if (lane == 0) {
+        const uint32_t id = Lid[j];
+        atomicAdd(&dmeans2d[2 * id], gu);
+        atomicAdd(&dmeans2d[2 * id + 1], gv);
+        atomicAdd(&dconic[4 * id], ga);
+        atomicAdd(&dconic[4 * id + 1], gb);
+        atomicAdd(&dconic[4 * id + 2], gc);
+        atomicAdd(&dconic[4 * id + 3], go);
+        atomicAdd(&drgb[3 * id], gr);
+        atomicAdd(&drgb[3 * id + 1], gg);
+        atomicAdd(&drgb[3 * id + 2], gbl);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// projection adjoint
+// ---------------------------------------------------------------------------
+
+// SH basis values and their gradients w.r.t. the unit direction (x, y, z)
+__device__ inline void sh_basis_grad(int deg, double x, double y, double z, double Y[16], double dY[16][3]) {
+  const double PI = 3.14159265358979323846;
+  for (int k = 0; k < 16; ++k) {
+    Y[k] = 0.0;
+    dY[k][0] = dY[k][1] = dY[k][2] = 0.0;
+  }
+  Y[0] = sqrt(1.0 / (4.0 * PI));
+  if (deg >= 1) {
+    const double k1 = sqrt(3.0 / (4.0 * PI));
+    Y[1] = -k1 * y; dY[1][1] = -k1;
+    Y[2] = k1 * z; dY[2][2] = k1;
+    Y[3] = -k1 * x; dY[3][0] = -k1;
+  }
+  if (deg >= 2) {
+    const double a = sqrt(15.0 / (4.0 * PI)), b = sqrt(5.0 / (16.0 * PI)), c = sqrt(15.0 / (16.0 * PI));
+    Y[4] = a * x * y; dY[4][0] = a * y; dY[4][1] = a * x;
+    Y[5] = -a * y * z; dY[5][1] = -a * z; dY[5][2] = -a * y;
+    Y[6] = b * (2 * z * z - x * x - y * y); dY[6][0] = -2 * b * x; dY[6][1] = -2 * b * y; dY[6][2] = 4 * b * z;
+    Y[7] = -a * x * z; dY[7][0] = -a * z; dY[7][2] = -a * x;
+    Y[8] = c * (x * x - y * y); dY[8][0] = 2 * c * x; dY[8][1] = -2 * c * y;
+  }
+  if (deg >= 3) {
+    const double a = sqrt(35.0 / (32.0 * PI)), b = sqrt(105.0 / (4.0 * PI)), c = sqrt(21.0 / (32.0 * PI));
+    const double d = sqrt(7.0 / (16.0 * PI)), e = sqrt(105.0 / (16.0 * PI));
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[9] = -a * y * (3 * xx - yy);
+    dY[9][0] = -6 * a * x * y; dY[9][1] = -a * (3 * xx - 3 * yy);
+    Y[10] = b * x * y * z;
+    dY[10][0] = b * y * z; dY[10][1] = b * x * z; dY[10][2] = b * x * y;
+    Y[11] = -c * y * (4 * zz - xx - yy);
+    dY[11][0] = 2 * c * x * y; dY[11][1] = -c * (4 * zz - xx - 3 * yy); dY[11][2] = -8 * c * y * z;
+    Y[12] = d * z * (2 * zz - 3 * xx - 3 * yy);
+    dY[12][0] = -6 * d * x * z; dY[12][1] = -6 * d * y * z; dY[12][2] = d * (6 * zz - 3 * xx - 3 * yy);
+    Y[13] = -c * x * (4 * zz - xx - yy);
+    dY[13][0] = -c * (4 * zz - 3 * xx - yy); dY[13][1] = 2 * c * x * y; dY[13][2] = -8 * c * x * z;
+    Y[14] = e * z * (xx - yy);
+    dY[14][0] = 2 * e * x * z; dY[14][1] = -2 * e * y * z; dY[14][2] = e * (xx - yy);
+    Y[15] = -a * x * (xx - 3 * yy);
+    dY[15][0] = -a * (3 * xx - 3 * yy); dY[15][1] = 6 * a * x * y;
+  }
+}
+
+__global__ __launch_bounds__(128) void preprocess_bwd_kernel(
+    PreParams p, int64_t n, const float *__restrict__ means3d, const float *__restrict__ scales,
+    const float *__restrict__ quats, const float *__restrict__ opac, const float *__restrict__ sh,
+    const uint32_t *__restrict__ tiles, const float *__restrict__ dmeans2d, const float *__restrict__ dconic,
+    const float *__restrict__ drgb, float *__restrict__ dmeans3d, float *__restrict__ dscales,
+    float *__restrict__ dquats, float *__restrict__ dopac, float *__restrict__ dsh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int nsh = (p.sh_degree + 1) * (p.sh_degree + 1);
+  double gmu[3] = {0.0, 0.0, 0.0}, gs3[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0}, gop = 0.0;
+  const bool live = tiles[i] != 0u;
+  if (!live) {
+    for (int k = 0; k < nsh * 3; ++k) dsh[(size_t)i * nsh * 3 + k] = 0.0f;
+  } else {
+    const CamD &cam = p.cam;
+    const double mx = means3d[3 * i], my = means3d[3 * i + 1], mz = means3d[3 * i + 2];
+    double t[3];
+    for (int r = 0; r < 3; ++r) t[r] = cam.R[3 * r] * mx + cam.R[3 * r + 1] * my + cam.R[3 * r + 2] * mz + cam.t[r];
+
+    // ---- colour: rgb = max(sum_k Y_k(d) sh_k + 0.5, 0), d = (mu - campos) / |mu - campos|
+    {
+      double v[3] = {mx - cam.campos[0], my - cam.campos[1], mz - cam.campos[2]};
+      const double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      const double d[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
+      double Y[16], dY[16][3];
+      sh_basis_grad(p.sh_degree, d[0], d[1], d[2], Y, dY);
+      const float *shi = sh + (size_t)i * nsh * 3;
+      double acc[3] = {0.5, 0.5, 0.5};
+      for (int k = 0; k < nsh; ++k)
+        for (int c = 0; c < 3; ++c) acc[c] += Y[k] * (double)shi[3 * k + c];
+      double ga[3];
+      for (int c = 0; c < 3; ++c) ga[c] = acc[c] > 0.0 ? (double)drgb[3 * i + c] : 0.0;
+      double gd[3] = {0.0, 0.0, 0.0};
+      for (int k = 0; k < nsh; ++k) {
+        double s = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          dsh[(size_t)i * nsh * 3 + 3 * k + c] = (float)(Y[k] * ga[c]);
+          s += (double)shi[3 * k + c] * ga[c];
+        }
+        for (int a = 0; a < 3; ++a) gd[a] += dY[k][a] * s;
+      }
+      // d = v / |v|: dL/dv = (gd - d (d . gd)) / |v|
+      const double dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
+      for (int a = 0; a < 3; ++a) gmu[a] += (gd[a] - d[a] * dd) / vn;
+    }
+
+    // ---- geometry, recomputed as in the forward
+    double qw = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
+    const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const double w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+    const double R[3][3] = {{1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)},
+                            {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)},
+                            {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)}};
+    const double s[3] = {scales[3 * i], scales[3 * i + 1], scales[3 * i + 2]};
+    double Sig[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) Sig[a][b] = R[a][0] * s[0] * s[0] * R[b][0] + R[a][1] * s[1] * s[1] * R[b][1] +
+                                              R[a][2] * s[2] * s[2] * R[b][2];
+    const double tz = t[2], iz = 1.0 / tz;
+    const double rx = t[0] * iz, ry = t[1] * iz;
+    const bool inx = rx > -cam.limx && rx < cam.limx, iny = ry > -cam.limy && ry < cam.limy;
+    const double txz = fmin(fmax(rx, -cam.limx), cam.limx), tyz = fmin(fmax(ry, -cam.limy), cam.limy);
+    const double J[2][3] = {{cam.fx * iz, 0.0, -cam.fx * txz * iz}, {0.0, cam.fy * iz, -cam.fy * tyz * iz}};
+    double T2[2][3];
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 3; ++b) T2[a][b] = J[a][0] * cam.R[b] + J[a][1] * cam.R[3 + b] + J[a][2] * cam.R[6 + b];
+    double TS_[2][3];  // T2 Sigma
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 3; ++b) TS_[a][b] = T2[a][0] * Sig[0][b] + T2[a][1] * Sig[1][b] + T2[a][2] * Sig[2][b];
+    const double Sxx = TS_[0][0] * T2[0][0] + TS_[0][1] * T2[0][1] + TS_[0][2] * T2[0][2];
+    const double Sxy = TS_[0][0] * T2[1][0] + TS_[0][1] * T2[1][1] + TS_[0][2] * T2[1][2];
+    const double Syy = TS_[1][0] * T2[1][0] + TS_[1][1] * T2[1][1] + TS_[1][2] * T2[1][2];
+    const double det0 = Sxx * Syy - Sxy * Sxy;
+    const double Axx = Sxx + p.aa_v, Ayy = Syy + p.aa_v;
+    const double deta = Axx * Ayy - Sxy * Sxy;
+    const double ratio = det0 / deta;
+    const double sr = ratio > 0.0 ? sqrt(ratio) : 0.0;
+
+    // ---- opacity: o' = o sqrt(det0 / deta)
+    const double go2 = dconic[4 * i + 3];
+    gop = go2 * sr;
+    double gSxx = 0.0, gSxy = 0.0, gSyy = 0.0;
+    if (ratio > 0.0) {
+      const double gr = go2 * (double)opac[i] * 0.5 / sr;  // dL/dratio
+      const double gdet0 = gr / deta, gdeta = -gr * det0 / (deta * deta);
+      gSxx += gdet0 * Syy + gdeta * Ayy;
+      gSyy += gdet0 * Sxx + gdeta * Axx;
+      gSxy += -2.0 * Sxy * (gdet0 + gdeta);
+    }
+    // ---- conic = S_a^-1: dL/dS_a = -conic G conic, G the symmetric gradient matrix
+    {
+      const double ca = Ayy / deta, cb = -Sxy / deta, cc = Axx / deta;
+      const double Ga = dconic[4 * i], Gb = 0.5 * (double)dconic[4 * i + 1], Gc = dconic[4 * i + 2];
+      // M = conic * G
+      const double M00 = ca * Ga + cb * Gb, M01 = ca * Gb + cb * Gc, M10 = cb * Ga + cc * Gb, M11 = cb * Gb + cc * Gc;
+      // N = M * conic
+      const double N00 = M00 * ca + M01 * cb, N01 = M00 * cb + M01 * cc, N11 = M10 * cb + M11 * cc;
+      gSxx -= N00;
+      gSyy -= N11;
+      gSxy -= 2.0 * N01;
+    }
+    // ---- EWA: S' = T2 Sigma T2^T with G' = [[gSxx, gSxy/2], [gSxy/2, gSyy]]
+    const double G2[2][2] = {{gSxx, 0.5 * gSxy}, {0.5 * gSxy, gSyy}};
+    double gSig[3][3];  // T2^T G' T2
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double acc = 0.0;
+        for (int u = 0; u < 2; ++u)
+          for (int v = 0; v < 2; ++v) acc += T2[u][a] * G2[u][v] * T2[v][b];
+        gSig[a][b] = acc;
+      }
+    double gT2[2][3];  // 2 G' T2 Sigma
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 3; ++b) gT2[a][b] = 2.0 * (G2[a][0] * TS_[0][b] + G2[a][1] * TS_[1][b]);
+    double gJ[2][3];  // dL/dT2 W^T
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 3; ++b) gJ[a][b] = gT2[a][0] * cam.R[3 * b] + gT2[a][1] * cam.R[3 * b + 1] +
+                                            gT2[a][2] * cam.R[3 * b + 2];
+    // J entries: J00 = fx iz, J02 = -fx txz iz, J11 = fy iz, J12 = -fy tyz iz
+    double giz = gJ[0][0] * cam.fx + gJ[1][1] * cam.fy - gJ[0][2] * cam.fx * txz - gJ[1][2] * cam.fy * tyz;
+    double gtxz = -gJ[0][2] * cam.fx * iz, gtyz = -gJ[1][2] * cam.fy * iz;
+    double gt[3] = {0.0, 0.0, 0.0};
+    // means2d: u = fx t.x iz + cx, v = fy t.y iz + cy
+    const double gu = dmeans2d[2 * i], gv = dmeans2d[2 * i + 1];
+    gt[0] += gu * cam.fx * iz;
+    gt[1] += gv * cam.fy * iz;
+    giz += gu * cam.fx * t[0] + gv * cam.fy * t[1];
+    // txz = clamp(t.x iz), tyz = clamp(t.y iz)
+    if (inx) {
+      gt[0] += gtxz * iz;
+      giz += gtxz * t[0];
+    }
+    if (iny) {
+      gt[1] += gtyz * iz;
+      giz += gtyz * t[1];
+    }
+    gt[2] += -giz * iz * iz;
+    // t = W mu + tw
+    for (int a = 0; a < 3; ++a) gmu[a] += cam.R[a] * gt[0] + cam.R[3 + a] * gt[1] + cam.R[6 + a] * gt[2];
+
+    // ---- Sigma = M M^T with M = R diag(s): dL/dM = 2 gSig M
+    double gR[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int k = 0; k < 3; ++k) {
+        double gM = 0.0;
+        for (int b = 0; b < 3; ++b) gM += 2.0 * gSig[a][b] * R[b][k] * s[k];
+        gR[a][k] = gM * s[k];
+        gs3[k] += gM * R[a][k];
+      }
+    // ---- R(q) with q normalised
+    const double gw = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
+    const double gx = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2 * x * gR[1][1] - w * gR[1][2] +
+                             z * gR[2][0] + w * gR[2][1] - 2 * x * gR[2][2]);
+    const double gy = 2.0 * (-2 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] -
+                             w * gR[2][0] + z * gR[2][1] - 2 * y * gR[2][2]);
+    const double gz = 2.0 * (-2 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2 * z * gR[1][1] +
+                             y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
+    const double dotq = w * gw + x * gx + y * gy + z * gz;
+    gq[0] = (gw - w * dotq) / qn;
+    gq[1] = (gx - x * dotq) / qn;
+    gq[2] = (gy - y * dotq) / qn;
+    gq[3] = (gz - z * dotq) / qn;
+  }
+  for (int a = 0; a < 3; ++a) {
+    dmeans3d[3 * i + a] = (float)gmu[a];
+    dscales[3 * i + a] = (float)gs3[a];
+  }
+  for (int a = 0; a < 4; ++a) dquats[4 * i + a] = (float)gq[a];
+  dopac[i] = (float)gop;
+}
+
+}  // namespace
+
+hipError_t launch_blend_bwd(const BlendParams &p, int64_t n, const float *means2d, const float *conic_opacity,
+                            const float *rgb, const uint32_t *vals, const uint32_t *ranges, const float *final_T,
+                            const uint32_t *last_contrib, const float *dL_dimage, float *dmeans2d,
+                            float *dconic_opacity, float *drgb, hipStream_t s) {
+  if (n > 0) {
+    hipLaunchKernelGGL(zero_f32, dim3(ceil_div(2 * n, 256)), dim3(256), 0, s, dmeans2d, 2 * n);
+    hipLaunchKernelGGL(zero_f32, dim3(ceil_div(4 * n, 256)), dim3(256), 0, s, dconic_opacity, 4 * n);
+    hipLaunchKernelGGL(zero_f32, dim3(ceil_div(3 * n, 256)), dim3(256), 0, s, drgb, 3 * n);
+  }
+  const dim3 grid(p.gx * p.gy), block(WAVE);
+  switch (p.blend) {
+    case BLEND_EXP:
+      hipLaunchKernelGGL(blend_bwd<BLEND_EXP>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
+                         final_T, last_contrib, dL_dimage, dmeans2d, dconic_opacity, drgb);
+      break;
+    case BLEND_POLY1:
+      hipLaunchKernelGGL(blend_bwd<BLEND_POLY1>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
+                         final_T, last_contrib, dL_dimage, dmeans2d, dconic_opacity, drgb);
+      break;
+    case BLEND_POLY2:
+      hipLaunchKernelGGL(blend_bwd<BLEND_POLY2>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
+                         final_T, last_contrib, dL_dimage, dmeans2d, dconic_opacity, drgb);
+      break;
+    default:
+      hipLaunchKernelGGL(blend_bwd<BLEND_POLY3>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
+                         final_T, last_contrib, dL_dimage, dmeans2d, dconic_opacity, drgb);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const PreParams &p, int64_t n, const float *means3d, const float *scales,
+                                 const float *quats, const float *opac, const float *sh, const uint32_t *tiles,
+                                 const float *dmeans2d, const float *dconic_opacity, const float *drgb,
+                                 float *dmeans3d, float *dscales, float *dquats, float *dopac, float *dsh,
+                                 hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(preprocess_bwd_kernel, dim3(ceil_div(n, 128)), dim3(128), 0, s, p, n, means3d, scales, quats,
+                     opac, sh, tiles, dmeans2d, dconic_opacity, drgb, dmeans3d, dscales, dquats, dopac, dsh);
+  return hipGetLastError();
 }
 
 }  // namespace gs

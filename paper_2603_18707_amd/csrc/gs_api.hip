@@ -76,6 +76,8 @@ gs_status check_params(const gs_params *p) {
   if (!(p->radius_pad >= 1.0f) || !std::isfinite(p->radius_pad)) return fail(GS_EINVAL, "radius_pad must be >= 1");
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(p->bg[i])) return fail(GS_EINVAL, "bg must be finite");
+  if (p->blend_threads != 0 && p->blend_threads != 64 && p->blend_threads != 128 && p->blend_threads != 256)
+    return fail(GS_EINVAL, "blend_threads %d must be 0, 64, 128 or 256", p->blend_threads);
   return GS_OK;
 }
 
@@ -183,6 +185,7 @@ gs_status gs_params_default(gs_params *out) {
   out->radius_pad = 1.0f + 1.0f / 1048576.0f;
   out->bg[0] = out->bg[1] = out->bg[2] = 0.0f;
   out->tile = 16;
+  out->blend_threads = 0;
   return GS_OK;
 }
 
@@ -265,9 +268,11 @@ static gs_status make_blend(const gs_camera *cam, const gs_kernel *kernel, const
   for (int i = 0; i < 4; ++i) b->c[i] = (float)r.c[i];
   b->x0 = (float)r.x0;
   b->eps = params->eps;
+  b->log2_eps = std::log2(params->eps);
   b->alpha_max = params->alpha_max;
   b->t_min = params->t_min;
   for (int i = 0; i < 3; ++i) b->bg[i] = params->bg[i];
+  b->threads = params->blend_threads ? params->blend_threads : 256;
   return GS_OK;
 }
 

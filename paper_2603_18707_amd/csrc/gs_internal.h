@@ -79,6 +79,8 @@ struct BlendParams {
   float c[4];            // polynomial coefficients in float
   float x0;              // order-2 cut
   float eps, alpha_max, t_min;
+  float log2_eps;        // log2(eps), for the exponential's threshold
+  int threads;           // blend workgroup size per tile: 64, 128 or 256
   float bg[3];
 };
 

@@ -68,7 +68,9 @@ __device__ double opacity_root(const double *c, int order, double target) {
 
 // Real spherical harmonics up to degree 3 (3DGS ordering and signs), times
 // the coefficients of one channel layout [nsh][3], accumulated in double.
-__device__ inline void sh_colour(int deg, double x, double y, double z, const float *sh, double out[3]) {
+template <int DEG>
+__device__ inline void sh_colour(double x, double y, double z, const float *sh, double out[3]) {
+  constexpr int deg = DEG;
   const double PI = 3.14159265358979323846;
   double Y[16];
   Y[0] = sqrt(1.0 / (4.0 * PI));
@@ -114,12 +116,32 @@ __device__ inline void sh_colour(int deg, double x, double y, double z, const fl
   out[2] = bl;
 }
 
-__global__ __launch_bounds__(256) void preprocess_kernel(PreParams p, int64_t n, const float *__restrict__ means3d,
-                                                         const float *__restrict__ scales,
-                                                         const float *__restrict__ quats,
-                                                         const float *__restrict__ opac,
-                                                         const float *__restrict__ sh, PreOut out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per 64 splats. The wave first copies its splats' SH coefficients
+// (a contiguous block) into LDS with coalesced loads, padded to an odd row
+// stride so the per-lane reads hit distinct banks; reading 48 floats per lane
+// straight from global memory would touch 64 cache lines per instruction.
+template <int DEG>
+__global__ __launch_bounds__(64) void preprocess_kernel(PreParams p, int64_t n, const float *__restrict__ means3d,
+                                                        const float *__restrict__ scales,
+                                                        const float *__restrict__ quats,
+                                                        const float *__restrict__ opac,
+                                                        const float *__restrict__ sh, PreOut out) {
+  constexpr int NSH3 = 3 * (DEG + 1) * (DEG + 1);
+  constexpr int ROW = NSH3 + 1;
+  __shared__ float shs[64 * ROW];
+  const int64_t base = (int64_t)blockIdx.x * 64;
+  const int lane = threadIdx.x;
+  {
+    const int64_t cnt = (n - base) < 64 ? (n - base) : 64;
+    const float *src = sh + base * NSH3;
+    const int total = (int)cnt * NSH3;
+    for (int e = lane; e < total; e += 64) {
+      const int s = e / NSH3, k = e - s * NSH3;
+      shs[s * ROW + k] = src[e];
+    }
+  }
+  __syncthreads();
+  const int64_t i = base + lane;
   if (i >= n) return;
   const CamD &cam = p.cam;
   const double mx = means3d[3 * i], my = means3d[3 * i + 1], mz = means3d[3 * i + 2];
@@ -208,9 +230,8 @@ __global__ __launch_bounds__(256) void preprocess_kernel(PreParams p, int64_t n,
     // colour along the ray from the camera centre
     double d0 = mx - cam.campos[0], d1 = my - cam.campos[1], d2 = mz - cam.campos[2];
     const double dn = 1.0 / sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-    const int nsh = (p.sh_degree + 1) * (p.sh_degree + 1);
     double c3[3];
-    sh_colour(p.sh_degree, d0 * dn, d1 * dn, d2 * dn, sh + (size_t)i * nsh * 3, c3);
+    sh_colour<DEG>(d0 * dn, d1 * dn, d2 * dn, shs + lane * ROW, c3);
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) col[ch] = (float)fmax(c3[ch] + 0.5, 0.0);
   } while (false);
@@ -249,8 +270,21 @@ hipError_t launch_preprocess(const PreParams &p, int64_t n, const float *means3d
                              const float *quats, const float *opac, const float *sh, PreOut out,
                              hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(preprocess_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, s, p, n, means3d, scales, quats,
-                     opac, sh, out);
+  const dim3 grid(ceil_div(n, 64)), block(64);
+  switch (p.sh_degree) {
+    case 0:
+      hipLaunchKernelGGL(preprocess_kernel<0>, grid, block, 0, s, p, n, means3d, scales, quats, opac, sh, out);
+      break;
+    case 1:
+      hipLaunchKernelGGL(preprocess_kernel<1>, grid, block, 0, s, p, n, means3d, scales, quats, opac, sh, out);
+      break;
+    case 2:
+      hipLaunchKernelGGL(preprocess_kernel<2>, grid, block, 0, s, p, n, means3d, scales, quats, opac, sh, out);
+      break;
+    default:
+      hipLaunchKernelGGL(preprocess_kernel<3>, grid, block, 0, s, p, n, means3d, scales, quats, opac, sh, out);
+      break;
+  }
   return hipGetLastError();
 }
 

@@ -1,149 +1,161 @@
 // Front-to-back blending of the sorted per-tile splat lists.
 //
-// One 256-thread workgroup per 16x16 tile, one pixel per thread; wave w owns
-// rows 4w..4w+3 of the tile. The tile's list is walked in batches of 256: each
-// thread gathers one splat record, folds the kernel's constants into it and
-// stages it in LDS; every lane then reads the records by broadcast. A pixel
-// leaves the loop at the splat that would push T below t_min; a wave leaves
-// when all its lanes have, and the workgroup stops fetching batches once every
-// pixel is done.
+// One workgroup of NT threads (64, 128 or 256: a launch parameter) per 16x16
+// tile, P = 256 / NT pixels per lane: lane l owns column l % 16 and rows
+// l / 16 + (NT / 16) k, k < P. The tile's list is walked in batches of NT;
+// each lane gathers one splat record, folds the kernel's constants into it and
+// stages it in LDS, then every lane reads the batch by broadcast, so one LDS
+// read of a record serves P pixels.
 //
-// Folding the kernel into the record removes per-evaluation work:
-//   poly order 1:  alpha = o c_0 + Q (o c_1)           conic pre-scaled by o c_1
-//   exp:           alpha = exp2(log2 o - Q log2(e)/2)   conic pre-scaled by -log2(e)/2
-//   poly 2, 3:     alpha = o p(Q), Horner on the plain quadric
-// so order 1 costs 7 VALU operations for alpha, exp costs 7 plus one v_exp.
+// Every kernel here is decreasing in the quadric Q on the part of its support
+// that matters, so "alpha >= eps" is the same decision as "Q <= x_e", where
+// x_e is the splat's opacity threshold: the root of o' p(x) = eps for a
+// polynomial (App. B) or 2 ln(o'/eps) for the exponential (Sec. 3.2, Eq. 3).
+// The inner loop therefore computes t = x_e - Q for the four pixels (a few
+// FMAs, exact differences d = pixel - mean) and evaluates the kernel itself
+// only where t >= 0. With t:
+//   poly order 1:  alpha = eps + (-o' c_1) t                       (one FMA)
+//   exp:           alpha = eps * 2^(t log2(e) / 2)                 (FMA + v_exp)
+//   poly 2, 3:     alpha = o' p(x_e - t) by Horner; Q <= x_e < x_0, so the
+//                  first-root cut of Eq. 6 never applies to a passing pair.
+// Pairs below the threshold, the vast majority when splats are small, cost the
+// same for every kernel; the kernels differ in how many pairs culling leaves
+// and in the arithmetic of the pairs that blend.
 //
-// Workgroups are dispatched round-robin over the eight XCDs; tile indices are
-// remapped so each XCD renders one contiguous band of tiles and its L2 holds
-// the splat records that band shares.
+// A lane's rows are NT / 16 apart, so a small splat's footprint falls in one
+// or two of its per-pixel branches and divergence stays low.
+#include <cmath>
+
+#include "blend_common.h"
 #include "gs_internal.h"
 
 namespace gs {
 
 namespace {
 
-constexpr int TS = 16;
-constexpr int BS = TS * TS;
-constexpr int NXCD = 8;
-
-// staged record: r0 = (u, v, a', 2 b'), r1 = (c', K, r, g), r2 = b, with the
-// conic (a, b, c) scaled by the kernel's factor and K its folded constant
-template <int KIND>
-__device__ inline void fold(float u, float v, float4 co, float3 c, const BlendParams &p, float4 &r0, float4 &r1,
-                            float &r2) {
-  float sc, k;
-  if (KIND == BLEND_POLY1) {
-    sc = co.w * p.c[1];
-    k = co.w * p.c[0];
-  } else if (KIND == BLEND_EXP) {
-    sc = -0.72134752044448170f;  // -log2(e) / 2
-    k = log2f(co.w);
-  } else {
-    sc = 1.0f;
-    k = co.w;
-  }
-  r0 = make_float4(u, v, co.x * sc, 2.0f * co.y * sc);
-  r1 = make_float4(co.z * sc, k, c.x, c.y);
-  r2 = c.z;
-}
-
-template <int KIND>
-__device__ inline float alpha_of(float dx, float dy, const float4 &r0, const float4 &r1, const BlendParams &p) {
-  // quadric (pre-scaled for POLY1 / EXP) plus the folded constant
-  if (KIND == BLEND_POLY1) {
-    return fminf(p.alpha_max, fmaf(r1.x * dy, dy, fmaf(dx, fmaf(r0.z, dx, r0.w * dy), r1.y)));
-  } else if (KIND == BLEND_EXP) {
-    const float e = fmaf(r1.x * dy, dy, fmaf(dx, fmaf(r0.z, dx, r0.w * dy), r1.y));
-    return fminf(p.alpha_max, __builtin_amdgcn_exp2f(e));
-  } else {
-    const float Q = fmaf(r1.x * dy, dy, dx * fmaf(r0.z, dx, r0.w * dy));
-    float f;
-    if (KIND == BLEND_POLY2) {
-      f = fmaf(fmaf(p.c[2], Q, p.c[1]), Q, p.c[0]);
-      f = (Q < p.x0) ? f : 0.0f;  // first-root cut of the quadratic
-    } else {
-      f = fmaf(fmaf(fmaf(p.c[3], Q, p.c[2]), Q, p.c[1]), Q, p.c[0]);
-    }
-    return fminf(p.alpha_max, r1.y * fmaxf(f, 0.0f));
-  }
-}
-
-template <int KIND>
-__global__ __launch_bounds__(BS) void blend_fwd(BlendParams p, const float *__restrict__ means2d,
+template <int KIND, int NT>
+__global__ __launch_bounds__(NT) void blend_fwd(BlendParams p, const float *__restrict__ means2d,
                                                 const float *__restrict__ conic_opacity,
                                                 const float *__restrict__ rgb, const uint32_t *__restrict__ vals,
                                                 const uint32_t *__restrict__ ranges, BlendOut out) {
-  __shared__ float4 s0[BS];
-  __shared__ float4 s1[BS];
-  __shared__ float s2[BS];
-
-  // XCD-aware mapping: block b runs on XCD b % 8; give each XCD a contiguous band
+  constexpr int P = TS * TS / NT;   // pixels per lane
+  constexpr int RS = NT / TS;       // row stride between a lane's pixels
+  __shared__ float4 L0[NT], L1[NT], L2[NT];
   const int ntiles = p.gx * p.gy;
-  const int per = (ntiles + NXCD - 1) / NXCD;
-  const int tile = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+  const int tile = blockIdx.x;
   if (tile >= ntiles) return;
+  const int lane = threadIdx.x;
   const int tx = tile % p.gx, ty = tile / p.gx;
-  const int px = tx * TS + (threadIdx.x & (TS - 1));
-  const int py = ty * TS + threadIdx.x / TS;
-  const bool inside = px < p.W && py < p.H;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-
+  const int px = tx * TS + (lane & (TS - 1));
+  const int py0 = ty * TS + lane / TS;
+  const float fx = (float)px + 0.5f;
+  float fy[P], T[P], C0[P], C1[P], C2[P];
+  uint32_t ncon[P], last[P], nev[P];
+  bool alive[P];
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
-  float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-  uint32_t ncon = 0, last = 0, nev = end - start;
-  bool done = !inside;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    fy[k] = (float)(py0 + RS * k) + 0.5f;
+    T[k] = 1.0f;
+    C0[k] = C1[k] = C2[k] = 0.0f;
+    ncon[k] = last[k] = 0u;
+    nev[k] = end - start;
+    alive[k] = px < p.W && (py0 + RS * k) < p.H;
+  }
 
-  for (uint32_t b = start; b < end; b += BS) {
-    if (__syncthreads_count(done) == BS) break;
-    const uint32_t idx = b + threadIdx.x;
+  for (uint32_t b = start; b < end; b += NT) {
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < P; ++k) any = any || alive[k];
+    if (__syncthreads_or(any) == 0) break;  // every pixel of the tile has terminated
+    const uint32_t idx = b + lane;
     if (idx < end) {
       uint32_t id = vals[idx];
       if (id >= p.n) id = 0;  // never taken for a list built by gs_bin_sort over these n splats
       const float2 m = reinterpret_cast<const float2 *>(means2d)[id];
       const float4 co = reinterpret_cast<const float4 *>(conic_opacity)[id];
       const float3 c = make_float3(rgb[3 * id], rgb[3 * id + 1], rgb[3 * id + 2]);
-      float4 r0, r1;
-      float r2;
-      fold<KIND>(m.x, m.y, co, c, p, r0, r1, r2);
-      s0[threadIdx.x] = r0;
-      s1[threadIdx.x] = r1;
-      s2[threadIdx.x] = r2;
+      float4 a0, a1, a2;
+      fold<KIND>(m, co, c, p, a0, a1, a2);
+      L0[lane] = a0;
+      L1[lane] = a1;
+      L2[lane] = a2;
     }
     __syncthreads();
-    const int cnt = (int)min((uint32_t)BS, end - b);
-    if (!done) {
+    const int cnt = (int)min((uint32_t)NT, end - b);
+    if (any) {
       for (int j = 0; j < cnt; ++j) {
-        const float4 r0 = s0[j];
-        const float4 r1 = s1[j];
-        const float dx = fx - r0.x, dy = fy - r0.y;
-        const float a = alpha_of<KIND>(dx, dy, r0, r1, p);
-        if (a < p.eps) continue;
-        const float Tn = T * (1.0f - a);
-        if (Tn < p.t_min) {
-          done = true;
-          nev = b + j - start + 1;
-          break;
+        const float4 r0 = L0[j];
+        const float4 r1 = L1[j];
+        const float dx = fx - r0.x;
+        const float adx = r0.z * dx;
+        const float R0 = fmaf(-adx, dx, r1.y);
+        const float Pq = r0.w * dx;
+        float t[P];
+        float mx = -1.0f;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+          const float dy = fy[k] - r0.y;
+          t[k] = fmaf(-dy, fmaf(r1.x, dy, Pq), R0);
+          mx = fmaxf(mx, t[k]);
         }
-        const float wgt = a * T;
-        C0 = fmaf(r1.z, wgt, C0);
-        C1 = fmaf(r1.w, wgt, C1);
-        C2 = fmaf(s2[j], wgt, C2);
-        T = Tn;
-        ++ncon;
-        last = b + j - start + 1;
+        if (mx >= 0.0f) {
+          const uint32_t pos = b + j - start + 1;
+#pragma unroll
+          for (int k = 0; k < P; ++k) {
+            if (t[k] >= 0.0f && alive[k]) {
+              const float a = alpha_from<KIND>(t[k], r1, p);
+              const float Tn = T[k] * (1.0f - a);
+              if (Tn < p.t_min) {
+                alive[k] = false;
+                nev[k] = pos;
+              } else {
+                const float4 r2 = L2[j];
+                const float w = a * T[k];
+                C0[k] = fmaf(r2.x, w, C0[k]);
+                C1[k] = fmaf(r2.y, w, C1[k]);
+                C2[k] = fmaf(r2.z, w, C2[k]);
+                T[k] = Tn;
+                ++ncon[k];
+                last[k] = pos;
+              }
+            }
+          }
+        }
       }
     }
+    __syncthreads();
   }
-  if (!inside) return;
-  const size_t pix = (size_t)py * p.W + px, plane = (size_t)p.W * p.H;
-  out.image[pix] = fmaf(T, p.bg[0], C0);
-  out.image[plane + pix] = fmaf(T, p.bg[1], C1);
-  out.image[2 * plane + pix] = fmaf(T, p.bg[2], C2);
-  out.final_T[pix] = T;
-  out.n_contrib[pix] = ncon;
-  out.last_contrib[pix] = last;
-  if (out.n_eval) out.n_eval[pix] = nev;
+  const size_t plane = (size_t)p.W * p.H;
+#pragma unroll
+  for (int k = 0; k < P; ++k) {
+    const int py = py0 + RS * k;
+    if (px >= p.W || py >= p.H) continue;
+    const size_t pix = (size_t)py * p.W + px;
+    out.image[pix] = fmaf(T[k], p.bg[0], C0[k]);
+    out.image[plane + pix] = fmaf(T[k], p.bg[1], C1[k]);
+    out.image[2 * plane + pix] = fmaf(T[k], p.bg[2], C2[k]);
+    out.final_T[pix] = T[k];
+    out.n_contrib[pix] = ncon[k];
+    out.last_contrib[pix] = last[k];
+    if (out.n_eval) out.n_eval[pix] = nev[k];
+  }
+}
+
+template <int KIND>
+hipError_t launch_kind(const BlendParams &p, const float *means2d, const float *conic_opacity, const float *rgb,
+                       const uint32_t *vals, const uint32_t *ranges, BlendOut out, hipStream_t s) {
+  const dim3 grid(p.gx * p.gy);
+  if (p.threads == 64)
+    hipLaunchKernelGGL((blend_fwd<KIND, 64>), grid, dim3(64), 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
+                       out);
+  else if (p.threads == 128)
+    hipLaunchKernelGGL((blend_fwd<KIND, 128>), grid, dim3(128), 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
+                       out);
+  else
+    hipLaunchKernelGGL((blend_fwd<KIND, 256>), grid, dim3(256), 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
+                       out);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -156,27 +168,16 @@ int blend_kind(const Resolved &r) {
 hipError_t launch_blend_fwd(const BlendParams &p, const float *means2d, const float *conic_opacity,
                             const float *rgb, const uint32_t *vals, const uint32_t *ranges, BlendOut out,
                             hipStream_t s) {
-  const int ntiles = p.gx * p.gy;
-  const int per = (ntiles + NXCD - 1) / NXCD;
-  const dim3 grid(per * NXCD), block(BS);
   switch (p.blend) {
     case BLEND_EXP:
-      hipLaunchKernelGGL(blend_fwd<BLEND_EXP>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges, out);
-      break;
+      return launch_kind<BLEND_EXP>(p, means2d, conic_opacity, rgb, vals, ranges, out, s);
     case BLEND_POLY1:
-      hipLaunchKernelGGL(blend_fwd<BLEND_POLY1>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
-                         out);
-      break;
+      return launch_kind<BLEND_POLY1>(p, means2d, conic_opacity, rgb, vals, ranges, out, s);
     case BLEND_POLY2:
-      hipLaunchKernelGGL(blend_fwd<BLEND_POLY2>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
-                         out);
-      break;
+      return launch_kind<BLEND_POLY2>(p, means2d, conic_opacity, rgb, vals, ranges, out, s);
     default:
-      hipLaunchKernelGGL(blend_fwd<BLEND_POLY3>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
-                         out);
-      break;
+      return launch_kind<BLEND_POLY3>(p, means2d, conic_opacity, rgb, vals, ranges, out, s);
   }
-  return hipGetLastError();
 }
 
 }  // namespace gs

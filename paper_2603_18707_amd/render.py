@@ -50,17 +50,21 @@ class Rasterizer:
     """Renders frames of one kernel configuration; keeps its buffers and the
     key capacity between frames (the capacity grows when a frame overflows)."""
 
-    def __init__(self, kernel: L.GsKernel, params: L.GsParams = None, device="cuda", capacity: int = 0):
+    def __init__(self, kernel: L.GsKernel, params: L.GsParams = None, device="cuda", capacity: int = 0,
+                 reuse_buffers: bool = True):
         self.kernel = kernel
         self.params = params if params is not None else L.gs_params_default()
         self.device = torch.device(device)
         self.capacity = int(capacity)
+        self.reuse = reuse_buffers  # False: every frame gets fresh outputs (autograd keeps them)
         self._bufs = {}
 
     # -- buffers ---------------------------------------------------------
     def _buf(self, name, shape, dtype):
         t = self._bufs.get(name)
         numel = int(np.prod(shape))
+        if not self.reuse and name != "ws":
+            t = None
         if t is None or t.numel() < numel or t.dtype != dtype:
             t = torch.empty(max(numel, 1), dtype=dtype, device=self.device)
             self._bufs[name] = t

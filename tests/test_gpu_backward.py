@@ -1,0 +1,126 @@
+"""GPU backward against the reference gradient, through the C ABI.
+
+The reference gradient is exact reverse-mode through the FP64 torch
+re-implementation (``oracle.grad``), itself pinned to FP64 central finite
+differences of the C oracle (tests/test_oracle_grad.py). Sub-problem: 64
+splats, 32x32, SH degree 3 (and the same with 4x larger splats, where splats
+overlap and the transmittance recursion matters). Loss: sum of random weights
+times the image, so dL/dimage is the weight image.
+
+Bar (FP32 kernels with float atomics against FP64): cosine similarity of every
+parameter group above 0.9999, and per entry |g - g_ref| <= 2e-3 |g_ref| +
+2e-5 max |g_ref| of the group.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import core as ocore, grad as ograd
+from paper_2603_18707_amd import autograd, render, scenes
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("poly", 1, "opacity", 1.0), ("poly", 1, "opacity", 4.0), ("exp", 1, "sigma3", 4.0),
+         ("poly", 2, "opacity", 4.0), ("poly", 3, "opacity", 4.0), ("poly", 1, "universal", 4.0)]
+
+
+def _scene(scale_mul):
+    scene, cam = scenes.workload_fd()
+    scene.scales *= scale_mul
+    return scene, cam
+
+
+def _compare(name, g, ref):
+    g, ref = np.asarray(g, np.float64).ravel(), np.asarray(ref, np.float64).ravel()
+    mx = np.abs(ref).max()
+    if mx == 0:
+        assert np.abs(g).max() == 0, name
+        return
+    cos = g @ ref / (np.linalg.norm(g) * np.linalg.norm(ref))
+    assert cos > 0.9999, (name, cos)
+    bad = np.abs(g - ref) > 2e-3 * np.abs(ref) + 2e-5 * mx
+    assert not bad.any(), (name, np.nonzero(bad)[0][:5], g[bad][:5], ref[bad][:5])
+
+
+@pytest.mark.parametrize("kind,order,radius,scale_mul", CASES)
+def test_scene_gradients_match_reference(kind, order, radius, scale_mul):
+    scene, cam = _scene(scale_mul)
+    cfg = H.oracle_cfg(kind, order, radius)
+    # pixels holding a decision within single-precision reach of a threshold get zero weight,
+    # so whichever way the GPU takes that decision the loss does not see it
+    ref = ocore.render_image(scene, cam, cfg, round_to=None)
+    assert (ref["flags"] != 0).sum() <= 2
+    w = np.random.default_rng(31).normal(size=(3, cam.height, cam.width)) * (ref["flags"] == 0)
+
+    leaves = {k: torch.tensor(np.asarray(getattr(scene, k), np.float64), requires_grad=True)
+              for k in ("means3d", "scales", "quats", "opacities", "sh")}
+    img, _ = ograd.render(leaves["means3d"], leaves["scales"], leaves["quats"], leaves["opacities"], leaves["sh"],
+                          scene.sh_degree, cam, cfg)
+    (img * torch.as_tensor(w)).sum().backward()
+
+    print(f"[gpu] backward {kind}{order}/{radius} x{scale_mul}", flush=True)
+    dev = {k: torch.tensor(np.asarray(getattr(scene, k), np.float32), device="cuda", requires_grad=True)
+           for k in ("means3d", "scales", "quats", "opacities", "sh")}
+    gimg = autograd.render(dev["means3d"], dev["scales"], dev["quats"], dev["opacities"], dev["sh"], scene.sh_degree,
+                           cam, H.gpu_kernel(kind, order, radius), H.gpu_params())
+    assert np.abs(gimg.detach().cpu().numpy() - ref["image"]).max() < 2e-4
+    (gimg * torch.as_tensor(w, dtype=torch.float32, device="cuda")).sum().backward()
+    torch.cuda.synchronize()
+    for k in leaves:
+        _compare(k, dev[k].grad.cpu().numpy(), leaves[k].grad.numpy())
+
+
+@pytest.mark.parametrize("kind,order,radius,scale_mul", CASES[:4])
+def test_record_gradients_match_reference(kind, order, radius, scale_mul):
+    """Gradients of the 2D record (means2d, conic a/b/c, opacity o', rgb) from gs_rasterize_bwd."""
+    scene, cam = _scene(scale_mul)
+    cfg = H.oracle_cfg(kind, order, radius)
+    t64 = {k: torch.tensor(np.asarray(getattr(scene, k), np.float64)) for k in
+           ("means3d", "scales", "quats", "opacities", "sh")}
+    proj = ograd.project(t64["means3d"], t64["scales"], t64["quats"], t64["opacities"], t64["sh"], scene.sh_degree,
+                         cam, cfg)
+    leaf = {k: proj[k].detach().clone().requires_grad_(True) for k in ("u", "v", "a", "b", "c", "opac", "rgb")}
+    p2 = dict(proj, **leaf)
+    img, _ = ograd.render(None, None, None, None, None, scene.sh_degree, cam, cfg, proj=p2)
+    ref = ocore.render_image(scene, cam, cfg, round_to=None)
+    w = np.random.default_rng(32).normal(size=(3, cam.height, cam.width)) * (ref["flags"] == 0)
+    (img * torch.as_tensor(w)).sum().backward()
+
+    r = render.Rasterizer(H.gpu_kernel(kind, order, radius), H.gpu_params(), reuse_buffers=False)
+    frame = r.render(render.to_device(scene), cam)
+    g2d = autograd.rasterize_backward(r, frame, cam, torch.as_tensor(w, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    gm = g2d["means2d"].cpu().numpy()
+    gc = g2d["conic_opacity"].cpu().numpy()
+    _compare("u", gm[:, 0], leaf["u"].grad.numpy())
+    _compare("v", gm[:, 1], leaf["v"].grad.numpy())
+    _compare("a", gc[:, 0], leaf["a"].grad.numpy())
+    _compare("b", gc[:, 1], leaf["b"].grad.numpy())
+    _compare("c", gc[:, 2], leaf["c"].grad.numpy())
+    _compare("opacity", gc[:, 3], leaf["opac"].grad.numpy())
+    _compare("rgb", g2d["rgb"].cpu().numpy(), leaf["rgb"].grad.numpy())
+
+
+def test_backward_with_background_and_termination():
+    """Dense opaque splats so pixels terminate early, with a non-zero background."""
+    scene, cam = _scene(6.0)
+    scene.opacities[:] = np.float32(0.97)
+    bg = (0.3, 0.1, 0.7)
+    cfg = H.oracle_cfg("poly", 1, "opacity", bg=bg)
+    ref = ocore.render_image(scene, cam, cfg, round_to=None)
+    leaves = {k: torch.tensor(np.asarray(getattr(scene, k), np.float64), requires_grad=True)
+              for k in ("means3d", "scales", "quats", "opacities", "sh")}
+    img, _ = ograd.render(*[leaves[k] for k in ("means3d", "scales", "quats", "opacities", "sh")], scene.sh_degree,
+                          cam, cfg)
+    w = np.random.default_rng(33).normal(size=(3, cam.height, cam.width)) * (ref["flags"] == 0)
+    (img * torch.as_tensor(w)).sum().backward()
+    dev = {k: torch.tensor(np.asarray(getattr(scene, k), np.float32), device="cuda", requires_grad=True)
+           for k in ("means3d", "scales", "quats", "opacities", "sh")}
+    gimg = autograd.render(*[dev[k] for k in ("means3d", "scales", "quats", "opacities", "sh")], scene.sh_degree,
+                           cam, H.gpu_kernel("poly", 1, "opacity"), H.gpu_params(bg=bg))
+    (gimg * torch.as_tensor(w, dtype=torch.float32, device="cuda")).sum().backward()
+    torch.cuda.synchronize()
+    assert (ref["T"] < 1.5e-4).sum() > 50  # many pixels end near t_min
+    for k in leaves:
+        _compare(k, dev[k].grad.cpu().numpy(), leaves[k].grad.numpy())

@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--only", default=None, help="time one configuration: poly1|exp")
     ap.add_argument("--blend-threads", type=int, default=0, help="64|128|256; 0 = autotune")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-view measurement")
+    ap.add_argument("--no-train", action="store_true", help="skip the forward+backward step measurement")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -109,6 +113,114 @@ def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, t
                 threads=int(r.params.blend_threads), tuned=tuned)
 
 
+def time_batched(torch, render, scenes, steps):
+    """96 views of 6 scenes (100k-2M splats): per-view sequential frames against
+    one batched frame (eager, then replayed from a captured HIP graph)."""
+    from paper_2603_18707_amd import batch
+    sc_np, views = scenes.workload_batched()
+    dev = [render.to_device(s) for s in sc_np]
+    kern = render.kernel_spec("poly", 1, "opacity")
+    stream = torch.cuda.current_stream()
+    npix = sum(int(c.width) * int(c.height) for _, c in views)
+
+    # per-view sequential launches (capacity fitted once per view, outside the timing)
+    rs = []
+    for si, cam in views:
+        r = render.Rasterizer(kern)
+        f = r.render(dev[si], cam)
+        r.capacity = int(int(f["binned"]["num_keys"].item()) * 1.05) + 4096
+        rs.append(r)
+    for (si, cam), r in zip(views, rs):
+        pr = r.preprocess(dev[si], cam)
+        r.rasterize(pr, r.bin_sort(pr, cam), cam)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        for (si, cam), r in zip(views, rs):
+            pr = r.preprocess(dev[si], cam)
+            r.rasterize(pr, r.bin_sort(pr, cam), cam)
+    b.record(stream)
+    torch.cuda.synchronize()
+    seq_ms = a.elapsed_time(b) / steps
+    del rs
+
+    br = batch.BatchRenderer(dev, views, kern)
+    K = br.render_fit()
+    br.capacity = int(K * 1.05) + 4096
+    br._layout()
+    tuned = batch.tune_batch(br)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(steps):
+        br.render()
+    b.record(stream)
+    torch.cuda.synchronize()
+    eager_ms = a.elapsed_time(b) / steps
+    br.capture()
+    br.replay()
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(steps):
+        br.replay()
+    b.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = a.elapsed_time(b) / steps
+    assert int(br.overflow.item()) == 0
+    return {"workload": "6 scenes (100k-2M splats, SH3), 96 views 640x360..1920x1080, poly-1/opacity",
+            "pixels": npix, "keys": K, "pairs": br.pairs,
+            "per_view_sequential_ms": round(seq_ms, 3), "batched_eager_ms": round(eager_ms, 3),
+            "batched_graph_ms": round(graph_ms, 3),
+            "Mpix_per_s_graph": round(npix / (graph_ms * 1e-3) / 1e6, 1),
+            "speedup_graph_vs_sequential": round(seq_ms / graph_ms, 3),
+            "tuned": {"blend_threads": int(br.params.blend_threads), "workgroups": int(br.workgroups),
+                      "candidates_ms": {f"{k[0]}x{k[1]}": round(v, 3) for k, v in tuned.items()}}}
+
+
+def time_train_step(torch, render, scenes, steps):
+    """One optimisation step's forward + hand-written backward: 500k splats,
+    4 views at 1280x720, poly-1/opacity, L1 loss against targets rendered
+    from a perturbed copy of the scene."""
+    from paper_2603_18707_amd import autograd
+    sc, tgt, cams = scenes.workload_train()
+    kern = render.kernel_spec("poly", 1, "opacity")
+    dt = render.to_device(tgt)
+    targets = []
+    for cam in cams:
+        r = render.Rasterizer(kern)
+        targets.append(r.render(dt, cam)["image"].clone())
+    dev = render.to_device(sc)
+    leaves = [t.clone().requires_grad_(True) for t in (dev.means3d, dev.scales, dev.quats, dev.opacities, dev.sh)]
+
+    rs = [render.Rasterizer(kern, reuse_buffers=False) for _ in cams]
+
+    def step():
+        loss = 0.0
+        for cam, tg, r in zip(cams, targets, rs):
+            img = autograd.render(*leaves, sc.sh_degree, cam, kern, rasterizer=r)
+            loss = loss + (img - tg).abs().mean()
+        loss.backward()
+        return loss
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        for t in leaves:
+            t.grad = None
+        loss = step()
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    g = torch.cat([t.grad.reshape(-1) for t in leaves])
+    assert torch.isfinite(g).all()
+    return {"workload": "500k splats (SH3), 4 views 1280x720, poly-1/opacity, L1 loss, forward + backward",
+            "ms_per_step": round(ms, 3), "views_per_s": round(4 / (ms * 1e-3), 1), "loss": float(loss)}
+
+
 def cpu_baseline(scene_np, cam, gpu_image, target_s):
     """The FP64 oracle on a bounded pixel sample of the same frame (poly-1, opacity radius)."""
     from oracle import core as ocore
@@ -154,6 +266,13 @@ def main():
     _lib.lib()
     torch.cuda.set_device(0)
     print(f"[bench] {_lib.gs_version()} on {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
+    if a.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     scene_np, cam = scenes.workload_scene()
     scene = render.to_device(scene_np)
     W, H = cam.width, cam.height
@@ -208,6 +327,14 @@ def main():
                                           "bin_sort": round(e["stage_ms"][1], 4),
                                           "blend": round(e["stage_ms"][2], 4)}}
         out["speedup_vs_exp_sigma3"] = round(e["ms"] / ms, 4)
+    if not a.no_batched and not a.only:
+        print("[bench] batched multi-view ...", file=sys.stderr, flush=True)
+        out["batched"] = time_batched(torch, render, scenes, max(2, a.steps // 10))
+        print(f"[bench] batched: {out['batched']}", file=sys.stderr, flush=True)
+    if not a.no_train and not a.only:
+        print("[bench] training step ...", file=sys.stderr, flush=True)
+        out["train_step"] = time_train_step(torch, render, scenes, max(3, a.steps // 10))
+        print(f"[bench] train: {out['train_step']}", file=sys.stderr, flush=True)
     if not a.no_cpu and hname == "poly1":
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
         cb, err, nflag, m = cpu_baseline(scene_np, cam, head["image"].cpu().numpy(), a.cpu_seconds)

@@ -182,12 +182,15 @@ gs_status gs_bin_sort_workspace(int64_t n, int64_t key_capacity, int32_t num_til
  *      overflow (device int32) = 1 when K > key_capacity, else 0. On overflow
  *      no key is written and every range is (0, 0); the caller reads
  *      *num_keys and calls again with a larger capacity.
+ *      tile_order [grid_w * grid_h] uint32 (may be NULL) = every tile id once,
+ *      longest lists first (lists bucketed by length); passed to the blend
+ *      entry points it makes the workgroups with the most work start first.
  * workspace: device buffer of at least gs_bin_sort_workspace() bytes,
  *      contents undefined before and after. */
 gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles_touched,
                       int32_t grid_w, int32_t grid_h, int64_t key_capacity, void *workspace,
                       size_t workspace_bytes, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
-                      int64_t *num_keys, int32_t *overflow, void *stream);
+                      uint32_t *tile_order, int64_t *num_keys, int32_t *overflow, void *stream);
 
 /* Front-to-back blending per pixel (Sec. 2, Eq. 1 and the alpha compositing
  * it feeds; the kernel of Sec. 3 Eq. 2 / Eq. 6 or exp). For each pixel, over
@@ -196,8 +199,10 @@ gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const 
  * the pixel stops, without blending, at the first splat with T' < t_min;
  * otherwise C += rgb alpha T and T = T'. image = C + T bg.
  *
- * in : means2d, conic_opacity, rgb (gs_preprocess), vals and ranges
- *      (gs_bin_sort), n = number of splats the values index.
+ * in : means2d, conic_opacity, rgb (gs_preprocess), vals, ranges and
+ *      tile_order (gs_bin_sort; tile_order may be NULL for row-major order,
+ *      it only changes which workgroup renders which tile), n = number of
+ *      splats the values index.
  * out: image [3,H,W] planar, final_T [H,W], n_contrib [H,W] = splats
  *      blended, last_contrib [H,W] = 1 + list position (within the tile)
  *      of the last blended splat, 0 if none (the backward pass starts there),
@@ -205,8 +210,9 @@ gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const 
  *      that stopped the pixel. */
 gs_status gs_rasterize_fwd(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
                            const float *means2d, const float *conic_opacity, const float *rgb,
-                           const uint32_t *vals, const uint32_t *ranges, float *image, float *final_T,
-                           uint32_t *n_contrib, uint32_t *last_contrib, uint32_t *n_eval, void *stream);
+                           const uint32_t *vals, const uint32_t *ranges, const uint32_t *tile_order, float *image,
+                           float *final_T, uint32_t *n_contrib, uint32_t *last_contrib, uint32_t *n_eval,
+                           void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* backward path (the derivative of the ReLU-polynomial kernel the paper   */
@@ -224,9 +230,9 @@ gs_status gs_rasterize_fwd(const gs_camera *cam, const gs_kernel *kernel, const 
  *      dL_drgb [n,3]. The outputs are zeroed, then accumulated. */
 gs_status gs_rasterize_bwd(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
                            const float *means2d, const float *conic_opacity, const float *rgb,
-                           const uint32_t *vals, const uint32_t *ranges, const float *final_T,
-                           const uint32_t *last_contrib, const float *dL_dimage, float *dL_dmeans2d,
-                           float *dL_dconic_opacity, float *dL_drgb, void *stream);
+                           const uint32_t *vals, const uint32_t *ranges, const uint32_t *tile_order,
+                           const float *final_T, const uint32_t *last_contrib, const float *dL_dimage,
+                           float *dL_dmeans2d, float *dL_dconic_opacity, float *dL_drgb, void *stream);
 
 /* Adjoint of gs_preprocess: chains the 2D gradients through the anti-aliasing
  * factor, the conic inverse, EWA, the rotation and scale and the spherical
@@ -244,6 +250,57 @@ gs_status gs_preprocess_bwd(const gs_camera *cam, const gs_kernel *kernel, const
                             const float *dL_dconic_opacity, const float *dL_drgb, float *dL_dmeans3d,
                             float *dL_dscales, float *dL_dquats, float *dL_dopacities, float *dL_dsh,
                             void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* batched rendering: many (scene, view) pairs in one graph-capturable     */
+/* frame                                                                   */
+/* ---------------------------------------------------------------------- */
+
+/* A scene: n splats in the layouts gs_preprocess takes (device pointers). */
+typedef struct {
+  int64_t n;
+  const float *means3d, *scales, *quats, *opacities, *sh;
+  int32_t sh_degree;  /* must be the same for every scene of a batch */
+  int32_t reserved;   /* must be 0 */
+} gs_scene;
+
+/* A view: which scene it renders, with which camera, and where its outputs
+ * go: image [3,H,W] at images + image_offset, and the [H,W] planes at
+ * final_T / n_contrib / last_contrib + pixel_offset (element offsets). */
+typedef struct {
+  gs_camera cam;
+  int32_t scene;
+  int32_t reserved;   /* must be 0 */
+  int64_t image_offset;
+  int64_t pixel_offset;
+} gs_view;
+
+/* Sizes of a batch: num_pairs (scene splats per view, each view padded to a
+ * multiple of 64), the virtual tile grid (width = widest view's tile columns,
+ * height = all views' tile rows stacked) and the workspace bytes
+ * gs_render_batched needs for the given key capacity. Host only. */
+gs_status gs_batch_layout(const gs_scene *scenes, int32_t num_scenes, const gs_view *views, int32_t num_views,
+                          int64_t key_capacity, int64_t *num_pairs, int32_t *grid_w, int32_t *grid_h,
+                          size_t *workspace_bytes);
+
+/* Renders every view of `views` (host copy, validated here) with one batched
+ * projection, one binning and sort of all views' keys in a shared virtual tile
+ * grid (the keys of Sec. 2.1's tile partitioning with view tile rows stacked),
+ * and one persistent blend launch whose workgroups take tiles from a device
+ * queue. `views_device` must hold the same table in device memory: kernels
+ * read it there, so the call enqueues kernels only (no host copies, no
+ * allocation, no memset) and can be captured in a graph and replayed; a device
+ * entry that fails the host's bounds checks renders nothing. Outputs equal
+ * gs_rasterize_fwd's for each view bit for bit. workgroups: persistent blend
+ * workgroups (0 = library default). images_len / planes_len: lengths (in
+ * elements) of the output buffers, checked against every view's range.
+ * num_keys / overflow as in gs_bin_sort (on overflow nothing is blended). */
+gs_status gs_render_batched(const gs_kernel *kernel, const gs_params *params, const gs_scene *scenes,
+                            int32_t num_scenes, const gs_view *views, const gs_view *views_device,
+                            int32_t num_views, int64_t key_capacity, int32_t workgroups, void *workspace,
+                            size_t workspace_bytes, float *images, int64_t images_len, float *final_T,
+                            uint32_t *n_contrib, uint32_t *last_contrib, int64_t planes_len, int64_t *num_keys,
+                            int32_t *overflow, void *stream);
 
 #ifdef __cplusplus
 }

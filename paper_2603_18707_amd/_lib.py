@@ -34,6 +34,17 @@ class GsCamera(ctypes.Structure):
                 ("height", ctypes.c_int32)]
 
 
+class GsScene(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("means3d", ctypes.c_void_p), ("scales", ctypes.c_void_p),
+                ("quats", ctypes.c_void_p), ("opacities", ctypes.c_void_p), ("sh", ctypes.c_void_p),
+                ("sh_degree", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class GsView(ctypes.Structure):
+    _fields_ = [("cam", GsCamera), ("scene", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("image_offset", ctypes.c_int64), ("pixel_offset", ctypes.c_int64)]
+
+
 class GsError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"libgs status {status}: {msg}")
@@ -44,7 +55,7 @@ _lib = None
 
 EXPORTS = ("gs_version", "gs_last_error", "gs_kernel_default", "gs_kernel_root", "gs_params_default",
            "gs_preprocess", "gs_bin_sort_workspace", "gs_bin_sort", "gs_rasterize_fwd", "gs_rasterize_bwd",
-           "gs_preprocess_bwd")
+           "gs_preprocess_bwd", "gs_batch_layout", "gs_render_batched")
 
 
 def lib():
@@ -63,10 +74,13 @@ def lib():
         L.gs_params_default.argtypes = [P]
         L.gs_preprocess.argtypes = [P, P, P, I64] + [P] * 5 + [I32] + [P] * 6 + [P]
         L.gs_bin_sort_workspace.argtypes = [I64, I64, I32, P]
-        L.gs_bin_sort.argtypes = [I64, P, P, P, I32, I32, I64, P, ctypes.c_size_t] + [P] * 5 + [P]
-        L.gs_rasterize_fwd.argtypes = [P, P, P, I64] + [P] * 5 + [P] * 5 + [P]
-        L.gs_rasterize_bwd.argtypes = [P, P, P, I64] + [P] * 5 + [P] * 3 + [P] * 3 + [P]
+        L.gs_bin_sort.argtypes = [I64, P, P, P, I32, I32, I64, P, ctypes.c_size_t] + [P] * 6 + [P]
+        L.gs_rasterize_fwd.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 5 + [P]
+        L.gs_rasterize_bwd.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 3 + [P] * 3 + [P]
         L.gs_preprocess_bwd.argtypes = [P, P, P, I64] + [P] * 5 + [I32] + [P] * 4 + [P] * 5 + [P]
+        L.gs_batch_layout.argtypes = [P, I32, P, I32, I64, P, P, P, P]
+        L.gs_render_batched.argtypes = [P, P, P, I32, P, P, I32, I64, I32, P, ctypes.c_size_t, P, I64, P, P, P, I64,
+                                        P, P, P]
         for name in EXPORTS[2:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -161,26 +175,26 @@ def gs_bin_sort_workspace(n, key_capacity, num_tiles) -> int:
 
 
 def gs_bin_sort(n, depth, rect, tiles_touched, grid_w, grid_h, key_capacity, workspace, workspace_bytes, keys,
-                vals, ranges, num_keys, overflow, stream=None):
+                vals, ranges, tile_order, num_keys, overflow, stream=None):
     _check(lib().gs_bin_sort(int(n), _ptr(depth), _ptr(rect), _ptr(tiles_touched), int(grid_w), int(grid_h),
                              int(key_capacity), _ptr(workspace), int(workspace_bytes), _ptr(keys), _ptr(vals),
-                             _ptr(ranges), _ptr(num_keys), _ptr(overflow), _stream(stream)))
+                             _ptr(ranges), _ptr(tile_order), _ptr(num_keys), _ptr(overflow), _stream(stream)))
 
 
-def gs_rasterize_fwd(cam, kernel, params, n, means2d, conic_opacity, rgb, vals, ranges, image, final_T,
+def gs_rasterize_fwd(cam, kernel, params, n, means2d, conic_opacity, rgb, vals, ranges, tile_order, image, final_T,
                      n_contrib, last_contrib, n_eval=None, stream=None):
     _check(lib().gs_rasterize_fwd(ctypes.byref(cam), ctypes.byref(kernel), ctypes.byref(params), int(n),
                                   _ptr(means2d), _ptr(conic_opacity), _ptr(rgb), _ptr(vals), _ptr(ranges),
-                                  _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(last_contrib), _ptr(n_eval),
-                                  _stream(stream)))
+                                  _ptr(tile_order), _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(last_contrib),
+                                  _ptr(n_eval), _stream(stream)))
 
 
-def gs_rasterize_bwd(cam, kernel, params, n, means2d, conic_opacity, rgb, vals, ranges, final_T, last_contrib,
-                     dL_dimage, dL_dmeans2d, dL_dconic_opacity, dL_drgb, stream=None):
+def gs_rasterize_bwd(cam, kernel, params, n, means2d, conic_opacity, rgb, vals, ranges, tile_order, final_T,
+                     last_contrib, dL_dimage, dL_dmeans2d, dL_dconic_opacity, dL_drgb, stream=None):
     _check(lib().gs_rasterize_bwd(ctypes.byref(cam), ctypes.byref(kernel), ctypes.byref(params), int(n),
                                   _ptr(means2d), _ptr(conic_opacity), _ptr(rgb), _ptr(vals), _ptr(ranges),
-                                  _ptr(final_T), _ptr(last_contrib), _ptr(dL_dimage), _ptr(dL_dmeans2d),
-                                  _ptr(dL_dconic_opacity), _ptr(dL_drgb), _stream(stream)))
+                                  _ptr(tile_order), _ptr(final_T), _ptr(last_contrib), _ptr(dL_dimage),
+                                  _ptr(dL_dmeans2d), _ptr(dL_dconic_opacity), _ptr(dL_drgb), _stream(stream)))
 
 
 def gs_preprocess_bwd(cam, kernel, params, n, means3d, scales, quats, opacities, sh, sh_degree, tiles_touched,
@@ -191,3 +205,21 @@ def gs_preprocess_bwd(cam, kernel, params, n, means3d, scales, quats, opacities,
                                    int(sh_degree), _ptr(tiles_touched), _ptr(dL_dmeans2d), _ptr(dL_dconic_opacity),
                                    _ptr(dL_drgb), _ptr(dL_dmeans3d), _ptr(dL_dscales), _ptr(dL_dquats),
                                    _ptr(dL_dopacities), _ptr(dL_dsh), _stream(stream)))
+
+
+def gs_batch_layout(scenes, views, key_capacity):
+    """(num_pairs, grid_w, grid_h, workspace_bytes) for ctypes arrays of GsScene / GsView."""
+    n, gw, gh, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_size_t()
+    _check(lib().gs_batch_layout(scenes, len(scenes), views, len(views), int(key_capacity), ctypes.byref(n),
+                                 ctypes.byref(gw), ctypes.byref(gh), ctypes.byref(b)))
+    return n.value, gw.value, gh.value, b.value
+
+
+def gs_render_batched(kernel, params, scenes, views, views_device, key_capacity, workgroups, workspace,
+                      workspace_bytes, images, images_len, final_T, n_contrib, last_contrib, planes_len, num_keys,
+                      overflow, stream=None):
+    _check(lib().gs_render_batched(ctypes.byref(kernel), ctypes.byref(params), scenes, len(scenes), views,
+                                   _ptr(views_device), len(views), int(key_capacity), int(workgroups),
+                                   _ptr(workspace), int(workspace_bytes), _ptr(images), int(images_len),
+                                   _ptr(final_T), _ptr(n_contrib), _ptr(last_contrib), int(planes_len),
+                                   _ptr(num_keys), _ptr(overflow), _stream(stream)))

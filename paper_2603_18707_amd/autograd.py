@@ -22,7 +22,8 @@ def rasterize_backward(r: Rasterizer, frame: dict, cam, dL_dimage: torch.Tensor)
                conic_opacity=torch.empty((n, 4), dtype=torch.float32, device=dev),
                rgb=torch.empty((n, 3), dtype=torch.float32, device=dev))
     L.gs_rasterize_bwd(L.make_camera(cam), r.kernel, r.params, n, proj["means2d"], proj["conic_opacity"], proj["rgb"],
-                       b["vals"], b["ranges"], frame["final_T"], frame["last_contrib"], dL_dimage.contiguous(),
+                       b["vals"], b["ranges"], b.get("tile_order"), frame["final_T"], frame["last_contrib"],
+                       dL_dimage.contiguous(),
                        out["means2d"], out["conic_opacity"], out["rgb"])
     return out
 
@@ -59,7 +60,10 @@ class _Render(torch.autograd.Function):
 
 
 def render(means3d, scales, quats, opacities, sh, sh_degree: int, cam, kernel: L.GsKernel,
-           params: L.GsParams = None) -> torch.Tensor:
-    """Differentiable image [3, H, W] of the scene (activated parameters)."""
-    r = Rasterizer(kernel, params, device=means3d.device, reuse_buffers=False)
+           params: L.GsParams = None, rasterizer: Rasterizer = None) -> torch.Tensor:
+    """Differentiable image [3, H, W] of the scene (activated parameters).
+    Passing the same ``rasterizer`` (built with reuse_buffers=False) across
+    steps keeps its fitted key capacity."""
+    r = rasterizer if rasterizer is not None else Rasterizer(kernel, params, device=means3d.device,
+                                                             reuse_buffers=False)
     return _Render.apply(means3d, scales, quats, opacities, sh, sh_degree, cam, r)

@@ -59,6 +59,7 @@ __global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__
                                                   const float *__restrict__ conic_opacity,
                                                   const float *__restrict__ rgb, const uint32_t *__restrict__ vals,
                                                   const uint32_t *__restrict__ ranges,
+                                                  const uint32_t *__restrict__ tile_order,
                                                   const float *__restrict__ final_T,
                                                   const uint32_t *__restrict__ last_contrib,
                                                   const float *__restrict__ dL_dimage, float *__restrict__ dmeans2d,
@@ -67,8 +68,8 @@ __global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__
   __shared__ uint32_t Lid[WAVE];
   constexpr int ORDER = KIND == BLEND_POLY2 ? 2 : (KIND == BLEND_POLY3 ? 3 : 1);
   const int ntiles = p.gx * p.gy;
-  const int tile = blockIdx.x;
-  if (tile >= ntiles) return;
+  if ((int)blockIdx.x >= ntiles) return;
+  const int tile = tile_order ? (int)min(tile_order[blockIdx.x], (uint32_t)(ntiles - 1)) : (int)blockIdx.x;
   const int lane = threadIdx.x;
   const int tx = tile % p.gx, ty = tile / p.gx;
   const int px = tx * TS + (lane & (TS - 1));
@@ -431,7 +432,8 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
 }  // namespace
 
 hipError_t launch_blend_bwd(const BlendParams &p, int64_t n, const float *means2d, const float *conic_opacity,
-                            const float *rgb, const uint32_t *vals, const uint32_t *ranges, const float *final_T,
+                            const float *rgb, const uint32_t *vals, const uint32_t *ranges,
+                            const uint32_t *tile_order, const float *final_T,
                             const uint32_t *last_contrib, const float *dL_dimage, float *dmeans2d,
                             float *dconic_opacity, float *drgb, hipStream_t s) {
   if (n > 0) {
@@ -443,19 +445,19 @@ hipError_t launch_blend_bwd(const BlendParams &p, int64_t n, const float *means2
   switch (p.blend) {
     case BLEND_EXP:
       hipLaunchKernelGGL(blend_bwd<BLEND_EXP>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
-                         final_T, last_contrib, dL_dimage, dmeans2d, dconic_opacity, drgb);
+                         tile_order, final_T, last_contrib, dL_dimage, dmeans2d, dconic_opacity, drgb);
       break;
     case BLEND_POLY1:
       hipLaunchKernelGGL(blend_bwd<BLEND_POLY1>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
-                         final_T, last_contrib, dL_dimage, dmeans2d, dconic_opacity, drgb);
+                         tile_order, final_T, last_contrib, dL_dimage, dmeans2d, dconic_opacity, drgb);
       break;
     case BLEND_POLY2:
       hipLaunchKernelGGL(blend_bwd<BLEND_POLY2>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
-                         final_T, last_contrib, dL_dimage, dmeans2d, dconic_opacity, drgb);
+                         tile_order, final_T, last_contrib, dL_dimage, dmeans2d, dconic_opacity, drgb);
       break;
     default:
       hipLaunchKernelGGL(blend_bwd<BLEND_POLY3>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
-                         final_T, last_contrib, dL_dimage, dmeans2d, dconic_opacity, drgb);
+                         tile_order, final_T, last_contrib, dL_dimage, dmeans2d, dconic_opacity, drgb);
       break;
   }
   return hipGetLastError();

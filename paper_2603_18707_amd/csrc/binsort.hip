@@ -21,8 +21,10 @@ namespace gs {
 namespace {
 
 constexpr int BS = 256;           // threads per block
-constexpr int IPT = 16;           // items per thread
-constexpr int TILE = BS * IPT;    // items per block
+constexpr int IPT = 16;           // items per thread (scans)
+constexpr int TILE = BS * IPT;    // items per block (scans)
+constexpr int RIPT = 4;           // items per thread (radix passes): more, smaller blocks fill the CUs
+constexpr int RTILE = BS * RIPT;  // items per block (radix passes)
 constexpr int RADIX = 256;        // max buckets per pass (8-bit digits)
 constexpr uint32_t BIG = 64;      // splats with more copies are expanded block-wide
 
@@ -142,11 +144,11 @@ __global__ __launch_bounds__(BS) void radix_upsweep(const uint32_t *__restrict__
   const uint32_t R = 1u << nbits, mask = R - 1u;
   for (int d = threadIdx.x; d < (BS / 64) * RADIX; d += BS) (&h[0][0])[d] = 0u;
   __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * TILE;
+  const uint64_t base = (uint64_t)blockIdx.x * RTILE;
   const int w = threadIdx.x >> 6;
   if (base < K) {
-#pragma unroll 4
-    for (int it = 0; it < IPT; ++it) {
+#pragma unroll
+    for (int it = 0; it < RIPT; ++it) {
       const uint64_t idx = base + (uint64_t)it * BS + threadIdx.x;
       if (idx < K) atomicAdd(&h[w][(keys[idx] >> shift) & mask], 1u);
     }
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(BS) void radix_downsweep(const uint32_t *__restrict
   __shared__ uint32_t wcnt[BS / 64][RADIX];
   __shared__ uint32_t woff[BS / 64][RADIX];
   const uint32_t K = item_count(kh, kd);
-  const uint64_t base = (uint64_t)blockIdx.x * TILE;
+  const uint64_t base = (uint64_t)blockIdx.x * RTILE;
   if (base >= K) return;
   const uint32_t R = 1u << nbits, mask = R - 1u;
   for (uint32_t d = threadIdx.x; d < R; d += BS) {
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(BS) void radix_downsweep(const uint32_t *__restrict
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int it = 0; it < IPT; ++it) {
+  for (int it = 0; it < RIPT; ++it) {
     const uint64_t idx = base + (uint64_t)it * BS + threadIdx.x;
     const bool valid = idx < K;
     const uint32_t key = valid ? kin[idx] : 0u;
@@ -319,6 +321,44 @@ __global__ void tile_ranges(const uint64_t *__restrict__ keys, const uint32_t *_
   if (k + 1 == K || (uint32_t)(keys[k + 1] >> 32) != t) ranges[2 * (size_t)t + 1] = (uint32_t)(k + 1);
 }
 
+// Longest-list-first dispatch order of the tiles: tiles bucketed by their list
+// length (256 linear buckets up to the longest list), heaviest bucket first.
+// A workgroup's time grows with its tile's list, so starting the long lists
+// first keeps them off the tail of the blend launch. One workgroup.
+__global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t *__restrict__ ranges, int64_t ntiles,
+                                                          uint32_t *__restrict__ order) {
+  constexpr int NB = 256;
+  __shared__ uint32_t hist[NB];
+  __shared__ uint32_t s_max;
+  if (threadIdx.x == 0) s_max = 0u;
+  for (int b = threadIdx.x; b < NB; b += blockDim.x) hist[b] = 0u;
+  __syncthreads();
+  uint32_t mx = 0;
+  for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) mx = max(mx, ranges[2 * t + 1] - ranges[2 * t]);
+  atomicMax(&s_max, mx);
+  __syncthreads();
+  const uint64_t span = (uint64_t)s_max + 1ull;
+  for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    const uint64_t len = ranges[2 * t + 1] - ranges[2 * t];
+    atomicAdd(&hist[NB - 1 - (int)(len * NB / span)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = 0; b < NB; ++b) {
+      const uint32_t c = hist[b];
+      hist[b] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    const uint64_t len = ranges[2 * t + 1] - ranges[2 * t];
+    const uint32_t pos = atomicAdd(&hist[NB - 1 - (int)(len * NB / span)], 1u);
+    if ((int64_t)pos < ntiles) order[pos] = (uint32_t)t;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // workspace
 // ---------------------------------------------------------------------------
@@ -338,7 +378,7 @@ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t carve(void *base, int64_t n, int64_t cap, Workspace *w) {
   const size_t N = (size_t)(n > 0 ? n : 1), C = (size_t)(cap > 0 ? cap : 1);
-  const size_t nbn = ceil_div((int64_t)N, TILE), nbk = ceil_div((int64_t)C, TILE);
+  const size_t nbn = ceil_div((int64_t)N, RTILE), nbk = ceil_div((int64_t)C, RTILE);
   const size_t nbmax = nbn > nbk ? nbn : nbk;
   const size_t hist_items = (size_t)RADIX * nbmax;
   const size_t parts = ceil_div((int64_t)(hist_items > N + 1 ? hist_items : N + 1), TILE) + 1;
@@ -390,7 +430,8 @@ size_t binsort_workspace_bytes(int64_t n, int64_t capacity, int32_t) { return ca
 
 hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles, int grid_w,
                           int grid_h, int64_t capacity, void *ws, size_t, uint64_t *keys, uint32_t *vals,
-                          uint32_t *ranges, int64_t *num_keys, int32_t *overflow, hipStream_t s) {
+                          uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys, int32_t *overflow,
+                          hipStream_t s) {
   Workspace w;
   carve(ws, n, capacity, &w);
   const int64_t ntiles = (int64_t)grid_w * grid_h;
@@ -398,7 +439,7 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 
-  const uint32_t nbn = n > 0 ? ceil_div(n, TILE) : 0;
+  const uint32_t nbn = n > 0 ? ceil_div(n, RTILE) : 0;
   if (n > 0) {
     // 1. splats by depth (stable, index order on ties): four 8-bit passes
     hipLaunchKernelGGL(depth_keys, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, depth, tiles, w.dk0, w.di0);
@@ -426,14 +467,18 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (capacity == 0) return hipSuccess;
+  if (capacity == 0) {
+    if (tile_order)
+      hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order);
+    return hipGetLastError();
+  }
 
   // 4. stable LSD passes over the tile digits; the last writes the 64-bit keys
   int tile_bits = 1;
   while ((1ll << tile_bits) < ntiles) ++tile_bits;
   const int passes = (tile_bits + 7) / 8;
   const int bits = (tile_bits + passes - 1) / passes;
-  const uint32_t nbk = ceil_div(capacity, TILE);
+  const uint32_t nbk = ceil_div(capacity, RTILE);
   const uint32_t *depth_bits = reinterpret_cast<const uint32_t *>(depth);
   uint32_t *ka = w.tk0, *va = w.tv0, *kb = w.tk1, *vb = w.tv1;
   for (int pass = 0; pass < passes; ++pass) {
@@ -446,6 +491,8 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
   }
   // 5. per-tile ranges
   hipLaunchKernelGGL(tile_ranges, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, keys, w.ctr, ntiles, ranges);
+  // 6. longest-first dispatch order for the blend
+  if (tile_order) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order);
   return hipGetLastError();
 }
 

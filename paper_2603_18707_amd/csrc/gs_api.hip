@@ -234,8 +234,8 @@ gs_status gs_bin_sort_workspace(int64_t n, int64_t key_capacity, int32_t num_til
 
 gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles_touched,
                       int32_t grid_w, int32_t grid_h, int64_t key_capacity, void *workspace, size_t workspace_bytes,
-                      uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *num_keys, int32_t *overflow,
-                      void *stream) {
+                      uint64_t *keys, uint32_t *vals, uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys,
+                      int32_t *overflow, void *stream) {
   if (grid_w < 1 || grid_h < 1 || (int64_t)grid_w * grid_h > (1ll << 30))
     return fail(GS_EINVAL, "tile grid %dx%d invalid", grid_w, grid_h);
   size_t need = 0;
@@ -249,7 +249,8 @@ gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const 
   if (!aligned(workspace, 256) || (rect && !aligned(rect, 16)) || (keys && !aligned(keys, 8)))
     return fail(GS_EINVAL, "workspace needs 256-byte, rect 16-byte, keys 8-byte alignment");
   return check_hip(launch_binsort(n, depth, rect, tiles_touched, grid_w, grid_h, key_capacity, workspace,
-                                  workspace_bytes, keys, vals, ranges, num_keys, overflow, (hipStream_t)stream),
+                                  workspace_bytes, keys, vals, ranges, tile_order, num_keys, overflow,
+                                  (hipStream_t)stream),
                    "gs_bin_sort launch");
 }
 
@@ -278,8 +279,9 @@ static gs_status make_blend(const gs_camera *cam, const gs_kernel *kernel, const
 
 gs_status gs_rasterize_fwd(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
                            const float *means2d, const float *conic_opacity, const float *rgb,
-                           const uint32_t *vals, const uint32_t *ranges, float *image, float *final_T,
-                           uint32_t *n_contrib, uint32_t *last_contrib, uint32_t *n_eval, void *stream) {
+                           const uint32_t *vals, const uint32_t *ranges, const uint32_t *tile_order, float *image,
+                           float *final_T, uint32_t *n_contrib, uint32_t *last_contrib, uint32_t *n_eval,
+                           void *stream) {
   BlendParams b;
   gs_status st = make_blend(cam, kernel, params, &b);
   if (st != GS_OK) return st;
@@ -290,15 +292,15 @@ gs_status gs_rasterize_fwd(const gs_camera *cam, const gs_kernel *kernel, const 
   if ((means2d && !aligned(means2d, 8)) || (conic_opacity && !aligned(conic_opacity, 16)))
     return fail(GS_EINVAL, "means2d needs 8-byte, conic_opacity 16-byte alignment");
   BlendOut o{image, final_T, n_contrib, last_contrib, n_eval};
-  return check_hip(launch_blend_fwd(b, means2d, conic_opacity, rgb, vals, ranges, o, (hipStream_t)stream),
+  return check_hip(launch_blend_fwd(b, means2d, conic_opacity, rgb, vals, ranges, tile_order, o, (hipStream_t)stream),
                    "gs_rasterize_fwd launch");
 }
 
 gs_status gs_rasterize_bwd(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
                            const float *means2d, const float *conic_opacity, const float *rgb,
-                           const uint32_t *vals, const uint32_t *ranges, const float *final_T,
-                           const uint32_t *last_contrib, const float *dL_dimage, float *dL_dmeans2d,
-                           float *dL_dconic_opacity, float *dL_drgb, void *stream) {
+                           const uint32_t *vals, const uint32_t *ranges, const uint32_t *tile_order,
+                           const float *final_T, const uint32_t *last_contrib, const float *dL_dimage,
+                           float *dL_dmeans2d, float *dL_dconic_opacity, float *dL_drgb, void *stream) {
   BlendParams b;
   gs_status st = make_blend(cam, kernel, params, &b);
   if (st != GS_OK) return st;
@@ -310,7 +312,7 @@ gs_status gs_rasterize_bwd(const gs_camera *cam, const gs_kernel *kernel, const 
   if ((means2d && !aligned(means2d, 8)) || (conic_opacity && !aligned(conic_opacity, 16)) ||
       (dL_dmeans2d && !aligned(dL_dmeans2d, 8)) || (dL_dconic_opacity && !aligned(dL_dconic_opacity, 16)))
     return fail(GS_EINVAL, "2D records need 8 (means) and 16 (conic_opacity) byte alignment");
-  return check_hip(launch_blend_bwd(b, n, means2d, conic_opacity, rgb, vals, ranges, final_T, last_contrib,
+  return check_hip(launch_blend_bwd(b, n, means2d, conic_opacity, rgb, vals, ranges, tile_order, final_T, last_contrib,
                                     dL_dimage, dL_dmeans2d, dL_dconic_opacity, dL_drgb, (hipStream_t)stream),
                    "gs_rasterize_bwd launch");
 }
@@ -351,6 +353,112 @@ gs_status gs_preprocess_bwd(const gs_camera *cam, const gs_kernel *kernel, const
                                          dL_dconic_opacity, dL_drgb, dL_dmeans3d, dL_dscales, dL_dquats,
                                          dL_dopacities, dL_dsh, (hipStream_t)stream),
                    "gs_preprocess_bwd launch");
+}
+
+static gs_status batch_check(const gs_scene *scenes, int32_t num_scenes, const gs_view *views, int32_t num_views,
+                             int64_t key_capacity, int64_t *pairs, int32_t *gw, int32_t *gh) {
+  if (!scenes || !views) return fail(GS_EINVAL, "NULL scenes or views");
+  if (num_scenes < 1 || num_scenes > 16) return fail(GS_EUNSUPPORTED, "num_scenes %d outside 1..16", num_scenes);
+  if (num_views < 1 || num_views > 4096) return fail(GS_EUNSUPPORTED, "num_views %d outside 1..4096", num_views);
+  if (key_capacity < 0 || key_capacity >= (1ll << 32)) return fail(GS_EINVAL, "key_capacity outside [0, 2^32)");
+  for (int i = 0; i < num_scenes; ++i) {
+    const gs_scene &sc = scenes[i];
+    if (sc.n < 0 || sc.n >= (1ll << 31)) return fail(GS_EINVAL, "scene %d: n outside [0, 2^31)", i);
+    if (sc.sh_degree < 0 || sc.sh_degree > 3) return fail(GS_EINVAL, "scene %d: sh_degree outside 0..3", i);
+    if (sc.sh_degree != scenes[0].sh_degree) return fail(GS_EUNSUPPORTED, "scenes must share one sh_degree");
+    if (sc.reserved != 0) return fail(GS_EINVAL, "scene %d: reserved must be 0", i);
+    if (sc.n > 0 && (!sc.means3d || !sc.scales || !sc.quats || !sc.opacities || !sc.sh))
+      return fail(GS_EINVAL, "scene %d: NULL array", i);
+  }
+  int64_t p = 0, rows = 0;
+  int32_t cols = 1;
+  for (int v = 0; v < num_views; ++v) {
+    gs_status st = check_camera(&views[v].cam);
+    if (st != GS_OK) return st;
+    if (views[v].scene < 0 || views[v].scene >= num_scenes) return fail(GS_EINVAL, "view %d: scene index", v);
+    if (views[v].reserved != 0) return fail(GS_EINVAL, "view %d: reserved must be 0", v);
+    p += (scenes[views[v].scene].n + 63) / 64 * 64;
+    rows += (views[v].cam.height + 15) / 16;
+    const int32_t gxv = (views[v].cam.width + 15) / 16;
+    cols = gxv > cols ? gxv : cols;
+  }
+  if (p >= (1ll << 31)) return fail(GS_EUNSUPPORTED, "%lld pairs: more than 2^31", (long long)p);
+  if (rows * cols > (1ll << 30)) return fail(GS_EUNSUPPORTED, "virtual tile grid too large");
+  *pairs = p;
+  *gw = cols;
+  *gh = (int32_t)rows;
+  return GS_OK;
+}
+
+gs_status gs_batch_layout(const gs_scene *scenes, int32_t num_scenes, const gs_view *views, int32_t num_views,
+                          int64_t key_capacity, int64_t *num_pairs, int32_t *grid_w, int32_t *grid_h,
+                          size_t *workspace_bytes) {
+  if (!num_pairs || !grid_w || !grid_h || !workspace_bytes) return fail(GS_EINVAL, "NULL output");
+  int64_t p;
+  int32_t gw, gh;
+  gs_status st = batch_check(scenes, num_scenes, views, num_views, key_capacity, &p, &gw, &gh);
+  if (st != GS_OK) return st;
+  *num_pairs = p;
+  *grid_w = gw;
+  *grid_h = gh;
+  *workspace_bytes = batch_workspace_bytes(num_views, p, gw, gh, key_capacity);
+  return GS_OK;
+}
+
+gs_status gs_render_batched(const gs_kernel *kernel, const gs_params *params, const gs_scene *scenes,
+                            int32_t num_scenes, const gs_view *views, const gs_view *views_device,
+                            int32_t num_views, int64_t key_capacity, int32_t workgroups, void *workspace,
+                            size_t workspace_bytes, float *images, int64_t images_len, float *final_T,
+                            uint32_t *n_contrib, uint32_t *last_contrib, int64_t planes_len, int64_t *num_keys,
+                            int32_t *overflow, void *stream) {
+  gs_status st;
+  if ((st = check_params(params)) != GS_OK) return st;
+  Resolved r;
+  if ((st = resolve_kernel(kernel, &r)) != GS_OK) return st;
+  int64_t pairs;
+  int32_t gw, gh;
+  if ((st = batch_check(scenes, num_scenes, views, num_views, key_capacity, &pairs, &gw, &gh)) != GS_OK) return st;
+  if (!views_device || !workspace || !images || !final_T || !n_contrib || !last_contrib || !num_keys || !overflow)
+    return fail(GS_EINVAL, "NULL argument");
+  if (workgroups < 0 || workgroups > 65536) return fail(GS_EINVAL, "workgroups outside 0..65536");
+  const size_t need = batch_workspace_bytes(num_views, pairs, gw, gh, key_capacity);
+  if (workspace_bytes < need) return fail(GS_EINVAL, "workspace of %zu bytes is smaller than the %zu needed",
+                                          workspace_bytes, need);
+  if (!aligned(workspace, 256)) return fail(GS_EINVAL, "workspace needs 256-byte alignment");
+  for (int v = 0; v < num_views; ++v) {
+    const int64_t WH = (int64_t)views[v].cam.width * views[v].cam.height;
+    if (views[v].image_offset < 0 || views[v].image_offset + 3 * WH > images_len || views[v].pixel_offset < 0 ||
+        views[v].pixel_offset + WH > planes_len)
+      return fail(GS_EINVAL, "view %d: output range outside the buffers", v);
+  }
+  PreParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.radius_mode = r.radius_mode;
+  p.order = r.order;
+  p.sh_degree = scenes[0].sh_degree;
+  p.tile = params->tile;
+  for (int i = 0; i < 4; ++i) p.c[i] = r.c[i];
+  p.k_universal = std::sqrt(r.x0);
+  p.eps = params->eps;
+  p.aa_v = params->aa_v;
+  p.near_z = params->near_z;
+  p.pad = params->radius_pad;
+  BlendParams b;
+  std::memset(&b, 0, sizeof(b));
+  b.n = (uint32_t)pairs;
+  b.blend = blend_kind(r);
+  for (int i = 0; i < 4; ++i) b.c[i] = (float)r.c[i];
+  b.x0 = (float)r.x0;
+  b.eps = params->eps;
+  b.log2_eps = std::log2(params->eps);
+  b.alpha_max = params->alpha_max;
+  b.t_min = params->t_min;
+  for (int i = 0; i < 3; ++i) b.bg[i] = params->bg[i];
+  b.threads = params->blend_threads ? params->blend_threads : 256;
+  return check_hip(launch_batch(p, b, scenes, num_scenes, views_device, num_views, pairs, gw, gh, key_capacity,
+                                workgroups, workspace, images, images_len, final_T, n_contrib, last_contrib,
+                                planes_len, num_keys, overflow, (hipStream_t)stream),
+                   "gs_render_batched launch");
 }
 
 }  // extern "C"

@@ -55,7 +55,26 @@ struct PreOut {
   uint32_t *tiles;
 };
 
-void make_cam(const gs_camera *cam, int tile, CamD *out);
+// camera in double precision, with the Jacobian clamp limits and the centre
+__host__ __device__ inline void make_cam(const gs_camera *c, int tile, CamD *o) {
+  for (int r = 0; r < 3; ++r) {
+    for (int k = 0; k < 3; ++k) o->R[3 * r + k] = (double)c->viewmat[4 * r + k];
+    o->t[r] = (double)c->viewmat[4 * r + 3];
+  }
+  o->fx = c->fx;
+  o->fy = c->fy;
+  o->cx = c->cx;
+  o->cy = c->cy;
+  o->limx = 1.3 * (c->width / (2.0 * o->fx));
+  o->limy = 1.3 * (c->height / (2.0 * o->fy));
+  for (int i = 0; i < 3; ++i)
+    o->campos[i] = -(o->R[i] * o->t[0] + o->R[3 + i] * o->t[1] + o->R[6 + i] * o->t[2]);
+  o->W = c->width;
+  o->H = c->height;
+  o->gx = (c->width + tile - 1) / tile;
+  o->gy = (c->height + tile - 1) / tile;
+}
+
 hipError_t launch_preprocess(const PreParams &p, int64_t n, const float *means3d, const float *scales,
                              const float *quats, const float *opac, const float *sh, PreOut out,
                              hipStream_t s);
@@ -66,8 +85,8 @@ hipError_t launch_preprocess(const PreParams &p, int64_t n, const float *means3d
 size_t binsort_workspace_bytes(int64_t n, int64_t capacity, int32_t num_tiles);
 hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles,
                           int grid_w, int grid_h, int64_t capacity, void *ws, size_t ws_bytes, uint64_t *keys,
-                          uint32_t *vals, uint32_t *ranges, int64_t *num_keys, int32_t *overflow,
-                          hipStream_t s);
+                          uint32_t *vals, uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys,
+                          int32_t *overflow, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // blending
@@ -91,11 +110,12 @@ struct BlendOut {
 
 int blend_kind(const Resolved &r);
 hipError_t launch_blend_fwd(const BlendParams &p, const float *means2d, const float *conic_opacity,
-                            const float *rgb, const uint32_t *vals, const uint32_t *ranges, BlendOut out,
-                            hipStream_t s);
+                            const float *rgb, const uint32_t *vals, const uint32_t *ranges,
+                            const uint32_t *tile_order, BlendOut out, hipStream_t s);
 
 hipError_t launch_blend_bwd(const BlendParams &p, int64_t n, const float *means2d, const float *conic_opacity,
                             const float *rgb, const uint32_t *vals, const uint32_t *ranges,
+                            const uint32_t *tile_order,
                             const float *final_T, const uint32_t *last_contrib, const float *dL_dimage,
                             float *dmeans2d, float *dconic_opacity, float *drgb, hipStream_t s);
 
@@ -104,6 +124,14 @@ hipError_t launch_preprocess_bwd(const PreParams &p, int64_t n, const float *mea
                                  const float *dmeans2d, const float *dconic_opacity, const float *drgb,
                                  float *dmeans3d, float *dscales, float *dquats, float *dopac, float *dsh,
                                  hipStream_t s);
+
+// batched rendering
+size_t batch_workspace_bytes(int nviews, int64_t pairs, int gw, int gh, int64_t capacity);
+hipError_t launch_batch(const PreParams &pre, const BlendParams &blend, const gs_scene *scenes, int nscenes,
+                        const gs_view *views_dev, int nviews, int64_t pairs, int gw, int gh, int64_t capacity,
+                        int workgroups, void *ws, float *images, int64_t images_len, float *final_T,
+                        uint32_t *n_contrib, uint32_t *last_contrib, int64_t planes_len, int64_t *num_keys,
+                        int32_t *overflow, hipStream_t s);
 
 inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 

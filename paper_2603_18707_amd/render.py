@@ -94,10 +94,11 @@ class Rasterizer:
         out = dict(keys=self._buf("keys", (max(cap, 1),), torch.int64),
                    vals=self._buf("vals", (max(cap, 1),), torch.int32),
                    ranges=self._buf("ranges", (gw * gh, 2), torch.int32),
+                   tile_order=self._buf("tile_order", (gw * gh,), torch.int32),
                    num_keys=self._buf("num_keys", (1,), torch.int64),
                    overflow=self._buf("overflow", (1,), torch.int32))
         L.gs_bin_sort(n, proj["depth"], proj["rect"], proj["tiles"], gw, gh, cap, ws, ws.numel(), out["keys"],
-                      out["vals"], out["ranges"], out["num_keys"], out["overflow"], stream)
+                      out["vals"], out["ranges"], out["tile_order"], out["num_keys"], out["overflow"], stream)
         out["capacity"] = cap
         return out
 
@@ -120,7 +121,8 @@ class Rasterizer:
                    last_contrib=self._buf("last_contrib", (H, W), torch.int32),
                    n_eval=self._buf("n_eval", (H, W), torch.int32) if want_eval else None)
         L.gs_rasterize_fwd(L.make_camera(cam), self.kernel, self.params, proj["n"], proj["means2d"],
-                           proj["conic_opacity"], proj["rgb"], binned["vals"], binned["ranges"], out["image"],
+                           proj["conic_opacity"], proj["rgb"], binned["vals"], binned["ranges"],
+                           binned.get("tile_order"), out["image"],
                            out["final_T"], out["n_contrib"], out["last_contrib"], out["n_eval"], stream)
         return out
 

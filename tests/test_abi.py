@@ -100,12 +100,12 @@ def test_device_calls_reject_bad_arguments_on_host():
     # n = 0 is a no-op that enqueues nothing
     L.gs_preprocess(cam, k, p, 0, *null8, 0, *out6)
     # bin sort: workspace too small, capacity too large, grid invalid
-    _expect(L.GS_EINVAL, L.gs_bin_sort, 10, 256, 256, 256, 4, 4, 100, 256, 10, 256, 256, 256, 256, 256)
+    _expect(L.GS_EINVAL, L.gs_bin_sort, 10, 256, 256, 256, 4, 4, 100, 256, 10, 256, 256, 256, None, 256, 256)
     _expect(L.GS_EINVAL, L.gs_bin_sort_workspace, 10, 1 << 33, 16)
-    _expect(L.GS_EINVAL, L.gs_bin_sort, 10, 256, 256, 256, 0, 4, 100, 256, 1 << 30, 256, 256, 256, 256, 256)
+    _expect(L.GS_EINVAL, L.gs_bin_sort, 10, 256, 256, 256, 0, 4, 100, 256, 1 << 30, 256, 256, 256, None, 256, 256)
     # rasterize: NULL outputs
-    _expect(L.GS_EINVAL, L.gs_rasterize_fwd, cam, k, p, 0, None, None, None, None, None, None, None, None, None)
-    msg = _expect(L.GS_EINVAL, L.gs_rasterize_bwd, cam, k, p, 5, None, None, None, None, 256, 256, 256, 256,
+    _expect(L.GS_EINVAL, L.gs_rasterize_fwd, cam, k, p, 0, None, None, None, None, None, None, None, None, None, None)
+    msg = _expect(L.GS_EINVAL, L.gs_rasterize_bwd, cam, k, p, 5, None, None, None, None, 256, None, 256, 256, 256,
                   None, None, None)
     assert "NULL" in msg
 
@@ -115,3 +115,49 @@ def test_workspace_grows_with_sizes():
     b = L.gs_bin_sort_workspace(1000, 20000, 64)
     c = L.gs_bin_sort_workspace(2000, 10000, 64)
     assert 0 < a < b and a < c
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the public structs have the header's sizes and offsets (gcc)."""
+    src = tmp_path / "sz.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "gs.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gs_kernel), sizeof(gs_params), sizeof(gs_camera),
+         sizeof(gs_scene), sizeof(gs_view), offsetof(gs_view, image_offset), offsetof(gs_params, blend_threads),
+         offsetof(gs_kernel, coeffs));
+  return 0;
+}
+""")
+    import subprocess
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(L.GsKernel), ctypes.sizeof(L.GsParams), ctypes.sizeof(L.GsCamera), ctypes.sizeof(L.GsScene),
+            ctypes.sizeof(L.GsView), L.GsView.image_offset.offset, L.GsParams.blend_threads.offset,
+            L.GsKernel.coeffs.offset]
+    assert got == want
+
+
+def test_batch_layout_validation():
+    scenes = (L.GsScene * 2)()
+    scenes[0].n, scenes[1].n = 1000, 70
+    for s in scenes:
+        s.means3d = s.scales = s.quats = s.opacities = s.sh = 4096
+        s.sh_degree = 3
+    views = (L.GsView * 3)()
+    for i, (W, H, sc) in enumerate([(128, 64, 0), (33, 17, 1), (640, 360, 0)]):
+        views[i].cam = L.make_camera(type("C", (), dict(viewmat=np.eye(4, dtype=np.float32), fx=100.0, fy=100.0,
+                                                        cx=W / 2, cy=H / 2, width=W, height=H)))
+        views[i].scene = sc
+    pairs, gw, gh, ws = L.gs_batch_layout(scenes, views, 10000)
+    assert pairs == 1024 + 128 + 1024          # each view padded to a multiple of 64 splats
+    assert gw == 40 and gh == 4 + 2 + 23       # widest view's columns, all views' rows stacked
+    assert ws > 0
+    views[1].scene = 5
+    _expect(L.GS_EINVAL, L.gs_batch_layout, scenes, views, 10000)
+    views[1].scene = 1
+    scenes[1].sh_degree = 2
+    _expect(L.GS_EUNSUPPORTED, L.gs_batch_layout, scenes, views, 10000)

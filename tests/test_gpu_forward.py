@@ -49,7 +49,7 @@ def _check_projection(g, o, rect_exempt):
     scale = np.abs(o["conic"][vis]).max(axis=1, keepdims=True)
     assert np.all(np.abs(gc[vis, :3] - o["conic"][vis]) <= 1e-6 * scale + 1e-30)
     assert np.allclose(gc[vis, 3], o["opac"][vis], rtol=1e-6, atol=1e-9)
-    assert np.allclose(gr[vis], o["rgb"][vis], rtol=1e-6, atol=1e-6)
+    assert np.allclose(gr[vis], o["rgb"][vis], rtol=1e-6, atol=4e-6)  # colour is evaluated in float32
 
 
 def _check_binning(g, o, gx, gy, exempt):

@@ -72,11 +72,14 @@ class BatchRenderer:
     def render_fit(self):
         """Eager render that grows the key capacity until nothing overflows."""
         self.render()
-        if int(self.overflow.item()):
+        flag = int(self.overflow.item())
+        if flag & 1:
             self.capacity = int(int(self.num_keys.item()) * 1.05) + 4096
             self._layout()
             self.render()
-            assert not int(self.overflow.item())
+            flag = int(self.overflow.item())
+        if flag:
+            raise RuntimeError(f"gs_render_batched reported overflow flags {flag}")
         return int(self.num_keys.item())
 
     def capture(self):

@@ -4,33 +4,58 @@
 // The sort is organised around the key's structure. An LSD radix sort
 // processes the low digits first, and the 32 low bits (the depth) are the
 // same for every copy of a splat. So the depth passes run once per splat
-// (N items) instead of once per copy (K items, K ~ 3N at 1080p): splats are
-// sorted by depth stably in index order, copies are emitted in that order
-// (row-major tiles within each splat), and the remaining tile digits are
-// sorted stably over the copies. The result is exactly the stable sort of
-// the copies emitted in splat-index order, because within one tile each
+// (N items) instead of once per copy (K items, K ~ 2-3 N at 1080p): splats
+// are sorted by depth stably in index order, copies are emitted in that
+// order (row-major tiles within each splat), and the remaining tile digits
+// are sorted stably over the copies. The result is exactly the stable sort
+// of the copies emitted in splat-index order, because within one tile each
 // splat has at most one copy.
 //
-// Every kernel sized by the key count reads it from device memory, and grids
-// are sized by the key capacity, so the whole stage runs without a host
-// round trip (and can be captured in a graph).
+// A radix pass is three kernels and no workgroup ever waits on another (a
+// hand-off between workgroups costs ~0.5 us through memory, and device
+// atomics on scattered addresses cost more than the pass itself):
+//  * count_pass: the key array is cut into partitions of SPART items;
+//    C[d][p] = items of digit d in partition p (LDS histogram, plain stores).
+//  * scan_rows: one workgroup per digit turns its row into output offsets:
+//    the items of smaller digits (from digit totals known in advance) plus
+//    the row's exclusive prefix.
+//  * scatter_pass: each partition ranks its items stably (per-wave ballot
+//    matching of the digit, waves in index order) and writes them at
+//    C[d][p] + rank.
+// Digit totals do not depend on the order, so one read of the depths gives
+// them for all four depth passes (with the first pass's counts), and the
+// emission kernel gives them for the tile passes; they are accumulated in 8
+// striped copies (by workgroup) so no address sees more than an eighth of the
+// workgroups. The tile passes carry each copy's depth bits with it, so the
+// last one writes the 64-bit keys without gathering the depths.
+//
+// Every kernel sized by the key count reads it from device memory and grids
+// are sized by the key capacity, so the stage runs without a host round trip
+// (and can be captured in a graph).
 #include "gs_internal.h"
 
 namespace gs {
 
 namespace {
 
-constexpr int BS = 256;           // threads per block
-constexpr int IPT = 16;           // items per thread (scans)
-constexpr int TILE = BS * IPT;    // items per block (scans)
-constexpr int RIPT = 4;           // items per thread (radix passes): more, smaller blocks fill the CUs
-constexpr int RTILE = BS * RIPT;  // items per block (radix passes)
-constexpr int RADIX = 256;        // max buckets per pass (8-bit digits)
-constexpr uint32_t BIG = 64;      // splats with more copies are expanded block-wide
+constexpr int BS = 256;                 // threads per workgroup
+constexpr int SIPT = 4;                 // items per thread in a sort partition
+constexpr int SPART = BS * SIPT;        // items per sort partition
+constexpr int EIPT = 4;                 // splats per thread in an emission partition
+constexpr int EPART = BS * EIPT;        // splats per emission partition
+static_assert(EPART == 1024, "the emission's binary search takes 10 steps");
+constexpr int RADIX = 256;              // max buckets per pass (8-bit digits)
+constexpr int DEPTH_PASSES = 4;
+constexpr int MAX_TILE_PASSES = 4;      // tile ids < 2^30 need at most four digits of <= 8 bits
+constexpr int STRIPES = 8;              // copies of the digit totals
 
-// ---------------------------------------------------------------------------
-// scans
-// ---------------------------------------------------------------------------
+enum : int { CTR_KEYS = 0, CTR_SLOTS = 16 };
+
+// totals[stripe][pass][digit]
+__device__ inline uint32_t *total_at(uint32_t *tot, int stripe, int pass, int d) {
+  return tot + ((size_t)stripe * MAX_TILE_PASSES + pass) * RADIX + d;
+}
+
 template <typename T>
 __device__ inline T wave_inclusive(T v) {
   const int lane = threadIdx.x & 63;
@@ -42,7 +67,7 @@ __device__ inline T wave_inclusive(T v) {
   return v;
 }
 
-// exclusive scan over the 256 threads of a block; also returns the block total
+// exclusive scan over the 256 threads of a workgroup; also returns the total
 template <typename T>
 __device__ inline T block_exclusive(T v, T &total) {
   __shared__ T wsum[BS / 64];
@@ -62,257 +87,349 @@ __device__ inline T block_exclusive(T v, T &total) {
   return off + inc - v;
 }
 
-template <typename TIn, typename TOut>
-__global__ __launch_bounds__(BS) void scan_reduce(const TIn *__restrict__ in, int64_t m, TOut *partials) {
-  const int64_t base = (int64_t)blockIdx.x * TILE + (int64_t)threadIdx.x * IPT;
-  TOut s = 0;
-#pragma unroll
-  for (int j = 0; j < IPT; ++j)
-    if (base + j < m) s += (TOut)in[base + j];
-  TOut tot;
-  block_exclusive(s, tot);
-  if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+// visible splats have depth >= near_z > 0, where float bits order like the
+// values; splats without tiles sort last (they emit nothing)
+__device__ inline uint32_t depth_key(const float *depth, const uint32_t *tiles, uint32_t i) {
+  return tiles[i] ? __float_as_uint(depth[i]) : 0xFFFFFFFFu;
 }
 
-// single block: exclusive scan of nb partials in place; *total = their sum
-template <typename T>
-__global__ __launch_bounds__(BS) void scan_partials(T *partials, int64_t nb, T *total) {
-  T carry = 0;
-  for (int64_t base = 0; base < nb; base += (int64_t)BS * IPT) {
-    const int64_t b0 = base + (int64_t)threadIdx.x * IPT;
-    T loc[IPT];
-    T s = 0;
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-      loc[j] = (b0 + j < nb) ? partials[b0 + j] : (T)0;
-      s += loc[j];
-    }
-    T tot;
-    T off = block_exclusive(s, tot) + carry;
-#pragma unroll
-    for (int j = 0; j < IPT; ++j) {
-      if (b0 + j < nb) partials[b0 + j] = off;
-      off += loc[j];
-    }
-    carry += tot;
-  }
-  if (threadIdx.x == 0 && total) *total = carry;
-}
-
-template <typename TIn, typename TOut>
-__global__ __launch_bounds__(BS) void scan_down(const TIn *__restrict__ in, int64_t m,
-                                                const TOut *__restrict__ partials, TOut *__restrict__ out) {
-  const int64_t base = (int64_t)blockIdx.x * TILE + (int64_t)threadIdx.x * IPT;
-  TOut loc[IPT];
-  TOut s = 0;
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    loc[j] = (base + j < m) ? (TOut)in[base + j] : (TOut)0;
-    s += loc[j];
-  }
-  TOut tot;
-  TOut off = block_exclusive(s, tot) + partials[blockIdx.x];
-#pragma unroll
-  for (int j = 0; j < IPT; ++j) {
-    if (base + j < m) out[base + j] = off;
-    off += loc[j];
-  }
-}
-
-// exclusive scan of m items; out[m] receives the total when write_total
-template <typename TIn, typename TOut>
-hipError_t exclusive_scan(const TIn *in, int64_t m, TOut *out, TOut *partials, bool write_total, hipStream_t s) {
-  if (m == 0) return hipSuccess;  // callers only scan non-empty arrays
-  const unsigned nb = ceil_div(m, TILE);
-  hipLaunchKernelGGL((scan_reduce<TIn, TOut>), dim3(nb), dim3(BS), 0, s, in, m, partials);
-  hipLaunchKernelGGL((scan_partials<TOut>), dim3(1), dim3(BS), 0, s, partials, (int64_t)nb,
-                     write_total ? out + m : (TOut *)nullptr);
-  hipLaunchKernelGGL((scan_down<TIn, TOut>), dim3(nb), dim3(BS), 0, s, in, m, partials, out);
-  return hipGetLastError();
+__device__ inline uint32_t item_count(const uint32_t *count_dev, uint32_t count) {
+  return count_dev ? *count_dev : count;
 }
 
 // ---------------------------------------------------------------------------
-// radix sort passes over (uint32 key, uint32 value)
+// state reset: totals, counters, ranges, outputs
 // ---------------------------------------------------------------------------
-__device__ inline uint32_t item_count(uint32_t kh, const uint32_t *kd) { return kd ? *kd : kh; }
+__global__ __launch_bounds__(BS) void clear_state(uint4 *__restrict__ z, size_t nz16, uint32_t *__restrict__ ranges,
+                                                  size_t nr, int64_t *num_keys, int32_t *overflow) {
+  const size_t i = (size_t)blockIdx.x * BS + threadIdx.x, stride = (size_t)gridDim.x * BS;
+  for (size_t j = i; j < nz16; j += stride) z[j] = make_uint4(0u, 0u, 0u, 0u);
+  for (size_t j = i; j < nr; j += stride) ranges[j] = 0u;
+  if (i == 0) {
+    *num_keys = 0;
+    *overflow = 0;
+  }
+}
 
-__global__ __launch_bounds__(BS) void radix_upsweep(const uint32_t *__restrict__ keys, uint32_t kh,
-                                                    const uint32_t *kd, int shift, int nbits,
-                                                    uint32_t *__restrict__ hist, uint32_t nb) {
-  __shared__ uint32_t h[BS / 64][RADIX];
-  const uint32_t K = item_count(kh, kd);
-  const uint32_t R = 1u << nbits, mask = R - 1u;
-  for (int d = threadIdx.x; d < (BS / 64) * RADIX; d += BS) (&h[0][0])[d] = 0u;
+// ---------------------------------------------------------------------------
+// depth keys: counts of the first pass per partition, totals of all passes
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS) void depth_count(uint32_t n, const float *__restrict__ depth,
+                                                  const uint32_t *__restrict__ tiles, uint32_t *__restrict__ c0,
+                                                  size_t c_stride, uint32_t *__restrict__ tot) {
+  __shared__ uint32_t h[BS / 64][DEPTH_PASSES * RADIX];
+  for (int j = threadIdx.x; j < (BS / 64) * DEPTH_PASSES * RADIX; j += BS) (&h[0][0])[j] = 0u;
   __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * RTILE;
   const int w = threadIdx.x >> 6;
-  if (base < K) {
+  const uint64_t base = (uint64_t)blockIdx.x * SPART + threadIdx.x;
 #pragma unroll
-    for (int it = 0; it < RIPT; ++it) {
-      const uint64_t idx = base + (uint64_t)it * BS + threadIdx.x;
-      if (idx < K) atomicAdd(&h[w][(keys[idx] >> shift) & mask], 1u);
+  for (int r = 0; r < SIPT; ++r) {
+    const uint64_t i = base + (uint64_t)r * BS;
+    if (i < n) {
+      const uint32_t k = depth_key(depth, tiles, (uint32_t)i);
+#pragma unroll
+      for (int p = 0; p < DEPTH_PASSES; ++p) atomicAdd(&h[w][p * RADIX + ((k >> (8 * p)) & 255u)], 1u);
     }
   }
   __syncthreads();
-  for (uint32_t d = threadIdx.x; d < R; d += BS)
-    hist[(size_t)d * nb + blockIdx.x] = h[0][d] + h[1][d] + h[2][d] + h[3][d];
+  const int stripe = blockIdx.x % STRIPES;
+  for (int j = threadIdx.x; j < DEPTH_PASSES * RADIX; j += BS) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int ww = 0; ww < BS / 64; ++ww) v += h[ww][j];
+    const int p = j / RADIX, d = j % RADIX;
+    if (p == 0) c0[(size_t)d * c_stride + blockIdx.x] = v;
+    if (v) atomicAdd(total_at(tot, stripe, p, d), v);
+  }
 }
 
-// Stable scatter: within a block, items are ranked in index order (rounds of
-// 256 consecutive items; inside a round, wave by wave and lane by lane). The
-// per-wave rank among equal digits comes from matching the digit bit by bit
-// with ballots. FINAL writes the 64-bit output key (key << 32 | depth bits of
-// the value's splat) instead of the 32-bit key.
-template <bool FINAL>
-__global__ __launch_bounds__(BS) void radix_downsweep(const uint32_t *__restrict__ kin,
-                                                      const uint32_t *__restrict__ vin, uint32_t kh,
-                                                      const uint32_t *kd, int shift, int nbits,
-                                                      const uint32_t *__restrict__ hist, uint32_t nb,
-                                                      uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                      uint64_t *__restrict__ k64out,
-                                                      const uint32_t *__restrict__ depth_bits) {
-  __shared__ uint32_t run[RADIX];
-  __shared__ uint32_t wcnt[BS / 64][RADIX];
-  __shared__ uint32_t woff[BS / 64][RADIX];
-  const uint32_t K = item_count(kh, kd);
-  const uint64_t base = (uint64_t)blockIdx.x * RTILE;
-  if (base >= K) return;
-  const uint32_t R = 1u << nbits, mask = R - 1u;
-  for (uint32_t d = threadIdx.x; d < R; d += BS) {
-    run[d] = hist[(size_t)d * nb + blockIdx.x];
+// ---------------------------------------------------------------------------
+// one row per digit: C[d][p] <- items of smaller digits + items of digit d in
+// partitions before p
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS) void scan_rows(uint32_t *__restrict__ C, size_t c_stride,
+                                                const uint32_t *count_dev, uint32_t count,
+                                                const uint32_t *__restrict__ tot, int pass) {
+  const uint32_t K = item_count(count_dev, count);
+  const uint32_t P = (uint32_t)(((uint64_t)K + SPART - 1) / SPART);
+  const int d = blockIdx.x;
+  uint32_t mine = 0;
+  if ((int)threadIdx.x < d) {
 #pragma unroll
-    for (int w = 0; w < BS / 64; ++w) wcnt[w][d] = 0u;
+    for (int s = 0; s < STRIPES; ++s) mine += tot[((size_t)s * MAX_TILE_PASSES + pass) * RADIX + threadIdx.x];
+  }
+  uint32_t base;
+  block_exclusive<uint32_t>(mine, base);
+  uint32_t *row = C + (size_t)d * c_stride;
+  uint32_t carry = base;
+  for (uint32_t c0 = 0; c0 < P; c0 += BS * 4) {
+    const uint32_t b = c0 + threadIdx.x * 4;
+    uint32_t v[4], s = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      v[j] = b + j < P ? row[b + j] : 0u;
+      s += v[j];
+    }
+    uint32_t chunk;
+    uint32_t off = block_exclusive<uint32_t>(s, chunk) + carry;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (b + j < P) row[b + j] = off;
+      off += v[j];
+    }
+    carry += chunk;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C[d][p]: items of digit d in partition p
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS) void count_pass(const uint32_t *__restrict__ keys, const uint32_t *count_dev,
+                                                 uint32_t count, int shift, int nbits, uint32_t *__restrict__ C,
+                                                 size_t c_stride) {
+  __shared__ uint32_t h[BS / 64][RADIX];
+  const uint32_t K = item_count(count_dev, count);
+  const uint32_t nparts = (uint32_t)(((uint64_t)K + SPART - 1) / SPART);
+  if (blockIdx.x >= nparts) return;  // capacity-sized grids
+  for (int j = threadIdx.x; j < (BS / 64) * RADIX; j += BS) (&h[0][0])[j] = 0u;
+  __syncthreads();
+  const uint32_t R = 1u << nbits, mask = R - 1u;
+  const int w = threadIdx.x >> 6;
+  const uint64_t base = (uint64_t)blockIdx.x * SPART + threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < SIPT; ++r) {
+    const uint64_t i = base + (uint64_t)r * BS;
+    if (i < K) atomicAdd(&h[w][(keys[i] >> shift) & mask], 1u);
   }
   __syncthreads();
+  for (uint32_t d = threadIdx.x; d < R; d += BS) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int ww = 0; ww < BS / 64; ++ww) v += h[ww][d];
+    C[(size_t)d * c_stride + blockIdx.x] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// one stable radix pass (uint32 key, uint32 value)
+// ---------------------------------------------------------------------------
+enum { SRC_KV = 0, SRC_DEPTH = 1 };                  // where the items come from
+enum { DST_KV = 0, DST_ORDER = 1, DST_KEYS = 2 };    // what the pass writes
+
+struct Pass {
+  const uint32_t *kin, *vin;             // SRC_KV
+  const float *depth;                    // SRC_DEPTH keys; DST_KEYS low key words
+  const uint32_t *tiles;                 // SRC_DEPTH keys; DST_ORDER copy counts
+  uint32_t n;                            // splat count (bound of the values)
+  const uint32_t *count_dev;             // item count in device memory, or NULL ...
+  uint32_t count;                        // ... for this host value
+  int shift, nbits;                      // this pass's digit
+  const uint32_t *C;                     // [digit][partition] output offsets (scan_rows)
+  size_t c_stride;
+  const uint32_t *bin;                   // depth bits carried with each item (tile passes), or NULL
+  uint32_t *kout, *vout, *bout;          // DST_KV; DST_ORDER / DST_KEYS write vout
+  uint32_t *cnt_out;                     // DST_ORDER: tiles[value] at the output position
+  uint64_t *k64out;                      // DST_KEYS: (key << 32) | the carried depth bits
+};
+
+// Items of a partition are ranked in index order: wave w owns a contiguous
+// run of 64 * SIPT items, taken 64 at a time; inside a wave the rank among
+// equal digits comes from matching the digit bit by bit with ballots, plus a
+// per-wave running count per digit in LDS.
+template <int SRC, int DST>
+__global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
+  __shared__ uint32_t wc[BS / 64][RADIX];
+  const uint32_t K = item_count(a.count_dev, a.count);
+  const uint32_t nparts = (uint32_t)(((uint64_t)K + SPART - 1) / SPART);
+  if (blockIdx.x >= nparts) return;  // capacity-sized grids
+  const uint32_t part = blockIdx.x;
+  const uint32_t R = 1u << a.nbits, mask = R - 1u;
+  for (int j = threadIdx.x; j < (BS / 64) * RADIX; j += BS) (&wc[0][0])[j] = 0u;
+  __syncthreads();
+
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int it = 0; it < RIPT; ++it) {
-    const uint64_t idx = base + (uint64_t)it * BS + threadIdx.x;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint64_t base = (uint64_t)part * SPART + (uint64_t)w * (64 * SIPT) + lane;
+  uint32_t key[SIPT], val[SIPT], bits[SIPT], rk[SIPT];
+#pragma unroll
+  for (int r = 0; r < SIPT; ++r) {
+    const uint64_t idx = base + (uint64_t)r * 64;
     const bool valid = idx < K;
-    const uint32_t key = valid ? kin[idx] : 0u;
-    const uint32_t val = valid ? vin[idx] : 0u;
-    const uint32_t d = (key >> shift) & mask;
+    if (SRC == SRC_DEPTH) {
+      key[r] = valid ? depth_key(a.depth, a.tiles, (uint32_t)idx) : 0u;
+      val[r] = (uint32_t)idx;
+    } else {
+      key[r] = valid ? a.kin[idx] : 0u;
+      val[r] = valid ? a.vin[idx] : 0u;
+    }
+    bits[r] = (a.bin && valid) ? a.bin[idx] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < SIPT; ++r) {
+    const bool valid = base + (uint64_t)r * 64 < K;
+    const uint32_t d = (key[r] >> a.shift) & mask;
     uint64_t peers = __ballot(valid);
-    for (int b = 0; b < nbits; ++b) {
+    for (int b = 0; b < a.nbits; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t bb = __ballot(bit);
       peers &= bit ? bb : ~bb;
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && (peers & lt) == 0ull) wcnt[w][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    for (uint32_t dd = threadIdx.x; dd < R; dd += BS) {
-      uint32_t r = run[dd];
+    const uint32_t before = wc[w][d];
+    rk[r] = before + (uint32_t)__popcll(peers & lt);
+    __builtin_amdgcn_wave_barrier();
+    if (valid && (peers & lt) == 0ull) wc[w][d] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // per digit: where each wave's items start in the output
+  if (threadIdx.x < R) {
+    const uint32_t d = threadIdx.x;
+    uint32_t run = a.C[(size_t)d * a.c_stride + part];
 #pragma unroll
-      for (int ww = 0; ww < BS / 64; ++ww) {
-        const uint32_t c = wcnt[ww][dd];
-        woff[ww][dd] = r;
-        r += c;
-        wcnt[ww][dd] = 0u;
-      }
-      run[dd] = r;
+    for (int ww = 0; ww < BS / 64; ++ww) {
+      const uint32_t c = wc[ww][d];
+      wc[ww][d] = run;
+      run += c;
     }
-    __syncthreads();
-    const uint32_t pos = woff[w][d] + rank;
-    if (valid && pos < K) {  // pos < K always holds for a correct ranking
-      if (FINAL) {
-        k64out[pos] = ((uint64_t)key << 32) | (uint64_t)depth_bits[val];
-      } else {
-        kout[pos] = key;
-      }
-      vout[pos] = val;
+  }
+  __syncthreads();
+
+#pragma unroll
+  for (int r = 0; r < SIPT; ++r) {
+    const uint64_t idx = base + (uint64_t)r * 64;
+    if (idx >= K) break;
+    const uint32_t d = (key[r] >> a.shift) & mask;
+    const uint32_t pos = wc[w][d] + rk[r];
+    if (pos >= K) continue;  // unreachable when the counts are consistent
+    if (DST == DST_KV) {
+      a.kout[pos] = key[r];
+      a.vout[pos] = val[r];
+      if (a.bout) a.bout[pos] = bits[r];
+    } else if (DST == DST_ORDER) {
+      a.vout[pos] = val[r];
+      a.cnt_out[pos] = val[r] < a.n ? a.tiles[val[r]] : 0u;
+    } else {
+      a.k64out[pos] = ((uint64_t)key[r] << 32) | bits[r];
+      a.vout[pos] = val[r];
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// stage kernels
+// copies of the splats
 // ---------------------------------------------------------------------------
-__global__ void fill_u32(uint32_t *p, int64_t m, uint32_t v) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) p[i] = v;
+// copies per emission partition (plain stores; no inter-workgroup traffic)
+__global__ __launch_bounds__(BS) void emit_sums(uint32_t n, const uint32_t *__restrict__ cnt,
+                                                uint64_t *__restrict__ esum) {
+  const uint64_t s0 = (uint64_t)blockIdx.x * EPART + threadIdx.x;
+  uint64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < EIPT; ++j)
+    if (s0 + (uint64_t)j * BS < n) s += cnt[s0 + (uint64_t)j * BS];
+  uint64_t total;
+  block_exclusive<uint64_t>(s, total);
+  if (threadIdx.x == 0) esum[blockIdx.x] = total;
 }
 
-__global__ void depth_keys(int64_t n, const float *__restrict__ depth, const uint32_t *__restrict__ tiles,
-                           uint32_t *__restrict__ key, uint32_t *__restrict__ idx) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  // visible splats have depth >= near_z > 0, where float bits order like the values
-  key[i] = tiles[i] ? __float_as_uint(depth[i]) : 0xFFFFFFFFu;
-  idx[i] = (uint32_t)i;
-}
+struct Emit {
+  uint32_t n;
+  const uint32_t *order, *cnt;           // splats in depth order and their copy counts
+  const uint64_t *esum;                  // copies per partition
+  const int32_t *rect;
+  int grid_w;
+  uint64_t capacity;
+  uint32_t *ctr;
+  const float *depth;
+  uint32_t *tkey, *tval, *tbits;         // [capacity]: tile id, splat, depth bits
+  uint32_t *tot;                         // tile digit totals [stripe][pass][digit]
+  int tile_passes, tile_bits;            // digits per key and bits per digit
+  int64_t *num_keys;
+  int32_t *overflow;
+};
 
-__global__ void gather_counts(int64_t n, const uint32_t *__restrict__ order, const uint32_t *__restrict__ tiles,
-                              uint32_t *__restrict__ cnt) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const uint32_t i = order[s];
-  cnt[s] = (int64_t)i < n ? tiles[i] : 0u;
-}
-
-// ctr[0] = effective key count (0 on overflow), ctr[1] = big-splat count
-__global__ void finalize_count(int64_t n, const uint64_t *off, int64_t capacity, int64_t *num_keys,
-                               int32_t *overflow, uint32_t *ctr) {
-  const uint64_t K = n > 0 ? off[n] : 0ull;
-  const bool over = K > (uint64_t)capacity;
-  *num_keys = (int64_t)K;
-  *overflow = over ? 1 : 0;
-  ctr[0] = over ? 0u : (uint32_t)K;
-  ctr[1] = 0u;
-}
-
-__global__ __launch_bounds__(BS) void duplicate(int64_t n, const uint32_t *__restrict__ order,
-                                                const uint64_t *__restrict__ off, const int32_t *__restrict__ rect,
-                                                int grid_w, uint64_t capacity, const int32_t *__restrict__ overflow,
-                                                uint32_t *__restrict__ tkey, uint32_t *__restrict__ tval,
-                                                uint32_t *__restrict__ big, uint32_t *__restrict__ ctr) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n || *overflow) return;
-  const uint64_t o = off[s];
-  const uint32_t cnt = (uint32_t)(off[s + 1] - o);
-  if (cnt == 0 || o + cnt > capacity) return;
-  if (cnt > BIG) {
-    big[atomicAdd(&ctr[1], 1u)] = (uint32_t)s;
-    return;
+// Offsets from the partition sums before this one, then every copy of the
+// partition written by the whole workgroup (consecutive threads write
+// consecutive keys), counting the tile digits as they are written.
+__global__ __launch_bounds__(BS) void emit_copies(Emit a) {
+  __shared__ uint32_t loff[EPART + 1];   // local exclusive offsets of the partition's splats
+  __shared__ uint32_t sidx[EPART], sbits[EPART];
+  __shared__ int32_t sx[EPART], sy[EPART], sw[EPART];
+  __shared__ uint32_t th[MAX_TILE_PASSES * RADIX];
+  const uint32_t nparts = (uint32_t)(((uint64_t)a.n + EPART - 1) / EPART);
+  const uint32_t part = blockIdx.x;
+  for (int j = threadIdx.x; j < MAX_TILE_PASSES * RADIX; j += BS) th[j] = 0u;
+  // copies before this partition
+  uint64_t part_sum = 0, pre;
+  for (uint32_t q = threadIdx.x; q < part; q += BS) part_sum += a.esum[q];
+  block_exclusive<uint64_t>(part_sum, pre);
+  const uint64_t s0 = (uint64_t)part * EPART + (uint64_t)threadIdx.x * EIPT;
+  uint32_t c[EIPT];
+  uint64_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < EIPT; ++j) {
+    c[j] = s0 + j < a.n ? a.cnt[s0 + j] : 0u;
+    sum += c[j];
   }
-  const uint32_t i = order[s];
-  if ((int64_t)i >= n) return;
-  const int4 r = reinterpret_cast<const int4 *>(rect)[i];
-  uint64_t p = o;
-  for (int ty = r.y; ty <= r.w; ++ty)
-    for (int tx = r.x; tx <= r.z; ++tx) {
-      tkey[p] = (uint32_t)(ty * grid_w + tx);
-      tval[p] = i;
-      ++p;
-    }
-}
-
-__global__ __launch_bounds__(BS) void duplicate_big(int64_t n, const uint32_t *__restrict__ order,
-                                                    const uint64_t *__restrict__ off,
-                                                    const int32_t *__restrict__ rect, int grid_w, uint64_t capacity,
-                                                    const uint32_t *__restrict__ big, const uint32_t *__restrict__ ctr,
-                                                    uint32_t *__restrict__ tkey, uint32_t *__restrict__ tval) {
-  const uint32_t nbig = ctr[1];
-  for (uint32_t e = blockIdx.x; e < nbig; e += gridDim.x) {
-    const uint32_t s = big[e];
-    if ((int64_t)s >= n) continue;
-    const uint32_t i = order[s];
-    const uint64_t o = off[s];
-    const uint32_t cnt = (uint32_t)(off[s + 1] - o);
-    if ((int64_t)i >= n || o + cnt > capacity) continue;
-    const int4 r = reinterpret_cast<const int4 *>(rect)[i];
-    const uint32_t w = (uint32_t)(r.z - r.x + 1);
-    for (uint32_t j = threadIdx.x; j < cnt; j += BS) {
-      const uint32_t ty = r.y + j / w, tx = r.x + j % w;
-      tkey[o + j] = ty * (uint32_t)grid_w + tx;
-      tval[o + j] = i;
+  uint64_t total;
+  uint64_t off = block_exclusive<uint64_t>(sum, total);
+  if (threadIdx.x == 0 && part == nparts - 1) {
+    const uint64_t K = pre + total;
+    const bool over = K > a.capacity;
+    *a.num_keys = (int64_t)K;
+    *a.overflow = over ? 1 : 0;
+    a.ctr[CTR_KEYS] = over ? 0u : (uint32_t)K;
+  }
+#pragma unroll
+  for (int j = 0; j < EIPT; ++j) {
+    const int ls = threadIdx.x * EIPT + j;
+    loff[ls] = (uint32_t)off;  // only used when the partition fits the capacity (< 2^32)
+    off += c[j];
+    if (c[j]) {
+      const uint32_t i = a.order[s0 + j];
+      const int4 r = i < a.n ? reinterpret_cast<const int4 *>(a.rect)[i] : make_int4(0, 0, -1, -1);
+      sidx[ls] = i;
+      sbits[ls] = i < a.n ? __float_as_uint(a.depth[i]) : 0u;
+      sx[ls] = r.x;
+      sy[ls] = r.y;
+      sw[ls] = r.z - r.x + 1;
     }
   }
+  if (threadIdx.x == BS - 1) loff[EPART] = (uint32_t)off;
+  __syncthreads();
+  if (pre + total > a.capacity || total == 0) return;  // an overflowing call writes no key
+  const uint32_t T = (uint32_t)total;
+  const uint32_t dmask = (1u << a.tile_bits) - 1u;
+  for (uint32_t k = threadIdx.x; k < T; k += BS) {
+    uint32_t lo = 0, hi = EPART;  // loff[lo] <= k < loff[hi]
+#pragma unroll
+    for (int it = 0; it < 10; ++it) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (loff[mid] <= k) lo = mid; else hi = mid;
+    }
+    const uint32_t r = k - loff[lo];
+    const int32_t wdt = sw[lo];
+    if (wdt <= 0) continue;  // counts that disagree with the rectangle
+    const uint32_t q = r / (uint32_t)wdt;
+    const uint32_t tile = (uint32_t)(sy[lo] + (int32_t)q) * (uint32_t)a.grid_w +
+                          (uint32_t)(sx[lo] + (int32_t)(r - q * (uint32_t)wdt));
+    const uint64_t pos = pre + k;
+    a.tkey[pos] = tile;
+    a.tval[pos] = sidx[lo];
+    a.tbits[pos] = sbits[lo];
+    for (int p = 0; p < a.tile_passes; ++p) atomicAdd(&th[p * RADIX + ((tile >> (p * a.tile_bits)) & dmask)], 1u);
+  }
+  __syncthreads();
+  const int stripe = blockIdx.x % STRIPES;
+  for (int j = threadIdx.x; j < a.tile_passes * RADIX; j += BS) {
+    const uint32_t v = th[j];
+    if (v) atomicAdd(total_at(a.tot, stripe, j / RADIX, j % RADIX), v);
+  }
 }
 
+// ranges from the sorted keys
 __global__ void tile_ranges(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ctr, int64_t ntiles,
                             uint32_t *__restrict__ ranges) {
-  const uint32_t K = ctr[0];
+  const uint32_t K = ctr[CTR_KEYS];
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
   const uint32_t t = (uint32_t)(keys[k] >> 32);
@@ -321,40 +438,41 @@ __global__ void tile_ranges(const uint64_t *__restrict__ keys, const uint32_t *_
   if (k + 1 == K || (uint32_t)(keys[k + 1] >> 32) != t) ranges[2 * (size_t)t + 1] = (uint32_t)(k + 1);
 }
 
-// Longest-list-first dispatch order of the tiles: tiles bucketed by their list
-// length (256 linear buckets up to the longest list), heaviest bucket first.
-// A workgroup's time grows with its tile's list, so starting the long lists
-// first keeps them off the tail of the blend launch. One workgroup.
+// Longest-list-first dispatch order of the tiles: tiles bucketed by list
+// length on a log scale (16 buckets per doubling, so lengths within ~4% share
+// a bucket), heaviest bucket first. A workgroup's time grows with its tile's
+// list, so starting the long lists first keeps them off the tail of the blend
+// launch. The order inside a bucket is unspecified. One workgroup.
+__device__ inline int length_bucket(const uint32_t *ranges, int64_t t) {
+  const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+  const int b = (int)(log2f((float)len + 1.0f) * 16.0f);
+  return 255 - (b < 255 ? b : 255);
+}
+
 __global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t *__restrict__ ranges, int64_t ntiles,
                                                           uint32_t *__restrict__ order) {
   constexpr int NB = 256;
   __shared__ uint32_t hist[NB];
-  __shared__ uint32_t s_max;
-  if (threadIdx.x == 0) s_max = 0u;
-  for (int b = threadIdx.x; b < NB; b += blockDim.x) hist[b] = 0u;
+  __shared__ uint32_t wsum[NB / 64];
+  if (threadIdx.x < NB) hist[threadIdx.x] = 0u;
   __syncthreads();
-  uint32_t mx = 0;
-  for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) mx = max(mx, ranges[2 * t + 1] - ranges[2 * t]);
-  atomicMax(&s_max, mx);
+  for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) atomicAdd(&hist[length_bucket(ranges, t)], 1u);
   __syncthreads();
-  const uint64_t span = (uint64_t)s_max + 1ull;
-  for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
-    const uint64_t len = ranges[2 * t + 1] - ranges[2 * t];
-    atomicAdd(&hist[NB - 1 - (int)(len * NB / span)], 1u);
+  uint32_t v = 0, inc = 0;
+  if (threadIdx.x < NB) {
+    v = hist[threadIdx.x];
+    inc = wave_inclusive(v);
+    if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = inc;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int b = 0; b < NB; ++b) {
-      const uint32_t c = hist[b];
-      hist[b] = run;
-      run += c;
-    }
+  if (threadIdx.x < NB) {
+    uint32_t off = inc - v;
+    for (int k = 0; k < (int)(threadIdx.x >> 6); ++k) off += wsum[k];
+    hist[threadIdx.x] = off;
   }
   __syncthreads();
   for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
-    const uint64_t len = ranges[2 * t + 1] - ranges[2 * t];
-    const uint32_t pos = atomicAdd(&hist[NB - 1 - (int)(len * NB / span)], 1u);
+    const uint32_t pos = atomicAdd(&hist[length_bucket(ranges, t)], 1u);
     if ((int64_t)pos < ntiles) order[pos] = (uint32_t)t;
   }
 }
@@ -362,26 +480,39 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t *__rest
 // ---------------------------------------------------------------------------
 // workspace
 // ---------------------------------------------------------------------------
+struct TilePlan {
+  int passes, bits;
+};
+
+TilePlan tile_plan(int64_t ntiles) {
+  int tile_bits = 1;
+  while ((1ll << tile_bits) < ntiles) ++tile_bits;
+  TilePlan p;
+  p.passes = (tile_bits + 7) / 8;
+  p.bits = (tile_bits + p.passes - 1) / p.passes;
+  return p;
+}
+
 struct Workspace {
-  uint32_t *dk0, *di0, *dk1, *di1;   // depth sort ping-pong [n]
-  uint32_t *cnt;                     // copies per splat in depth order [n]
-  uint64_t *off;                     // their exclusive scan [n + 1]
-  uint32_t *hist;                    // digit histograms [RADIX * max blocks]
-  uint64_t *part64;                  // scan partials
-  uint32_t *part32;
-  uint32_t *tk0, *tv0, *tk1, *tv1;   // tile sort ping-pong [capacity]
-  uint32_t *big;                     // splats expanded block-wide [n]
-  uint32_t *ctr;                     // counters
+  uint32_t *dk0, *dv0, *dk1, *dv1;       // depth sort ping-pong [n]
+  uint32_t *order, *cnt;                 // splats in depth order, their copy counts [n]
+  uint64_t *esum;                        // copies per emission partition
+  uint32_t *tk0, *tv0, *tb0, *tk1, *tv1, *tb1;   // tile sort ping-pong [capacity]
+  uint32_t *dC;                          // depth passes' counts [pass][256][depth partitions]
+  uint32_t *tC;                          // tile passes' counts [pass][1 << bits][key partitions]
+  // zeroed at the start of every call, contiguous:
+  uint32_t *ctr;                         // counters
+  uint32_t *dtot, *ttot;                 // digit totals [stripe][pass][256]
+  void *zero_begin;
+  size_t zero_bytes;
+  size_t dstride, tstride;               // partitions per row
 };
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t carve(void *base, int64_t n, int64_t cap, Workspace *w) {
+size_t carve(void *base, int64_t n, int64_t cap, int64_t ntiles, Workspace *w) {
   const size_t N = (size_t)(n > 0 ? n : 1), C = (size_t)(cap > 0 ? cap : 1);
-  const size_t nbn = ceil_div((int64_t)N, RTILE), nbk = ceil_div((int64_t)C, RTILE);
-  const size_t nbmax = nbn > nbk ? nbn : nbk;
-  const size_t hist_items = (size_t)RADIX * nbmax;
-  const size_t parts = ceil_div((int64_t)(hist_items > N + 1 ? hist_items : N + 1), TILE) + 1;
+  const TilePlan tp = tile_plan(ntiles > 0 ? ntiles : 1);
   char *p = (char *)base;
   size_t o = 0;
   auto take = [&](size_t bytes) -> void * {
@@ -391,106 +522,160 @@ size_t carve(void *base, int64_t n, int64_t cap, Workspace *w) {
   };
   Workspace t;
   t.dk0 = (uint32_t *)take(4 * N);
-  t.di0 = (uint32_t *)take(4 * N);
+  t.dv0 = (uint32_t *)take(4 * N);
   t.dk1 = (uint32_t *)take(4 * N);
-  t.di1 = (uint32_t *)take(4 * N);
+  t.dv1 = (uint32_t *)take(4 * N);
+  t.order = (uint32_t *)take(4 * N);
   t.cnt = (uint32_t *)take(4 * N);
-  t.off = (uint64_t *)take(8 * (N + 1));
-  t.hist = (uint32_t *)take(4 * hist_items);
-  t.part64 = (uint64_t *)take(8 * parts);
-  t.part32 = (uint32_t *)take(4 * parts);
+  t.esum = (uint64_t *)take(8 * (size_t)ceil_div((int64_t)N, EPART));
   t.tk0 = (uint32_t *)take(4 * C);
   t.tv0 = (uint32_t *)take(4 * C);
+  t.tb0 = (uint32_t *)take(4 * C);
   t.tk1 = (uint32_t *)take(4 * C);
   t.tv1 = (uint32_t *)take(4 * C);
-  t.big = (uint32_t *)take(4 * N);
-  t.ctr = (uint32_t *)take(4 * 16);
+  t.tb1 = (uint32_t *)take(4 * C);
+  t.dstride = (size_t)ceil_div((int64_t)N, SPART);
+  t.dC = (uint32_t *)take(4 * (size_t)DEPTH_PASSES * RADIX * t.dstride);
+  t.tstride = (size_t)ceil_div((int64_t)C, SPART);
+  t.tC = (uint32_t *)take(4 * ((size_t)tp.passes << tp.bits) * t.tstride);
+  const size_t z0 = o;
+  t.ctr = (uint32_t *)take(4 * CTR_SLOTS);
+  t.dtot = (uint32_t *)take(4 * (size_t)STRIPES * MAX_TILE_PASSES * RADIX);
+  t.ttot = (uint32_t *)take(4 * (size_t)STRIPES * MAX_TILE_PASSES * RADIX);
+  t.zero_begin = p ? (void *)(p + z0) : nullptr;
+  t.zero_bytes = o - z0;
   if (w) *w = t;
   return o;
 }
 
-hipError_t radix_pass(const uint32_t *kin, const uint32_t *vin, uint32_t kh, const uint32_t *kd, uint32_t nb,
-                      int shift, int nbits, uint32_t *hist, uint32_t *part32, uint32_t *kout, uint32_t *vout,
-                      uint64_t *k64out, const uint32_t *depth_bits, bool final, hipStream_t s) {
-  hipLaunchKernelGGL(radix_upsweep, dim3(nb), dim3(BS), 0, s, kin, kh, kd, shift, nbits, hist, nb);
-  hipError_t e = exclusive_scan<uint32_t, uint32_t>(hist, (int64_t)(1u << nbits) * nb, hist, part32, false, s);
-  if (e != hipSuccess) return e;
-  if (final)
-    hipLaunchKernelGGL(radix_downsweep<true>, dim3(nb), dim3(BS), 0, s, kin, vin, kh, kd, shift, nbits, hist, nb,
-                       kout, vout, k64out, depth_bits);
-  else
-    hipLaunchKernelGGL(radix_downsweep<false>, dim3(nb), dim3(BS), 0, s, kin, vin, kh, kd, shift, nbits, hist,
-                       nb, kout, vout, k64out, depth_bits);
-  return hipGetLastError();
-}
-
 }  // namespace
 
-size_t binsort_workspace_bytes(int64_t n, int64_t capacity, int32_t) { return carve(nullptr, n, capacity, nullptr); }
+size_t binsort_workspace_bytes(int64_t n, int64_t capacity, int32_t num_tiles) {
+  return carve(nullptr, n, capacity, num_tiles, nullptr);
+}
 
 hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles, int grid_w,
                           int grid_h, int64_t capacity, void *ws, size_t, uint64_t *keys, uint32_t *vals,
                           uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys, int32_t *overflow,
                           hipStream_t s) {
-  Workspace w;
-  carve(ws, n, capacity, &w);
   const int64_t ntiles = (int64_t)grid_w * grid_h;
-  hipLaunchKernelGGL(fill_u32, dim3(ceil_div(2 * ntiles, 256)), dim3(256), 0, s, ranges, 2 * ntiles, 0u);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  Workspace w;
+  carve(ws, n, capacity, ntiles, &w);
+  const TilePlan tp = tile_plan(ntiles);
+  const size_t dpass = (size_t)RADIX * w.dstride;             // one depth pass's counts
+  const size_t tpass = ((size_t)1 << tp.bits) * w.tstride;    // one tile pass's counts
 
-  const uint32_t nbn = n > 0 ? ceil_div(n, RTILE) : 0;
+  // 0. zero totals, counters and ranges; num_keys = overflow = 0
+  {
+    const size_t nz16 = w.zero_bytes / 16, nr = 2 * (size_t)ntiles;
+    const size_t m = nz16 > nr ? nz16 : nr;
+    const unsigned grid = (unsigned)(m / BS + 1 < 2048 ? m / BS + 1 : 2048);
+    hipLaunchKernelGGL(clear_state, dim3(grid), dim3(BS), 0, s, (uint4 *)w.zero_begin, nz16, ranges, nr, num_keys,
+                       overflow);
+  }
+
   if (n > 0) {
-    // 1. splats by depth (stable, index order on ties): four 8-bit passes
-    hipLaunchKernelGGL(depth_keys, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, depth, tiles, w.dk0, w.di0);
-    uint32_t *ka = w.dk0, *va = w.di0, *kb = w.dk1, *vb = w.di1;
-    for (int pass = 0; pass < 4; ++pass) {
-      e = radix_pass(ka, va, (uint32_t)n, nullptr, nbn, 8 * pass, 8, w.hist, w.part32, kb, vb, nullptr, nullptr,
-                     false, s);
-      if (e != hipSuccess) return e;
+    // 1. depth keys: first pass's counts, all passes' totals
+    const unsigned dgrid = ceil_div(n, SPART);
+    hipLaunchKernelGGL(depth_count, dim3(dgrid), dim3(BS), 0, s, (uint32_t)n, depth, tiles, w.dC, w.dstride,
+                       w.dtot);
+    // 2. splats by depth (stable, index order on ties): four 8-bit passes; the
+    //    last writes the order and each splat's copy count
+    Pass a{};
+    a.depth = depth;
+    a.tiles = tiles;
+    a.n = (uint32_t)n;
+    a.count = (uint32_t)n;
+    a.nbits = 8;
+    a.c_stride = w.dstride;
+    a.cnt_out = w.cnt;
+    uint32_t *kin = nullptr, *vin = nullptr, *kb = w.dk0, *vb = w.dv0, *ka = w.dk1, *va = w.dv1;
+    for (int pass = 0; pass < DEPTH_PASSES; ++pass) {
+      uint32_t *Cp = w.dC + pass * dpass;
+      if (pass > 0)
+        hipLaunchKernelGGL(count_pass, dim3(dgrid), dim3(BS), 0, s, (const uint32_t *)kin, (const uint32_t *)nullptr,
+                           (uint32_t)n, 8 * pass, 8, Cp, w.dstride);
+      hipLaunchKernelGGL(scan_rows, dim3(RADIX), dim3(BS), 0, s, Cp, w.dstride, (const uint32_t *)nullptr,
+                         (uint32_t)n, (const uint32_t *)w.dtot, pass);
+      a.kin = kin;
+      a.vin = vin;
+      a.shift = 8 * pass;
+      a.C = Cp;
+      a.kout = kb;
+      a.vout = pass == DEPTH_PASSES - 1 ? w.order : vb;
+      if (pass == 0)
+        hipLaunchKernelGGL((scatter_pass<SRC_DEPTH, DST_KV>), dim3(dgrid), dim3(BS), 0, s, a);
+      else if (pass < DEPTH_PASSES - 1)
+        hipLaunchKernelGGL((scatter_pass<SRC_KV, DST_KV>), dim3(dgrid), dim3(BS), 0, s, a);
+      else
+        hipLaunchKernelGGL((scatter_pass<SRC_KV, DST_ORDER>), dim3(dgrid), dim3(BS), 0, s, a);
+      kin = kb;
+      vin = vb;
       uint32_t *tk = ka, *tv = va;
       ka = kb; va = vb; kb = tk; vb = tv;
     }
-    // 2. copies per splat in depth order and their offsets
-    hipLaunchKernelGGL(gather_counts, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, va, tiles, w.cnt);
-    e = exclusive_scan<uint32_t, uint64_t>(w.cnt, n, w.off, w.part64, true, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finalize_count, dim3(1), dim3(1), 0, s, n, w.off, capacity, num_keys, overflow, w.ctr);
-    // 3. emit (tile, splat) copies in depth order
-    hipLaunchKernelGGL(duplicate, dim3(ceil_div(n, BS)), dim3(BS), 0, s, n, va, w.off, rect, grid_w,
-                       (uint64_t)capacity, overflow, w.tk0, w.tv0, w.big, w.ctr);
-    hipLaunchKernelGGL(duplicate_big, dim3(1024), dim3(BS), 0, s, n, va, w.off, rect, grid_w, (uint64_t)capacity,
-                       w.big, w.ctr, w.tk0, w.tv0);
-  } else {
-    hipLaunchKernelGGL(finalize_count, dim3(1), dim3(1), 0, s, (int64_t)0, w.off, capacity, num_keys, overflow,
-                       w.ctr);
+    // 3. copies in depth order with their depth bits, the tile passes' totals, K
+    const unsigned egrid = ceil_div(n, EPART);
+    hipLaunchKernelGGL(emit_sums, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, (const uint32_t *)w.cnt, w.esum);
+    Emit e{};
+    e.n = (uint32_t)n;
+    e.order = w.order;
+    e.cnt = w.cnt;
+    e.esum = w.esum;
+    e.rect = rect;
+    e.grid_w = grid_w;
+    e.capacity = (uint64_t)capacity;
+    e.ctr = w.ctr;
+    e.depth = depth;
+    e.tkey = w.tk0;
+    e.tval = w.tv0;
+    e.tbits = w.tb0;
+    e.tot = w.ttot;
+    e.tile_passes = tp.passes;
+    e.tile_bits = tp.bits;
+    e.num_keys = num_keys;
+    e.overflow = overflow;
+    hipLaunchKernelGGL(emit_copies, dim3(egrid), dim3(BS), 0, s, e);
   }
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (capacity == 0) {
-    if (tile_order)
-      hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order);
-    return hipGetLastError();
-  }
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
 
-  // 4. stable LSD passes over the tile digits; the last writes the 64-bit keys
-  int tile_bits = 1;
-  while ((1ll << tile_bits) < ntiles) ++tile_bits;
-  const int passes = (tile_bits + 7) / 8;
-  const int bits = (tile_bits + passes - 1) / passes;
-  const uint32_t nbk = ceil_div(capacity, RTILE);
-  const uint32_t *depth_bits = reinterpret_cast<const uint32_t *>(depth);
-  uint32_t *ka = w.tk0, *va = w.tv0, *kb = w.tk1, *vb = w.tv1;
-  for (int pass = 0; pass < passes; ++pass) {
-    const bool last = pass == passes - 1;
-    e = radix_pass(ka, va, 0u, w.ctr, nbk, bits * pass, bits, w.hist, w.part32, last ? nullptr : kb,
-                   last ? vals : vb, last ? keys : nullptr, depth_bits, last, s);
-    if (e != hipSuccess) return e;
-    uint32_t *tk = ka, *tv = va;
-    ka = kb; va = vb; kb = tk; vb = tv;
+  if (capacity > 0 && n > 0) {
+    // 4. stable passes over the tile digits; the last writes the 64-bit keys
+    const unsigned kgrid = ceil_div(capacity, SPART);
+    Pass a{};
+    a.depth = depth;
+    a.n = (uint32_t)n;
+    a.count_dev = w.ctr + CTR_KEYS;
+    a.nbits = tp.bits;
+    a.c_stride = w.tstride;
+    uint32_t *ka = w.tk0, *va = w.tv0, *ba = w.tb0, *kb = w.tk1, *vb = w.tv1, *bb = w.tb1;
+    for (int pass = 0; pass < tp.passes; ++pass) {
+      const bool last = pass == tp.passes - 1;
+      uint32_t *Cp = w.tC + pass * tpass;
+      hipLaunchKernelGGL(count_pass, dim3(kgrid), dim3(BS), 0, s, (const uint32_t *)ka, a.count_dev, 0u,
+                         tp.bits * pass, tp.bits, Cp, w.tstride);
+      hipLaunchKernelGGL(scan_rows, dim3(1u << tp.bits), dim3(BS), 0, s, Cp, w.tstride, a.count_dev, 0u,
+                         (const uint32_t *)w.ttot, pass);
+      a.kin = ka;
+      a.vin = va;
+      a.bin = ba;
+      a.shift = tp.bits * pass;
+      a.C = Cp;
+      a.kout = kb;
+      a.vout = last ? vals : vb;
+      a.bout = bb;
+      a.k64out = keys;
+      if (last)
+        hipLaunchKernelGGL((scatter_pass<SRC_KV, DST_KEYS>), dim3(kgrid), dim3(BS), 0, s, a);
+      else
+        hipLaunchKernelGGL((scatter_pass<SRC_KV, DST_KV>), dim3(kgrid), dim3(BS), 0, s, a);
+      uint32_t *tk = ka, *tv = va, *tb = ba;
+      ka = kb; va = vb; ba = bb; kb = tk; vb = tv; bb = tb;
+    }
+    // 5. per-tile ranges
+    hipLaunchKernelGGL(tile_ranges, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, keys, w.ctr, ntiles, ranges);
   }
-  // 5. per-tile ranges
-  hipLaunchKernelGGL(tile_ranges, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, keys, w.ctr, ntiles, ranges);
   // 6. longest-first dispatch order for the blend
   if (tile_order) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order);
   return hipGetLastError();

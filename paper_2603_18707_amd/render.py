@@ -106,11 +106,14 @@ class Rasterizer:
         """bin_sort, growing the capacity and retrying when the keys overflow
         (reads two device scalars back: use outside timed or captured regions)."""
         b = self.bin_sort(proj, cam, stream=stream)
-        if int(b["overflow"].item()):
+        flag = int(b["overflow"].item())
+        if flag & 1:
             K = int(b["num_keys"].item())
             self.capacity = int(K * 1.125) + 1024
             b = self.bin_sort(proj, cam, stream=stream)
-            assert not int(b["overflow"].item())
+            flag = int(b["overflow"].item())
+        if flag:
+            raise RuntimeError(f"gs_bin_sort reported overflow flags {flag}")
         return b
 
     def rasterize(self, proj: dict, binned: dict, cam, want_eval: bool = False, stream=None) -> dict:

@@ -223,3 +223,31 @@ def sample_pixels(width: int, height: int, count: int, seed: int) -> np.ndarray:
     idx = rng.choice(width * height, size=count, replace=False)
     idx.sort()
     return np.stack([idx % width, idx // width], axis=1).astype(np.int32)
+
+
+def binning_inputs(n: int, grid_w: int, grid_h: int, seed: int, culled: float = 0.1, ties: float = 0.2,
+                   big: float = 0.003):
+    """Seeded inputs of the binning stage alone, shaped like a projection's
+    outputs: depth [n] float32 (positive; a fraction `ties` repeats another
+    splat's depth, so equal keys occur), rect [n, 4] int32 tile rectangles
+    (x0, y0, x1, y1) inside the grid, mostly one to a few tiles wide with a
+    fraction `big` spanning up to the whole grid, and the empty rectangle
+    (0, 0, -1, -1) for a fraction `culled`; tiles [n] uint32 = the rectangle's
+    tile count."""
+    rng = np.random.default_rng(seed)
+    depth = rng.uniform(0.2, 120.0, n).astype(np.float32)
+    if n > 1:
+        tie = rng.random(n) < ties
+        depth[tie] = depth[rng.integers(0, n, int(tie.sum()))]
+    w = np.minimum(rng.geometric(0.45, n), grid_w)
+    h = np.minimum(rng.geometric(0.45, n), grid_h)
+    is_big = rng.random(n) < big
+    w[is_big] = rng.integers(1, grid_w + 1, int(is_big.sum()))
+    h[is_big] = rng.integers(1, grid_h + 1, int(is_big.sum()))
+    x0 = (rng.random(n) * (grid_w - w + 1)).astype(np.int64)
+    y0 = (rng.random(n) * (grid_h - h + 1)).astype(np.int64)
+    rect = np.stack([x0, y0, x0 + w - 1, y0 + h - 1], axis=1)
+    dead = rng.random(n) < culled
+    rect[dead] = (0, 0, -1, -1)
+    tiles = np.where(dead, 0, w * h).astype(np.uint32)
+    return depth, rect.astype(np.int32), tiles

@@ -1,0 +1,103 @@
+"""gs_bin_sort alone on the GPU, through the C ABI, against the oracle's
+binning (oracle.binning), bit for bit: keys, values, tile ranges and the key
+count, on seeded synthetic rectangles and depths (scenes.binning_inputs) with
+depth ties, culled splats and splats spanning up to the whole grid. Grid
+shapes cover one, two and four tile-digit passes; capacities cover the exact
+fit, one short (overflow) and zero.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import binning
+from paper_2603_18707_amd import _lib as L
+from paper_2603_18707_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(depth, rect, tiles, gw, gh, capacity):
+    dev = torch.device("cuda", 0)
+    n = depth.shape[0]
+    d = torch.from_numpy(depth).to(dev)
+    r = torch.from_numpy(rect).to(dev)
+    t = torch.from_numpy(tiles.view(np.int32)).to(dev)
+    ntiles = gw * gh
+    ws_bytes = L.gs_bin_sort_workspace(n, capacity, ntiles)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    keys = torch.full((max(capacity, 1),), -1, dtype=torch.int64, device=dev)
+    vals = torch.full((max(capacity, 1),), -1, dtype=torch.int32, device=dev)
+    ranges = torch.full((ntiles, 2), -1, dtype=torch.int32, device=dev)
+    order = torch.full((ntiles,), -1, dtype=torch.int32, device=dev)
+    num_keys = torch.full((1,), -1, dtype=torch.int64, device=dev)
+    overflow = torch.full((1,), -1, dtype=torch.int32, device=dev)
+    L.gs_bin_sort(n, d, r, t, gw, gh, capacity, ws, ws_bytes, keys, vals, ranges, order, num_keys, overflow)
+    torch.cuda.synchronize()
+    K = int(num_keys.item())
+    kk = min(K, capacity)
+    return dict(K=K, overflow=int(overflow.item()), keys=keys.cpu().numpy()[:kk].view(np.uint64),
+                vals=vals.cpu().numpy()[:kk].view(np.uint32), ranges=ranges.cpu().numpy().view(np.uint32),
+                order=order.cpu().numpy().view(np.uint32))
+
+
+CASES = [  # n, grid_w, grid_h, seed, share of big splats
+    (0, 4, 4, 1, 0.0),
+    (1, 1, 1, 2, 0.0),
+    (5000, 120, 68, 3, 0.003),
+    (300_000, 120, 68, 4, 0.003),     # ~150 depth partitions, ~1500 key partitions
+    (20_000, 200, 1, 5, 0.003),       # 8 tile bits: the emitted copies go straight to the last pass
+    (20_000, 300, 1, 6, 0.003),       # 9 tile bits: two 5-bit passes
+    (3000, 8192, 2100, 7, 0.0),       # 25 tile bits: four 7-bit passes
+]
+
+
+@pytest.mark.parametrize("n,gw,gh,seed,big", CASES)
+def test_bin_sort_matches_oracle(n, gw, gh, seed, big):
+    depth, rect, tiles = scenes.binning_inputs(n, gw, gh, seed, big=big)
+    keys, vals, ranges = binning.bin_and_sort_fast(rect, depth, gw, gh)
+    K = keys.shape[0]
+    print(f"[gpu] bin_sort n={n} grid={gw}x{gh} K={K}", flush=True)
+    g = _run(depth, rect, tiles, gw, gh, K + 17)
+    assert g["overflow"] == 0 and g["K"] == K
+    assert np.array_equal(g["keys"], keys)
+    assert np.array_equal(g["vals"], vals)
+    assert np.array_equal(g["ranges"], ranges)
+    _check_order(g["order"], ranges)
+
+
+def _check_order(order, ranges):
+    """Every tile once, lists non-increasing in length up to the documented
+    bucket width (16 log-spaced buckets per doubling, longer than 2^16 merged)."""
+    ntiles = ranges.shape[0]
+    assert np.array_equal(np.sort(order), np.arange(ntiles, dtype=np.uint32))
+    lens = ranges[:, 1].astype(np.float64) - ranges[:, 0]
+    lo = np.minimum(np.log2(lens[order] + 1.0) * 16.0, 255.999)
+    run_min = np.minimum.accumulate(lo)
+    assert np.all(lo[1:] < run_min[:-1] + 1.0 + 1e-4)
+
+
+def test_bin_sort_capacity_edges():
+    gw, gh = 120, 68
+    depth, rect, tiles = scenes.binning_inputs(40_000, gw, gh, 8)
+    keys, vals, ranges = binning.bin_and_sort_fast(rect, depth, gw, gh)
+    K = keys.shape[0]
+    g = _run(depth, rect, tiles, gw, gh, K)  # exact fit
+    assert g["overflow"] == 0 and g["K"] == K
+    assert np.array_equal(g["keys"], keys) and np.array_equal(g["vals"], vals)
+    _check_order(g["order"], ranges)
+    for cap in (K - 1, 0):
+        g = _run(depth, rect, tiles, gw, gh, cap)
+        assert g["overflow"] == 1 and g["K"] == K
+        assert np.all(g["ranges"] == 0)
+
+
+def test_bin_sort_all_culled_and_repeatable():
+    gw, gh = 64, 40
+    depth, rect, tiles = scenes.binning_inputs(10_000, gw, gh, 9, culled=1.0)
+    g = _run(depth, rect, tiles, gw, gh, 128)
+    assert g["K"] == 0 and g["overflow"] == 0 and np.all(g["ranges"] == 0)
+    depth, rect, tiles = scenes.binning_inputs(70_000, gw, gh, 10)
+    a = _run(depth, rect, tiles, gw, gh, 1 << 20)
+    b = _run(depth, rect, tiles, gw, gh, 1 << 20)
+    for k in ("keys", "vals", "ranges"):  # tile_order's order inside a length bucket is unspecified
+        assert np.array_equal(a[k], b[k]), k

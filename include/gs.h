@@ -181,9 +181,7 @@ gs_status gs_bin_sort_workspace(int64_t n, int64_t key_capacity, int32_t num_til
  *      num_keys (device int64) = K, the total number of copies,
  *      overflow (device int32) = 1 when K > key_capacity, else 0. On overflow
  *      no key is written and every range is (0, 0); the caller reads
- *      *num_keys and calls again with a larger capacity. Bit value 2 marks
- *      an internal hand-off between workgroups that timed out (not expected
- *      to happen); the outputs are then invalid.
+ *      *num_keys and calls again with a larger capacity.
  *      tile_order [grid_w * grid_h] uint32 (may be NULL) = every tile id once,
  *      longest lists first (lists bucketed by length); passed to the blend
  *      entry points it makes the workgroups with the most work start first.

@@ -93,6 +93,16 @@ __device__ inline uint32_t depth_key(const float *depth, const uint32_t *tiles, 
   return tiles[i] ? __float_as_uint(depth[i]) : 0xFFFFFFFFu;
 }
 
+// Workgroup b of a G-workgroup launch runs on XCD b % 8 (round-robin
+// dispatch). Handing each XCD a contiguous run of partitions keeps the
+// neighbouring partitions, whose outputs share cache lines at every digit
+// boundary, in one L2 instead of writing the same lines from several. A
+// bijection on [0, G).
+__device__ inline uint32_t xcd_partition(uint32_t b, uint32_t G) {
+  const uint32_t q = G / 8, r = G % 8, x = b % 8;
+  return x * q + (x < r ? x : r) + b / 8;
+}
+
 __device__ inline uint32_t item_count(const uint32_t *count_dev, uint32_t count) {
   return count_dev ? *count_dev : count;
 }
@@ -242,7 +252,7 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
   const uint32_t K = item_count(a.count_dev, a.count);
   const uint32_t nparts = (uint32_t)(((uint64_t)K + SPART - 1) / SPART);
   if (blockIdx.x >= nparts) return;  // capacity-sized grids
-  const uint32_t part = blockIdx.x;
+  const uint32_t part = xcd_partition(blockIdx.x, nparts);
   const uint32_t R = 1u << a.nbits, mask = R - 1u;
   for (int j = threadIdx.x; j < (BS / 64) * RADIX; j += BS) (&wc[0][0])[j] = 0u;
   __syncthreads();

@@ -93,6 +93,8 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
                                   const BlendOut &out) {
   constexpr int P = TS * TS / NT;   // pixels per lane
   constexpr int RS = NT / TS;       // row stride between a lane's pixels
+  constexpr int G = 4;              // splats tested per step
+  static_assert(NT % G == 0, "a staged batch holds whole steps");
   __shared__ float4 L0[NT], L1[NT], L2[NT];
   const int lane = threadIdx.x;
   const int px = tx * TS + (lane & (TS - 1));
@@ -128,44 +130,58 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
       L0[lane] = a0;
       L1[lane] = a1;
       L2[lane] = a2;
+    } else {
+      // neutral record: zero quadric and threshold -1, so t = -1 everywhere
+      L0[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      L1[lane] = make_float4(0.0f, -1.0f, 0.0f, 0.0f);
     }
     __syncthreads();
     const int cnt = (int)min((uint32_t)NT, end - b);
     if (any) {
-      for (int j = 0; j < cnt; ++j) {
-        const float4 r0 = L0[j];
-        const float4 r1 = L1[j];
-        const float dx = fx - r0.x;
-        const float adx = r0.z * dx;
-        const float R0 = fmaf(-adx, dx, r1.y);
-        const float Pq = r0.w * dx;
-        float t[P];
+      // G splats per step: all G records are read and tested before the one
+      // branch that skips the step when no pixel of the lane passes (most
+      // steps); the blend then visits the G splats in list order
+      for (int j = 0; j < cnt; j += G) {
+        float t[G][P];
         float mx = -1.0f;
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-          const float dy = fy[k] - r0.y;
-          t[k] = fmaf(-dy, fmaf(r1.x, dy, Pq), R0);
-          mx = fmaxf(mx, t[k]);
-        }
-        if (mx >= 0.0f) {
-          const uint32_t pos = b + j - start + 1;
+        for (int q = 0; q < G; ++q) {
+          const float4 r0 = L0[j + q];
+          const float2 r1 = *reinterpret_cast<const float2 *>(&L1[j + q]);  // (c, x_e)
+          const float dx = fx - r0.x;
+          const float adx = r0.z * dx;
+          const float R0 = fmaf(-adx, dx, r1.y);
+          const float Pq = r0.w * dx;
 #pragma unroll
           for (int k = 0; k < P; ++k) {
-            if (t[k] >= 0.0f && alive[k]) {
-              const float a = alpha_from<KIND>(t[k], r1, p);
-              const float Tn = T[k] * (1.0f - a);
-              if (Tn < p.t_min) {
-                alive[k] = false;
-                nev[k] = pos;
-              } else {
-                const float4 r2 = L2[j];
-                const float w = a * T[k];
-                C0[k] = fmaf(r2.x, w, C0[k]);
-                C1[k] = fmaf(r2.y, w, C1[k]);
-                C2[k] = fmaf(r2.z, w, C2[k]);
-                T[k] = Tn;
-                ++ncon[k];
-                last[k] = pos;
+            const float dy = fy[k] - r0.y;
+            t[q][k] = fmaf(-dy, fmaf(r1.x, dy, Pq), R0);
+            mx = fmaxf(mx, t[q][k]);
+          }
+        }
+        if (mx >= 0.0f) {
+#pragma unroll
+          for (int q = 0; q < G; ++q) {
+            const uint32_t pos = b + j + q - start + 1;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+              if (t[q][k] >= 0.0f && alive[k]) {
+                const float4 r1 = L1[j + q];
+                const float a = alpha_from<KIND>(t[q][k], r1, p);
+                const float Tn = T[k] * (1.0f - a);
+                if (Tn < p.t_min) {
+                  alive[k] = false;
+                  nev[k] = pos;
+                } else {
+                  const float4 r2 = L2[j + q];
+                  const float w = a * T[k];
+                  C0[k] = fmaf(r2.x, w, C0[k]);
+                  C1[k] = fmaf(r2.y, w, C1[k]);
+                  C2[k] = fmaf(r2.z, w, C2[k]);
+                  T[k] = Tn;
+                  ++ncon[k];
+                  last[k] = pos;
+                }
               }
             }
           }

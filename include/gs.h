@@ -214,6 +214,20 @@ gs_status gs_rasterize_fwd(const gs_camera *cam, const gs_kernel *kernel, const 
                            float *final_T, uint32_t *n_contrib, uint32_t *last_contrib, uint32_t *n_eval,
                            void *stream);
 
+/* The work gs_rasterize_fwd performs, for measurement: the same blend with
+ * the same outputs, plus n_tested [H,W] uint32 = kernel evaluations done for
+ * the pixel (list entries its wave did not skip, while the pixel was alive,
+ * the entry that stopped it included). The forward skips an entry for a wave
+ * when a conservative box around the entry's threshold ellipse (Q <= x_e,
+ * the region where alpha >= eps) misses the wave's pixels, so n_tested <=
+ * n_eval and n_tested >= n_contrib. Slower than gs_rasterize_fwd (an extra
+ * counter in the inner loop); n_eval may be NULL, n_tested may not. */
+gs_status gs_rasterize_fwd_count(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
+                                 const float *means2d, const float *conic_opacity, const float *rgb,
+                                 const uint32_t *vals, const uint32_t *ranges, const uint32_t *tile_order,
+                                 float *image, float *final_T, uint32_t *n_contrib, uint32_t *last_contrib,
+                                 uint32_t *n_eval, uint32_t *n_tested, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* backward path (the derivative of the ReLU-polynomial kernel the paper   */
 /* adds to optimise scenes with it, Sec. 4.3)                              */

@@ -54,8 +54,8 @@ class GsError(RuntimeError):
 _lib = None
 
 EXPORTS = ("gs_version", "gs_last_error", "gs_kernel_default", "gs_kernel_root", "gs_params_default",
-           "gs_preprocess", "gs_bin_sort_workspace", "gs_bin_sort", "gs_rasterize_fwd", "gs_rasterize_bwd",
-           "gs_preprocess_bwd", "gs_batch_layout", "gs_render_batched")
+           "gs_preprocess", "gs_bin_sort_workspace", "gs_bin_sort", "gs_rasterize_fwd", "gs_rasterize_fwd_count",
+           "gs_rasterize_bwd", "gs_preprocess_bwd", "gs_batch_layout", "gs_render_batched")
 
 
 def lib():
@@ -187,6 +187,14 @@ def gs_rasterize_fwd(cam, kernel, params, n, means2d, conic_opacity, rgb, vals, 
                                   _ptr(means2d), _ptr(conic_opacity), _ptr(rgb), _ptr(vals), _ptr(ranges),
                                   _ptr(tile_order), _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(last_contrib),
                                   _ptr(n_eval), _stream(stream)))
+
+
+def gs_rasterize_fwd_count(cam, kernel, params, n, means2d, conic_opacity, rgb, vals, ranges, tile_order, image,
+                           final_T, n_contrib, last_contrib, n_eval, n_tested, stream=None):
+    _check(lib().gs_rasterize_fwd_count(ctypes.byref(cam), ctypes.byref(kernel), ctypes.byref(params), int(n),
+                                        _ptr(means2d), _ptr(conic_opacity), _ptr(rgb), _ptr(vals), _ptr(ranges),
+                                        _ptr(tile_order), _ptr(image), _ptr(final_T), _ptr(n_contrib),
+                                        _ptr(last_contrib), _ptr(n_eval), _ptr(n_tested), _stream(stream)))
 
 
 def gs_rasterize_bwd(cam, kernel, params, n, means2d, conic_opacity, rgb, vals, ranges, tile_order, final_T,

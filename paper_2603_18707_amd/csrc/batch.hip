@@ -163,7 +163,7 @@ __global__ __launch_bounds__(NT) void batch_blend(BlendParams base, const ViewIn
     p.gx = in.gx;
     p.gy = in.gy;
     const BlendOut out{images + in.image_offset, final_T + in.pixel_offset, n_contrib + in.pixel_offset,
-                       last_contrib + in.pixel_offset, nullptr};
+                       last_contrib + in.pixel_offset, nullptr, nullptr};
     blend_tile<KIND, NT>(p, (int)tx, (int)vrow - in.row_base, ranges[2 * (size_t)tile], ranges[2 * (size_t)tile + 1],
                          means2d, conic_opacity, rgb, vals, out);
   }

@@ -83,28 +83,66 @@ __device__ inline float alpha_from(float t, const float4 &s1, const BlendParams 
   return fminf(a, p.alpha_max);
 }
 
+// Conservative box around the pixels a staged record can pass: the region
+// t = x_e - Q >= 0 is an ellipse with half extents sqrt(x_e a / det) in y and
+// sqrt(x_e c / det) in x (det = a c - b^2, in double from the float record).
+// The box is widened by a margin that covers the float rounding of t: near
+// the edge, t falls with distance at a rate ~2 x_e / extent, and its rounding
+// error is a few ulps of the largest term in the box. Degenerate records get
+// an unbounded box (no culling); records that never pass get an empty one.
+__device__ inline void pass_box(const float4 &s0, const float4 &s1, float &hx, float &hy) {
+  const double a = s0.z, b = 0.5 * (double)s0.w, c = s1.x, xe = s1.y;
+  if (!(xe >= 0.0)) {
+    hx = hy = -__builtin_inff();
+    return;
+  }
+  const double det = a * c - b * b;
+  hx = hy = __builtin_inff();
+  if (!(det > 0.0) || !(a > 0.0) || !(c > 0.0) || !(xe > 1e-12)) return;
+  const double ey = sqrt(xe * a / det), ex = sqrt(xe * c / det);
+  const double big = (a + 2.0 * fabs(b) + c) * (ex + ey) * (ex + ey) + xe;
+  const double rel = 1e-3 + 1e-6 * big / xe;
+  if (rel > 0.05) return;
+  hx = (float)(ex * (1.0 + rel) + 0.01);
+  hy = (float)(ey * (1.0 + rel) + 0.01);
+}
+
 // Blends one 16x16 tile (tile coordinates tx, ty of an image of p.W x p.H
 // pixels) over its sorted list [start, end) of splat indices into `out`
 // (pointers to this image's planes). Called by NT threads of a workgroup.
-template <int KIND, int NT>
+//
+// Splats are staged NT at a time. Each staged record gets a bit per wave of
+// the workgroup telling whether its pass box meets the rows that wave
+// shades; every wave then walks a compacted list of its records, still in
+// list order, so splats that cannot reach a wave's pixels cost it nothing.
+//
+// COUNT adds a per-pixel count of the kernel evaluations performed (entries
+// of the wave's list while the pixel is alive, the one that stops it
+// included), written to out.n_tested: a measurement build, not for rendering.
+template <int KIND, int NT, bool COUNT = false>
 __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t start, uint32_t end,
                                   const float *__restrict__ means2d, const float *__restrict__ conic_opacity,
                                   const float *__restrict__ rgb, const uint32_t *__restrict__ vals,
                                   const BlendOut &out) {
   constexpr int P = TS * TS / NT;   // pixels per lane
   constexpr int RS = NT / TS;       // row stride between a lane's pixels
+  constexpr int NW = NT / WAVE;     // waves per workgroup
   constexpr int G = 4;              // splats tested per step
   static_assert(NT % G == 0, "a staged batch holds whole steps");
-  __shared__ float4 L0[NT], L1[NT], L2[NT];
-  const int lane = threadIdx.x;
+  __shared__ float4 L0[NT + 1], L1[NT + 1], L2[NT + 1];   // slot NT: neutral record
+  __shared__ uint16_t lst[NW][NT + G];
+  __shared__ uint32_t wcnt[NW][NW];                      // [staging wave][shading wave]
+  const int lane = threadIdx.x, wv = lane / WAVE;
+  const uint64_t lt = (1ull << (lane & (WAVE - 1))) - 1ull;
   const int px = tx * TS + (lane & (TS - 1));
   const int py0 = ty * TS + lane / TS;
   const float fx = (float)px + 0.5f;
   float fy[P], T[P], C0[P], C1[P], C2[P];
-  uint32_t ncon[P], last[P], nev[P];
+  uint32_t ncon[P], last[P], nev[P], tested[P];
   bool alive[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) {
+    tested[k] = 0u;
     fy[k] = (float)(py0 + RS * k) + 0.5f;
     T[k] = 1.0f;
     C0[k] = C1[k] = C2[k] = 0.0f;
@@ -112,6 +150,12 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
     nev[k] = end - start;
     alive[k] = px < p.W && (py0 + RS * k) < p.H;
   }
+  if (lane == 0) {
+    // zero quadric and threshold -1: t = -1 everywhere
+    L0[NT] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    L1[NT] = make_float4(0.0f, -1.0f, 0.0f, 0.0f);
+  }
+  const float tile_x0 = (float)(tx * TS) + 0.5f, tile_y0 = (float)(ty * TS) + 0.5f;
 
   for (uint32_t b = start; b < end; b += NT) {
     bool any = false;
@@ -119,6 +163,7 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
     for (int k = 0; k < P; ++k) any = any || alive[k];
     if (__syncthreads_or(any) == 0) break;  // every pixel of the tile has terminated
     const uint32_t idx = b + lane;
+    uint32_t mask = 0u;
     if (idx < end) {
       uint32_t id = vals[idx];
       if (id >= p.n) id = 0;  // never taken for a list built by gs_bin_sort over these n splats
@@ -130,24 +175,54 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
       L0[lane] = a0;
       L1[lane] = a1;
       L2[lane] = a2;
-    } else {
-      // neutral record: zero quadric and threshold -1, so t = -1 everywhere
-      L0[lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      L1[lane] = make_float4(0.0f, -1.0f, 0.0f, 0.0f);
+      float hx, hy;
+      pass_box(a0, a1, hx, hy);
+      if (a0.x + hx >= tile_x0 && a0.x - hx <= tile_x0 + (TS - 1)) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+#pragma unroll
+          for (int k = 0; k < P; ++k) {
+            const float r0 = tile_y0 + (float)(4 * w + RS * k);   // the wave's 4 rows for pixel k
+            if (a0.y + hy >= r0 && a0.y - hy <= r0 + 3.0f) mask |= 1u << w;
+          }
+        }
+      }
+    }
+    uint64_t bal[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) bal[w] = __ballot((mask >> w) & 1u);
+    if ((lane & (WAVE - 1)) == 0) {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) wcnt[wv][w] = (uint32_t)__popcll(bal[w]);
     }
     __syncthreads();
-    const int cnt = (int)min((uint32_t)NT, end - b);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      if ((mask >> w) & 1u) {
+        uint32_t off = (uint32_t)__popcll(bal[w] & lt);
+        for (int s = 0; s < wv; ++s) off += wcnt[s][w];
+        lst[w][off] = (uint16_t)lane;
+      }
+    }
+    uint32_t len = 0;
+#pragma unroll
+    for (int s = 0; s < NW; ++s) len += wcnt[s][wv];
+    if ((lane & (WAVE - 1)) < G) lst[wv][len + (lane & (WAVE - 1))] = (uint16_t)NT;
+    __syncthreads();
     if (any) {
       // G splats per step: all G records are read and tested before the one
       // branch that skips the step when no pixel of the lane passes (most
       // steps); the blend then visits the G splats in list order
-      for (int j = 0; j < cnt; j += G) {
+      for (uint32_t i = 0; i < len; i += G) {
+        int js[G];
+#pragma unroll
+        for (int q = 0; q < G; ++q) js[q] = lst[wv][i + q];
         float t[G][P];
         float mx = -1.0f;
 #pragma unroll
         for (int q = 0; q < G; ++q) {
-          const float4 r0 = L0[j + q];
-          const float2 r1 = *reinterpret_cast<const float2 *>(&L1[j + q]);  // (c, x_e)
+          const float4 r0 = L0[js[q]];
+          const float2 r1 = *reinterpret_cast<const float2 *>(&L1[js[q]]);  // (c, x_e)
           const float dx = fx - r0.x;
           const float adx = r0.z * dx;
           const float R0 = fmaf(-adx, dx, r1.y);
@@ -159,25 +234,37 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
             mx = fmaxf(mx, t[q][k]);
           }
         }
+        if (COUNT && !(mx >= 0.0f)) {
+          uint32_t nreal = 0;
+#pragma unroll
+          for (int q = 0; q < G; ++q) nreal += js[q] != NT;
+#pragma unroll
+          for (int k = 0; k < P; ++k) tested[k] += alive[k] ? nreal : 0u;
+        }
         if (mx >= 0.0f) {
+          float4 s1v[G], s2v[G];
 #pragma unroll
           for (int q = 0; q < G; ++q) {
-            const uint32_t pos = b + j + q - start + 1;
+            s1v[q] = L1[js[q]];
+            s2v[q] = L2[js[q]];
+          }
+#pragma unroll
+          for (int q = 0; q < G; ++q) {
+            const uint32_t pos = b + (uint32_t)js[q] - start + 1;
 #pragma unroll
             for (int k = 0; k < P; ++k) {
+              if (COUNT && js[q] != NT && alive[k]) ++tested[k];
               if (t[q][k] >= 0.0f && alive[k]) {
-                const float4 r1 = L1[j + q];
-                const float a = alpha_from<KIND>(t[q][k], r1, p);
+                const float a = alpha_from<KIND>(t[q][k], s1v[q], p);
                 const float Tn = T[k] * (1.0f - a);
                 if (Tn < p.t_min) {
                   alive[k] = false;
                   nev[k] = pos;
                 } else {
-                  const float4 r2 = L2[j + q];
                   const float w = a * T[k];
-                  C0[k] = fmaf(r2.x, w, C0[k]);
-                  C1[k] = fmaf(r2.y, w, C1[k]);
-                  C2[k] = fmaf(r2.z, w, C2[k]);
+                  C0[k] = fmaf(s2v[q].x, w, C0[k]);
+                  C1[k] = fmaf(s2v[q].y, w, C1[k]);
+                  C2[k] = fmaf(s2v[q].z, w, C2[k]);
                   T[k] = Tn;
                   ++ncon[k];
                   last[k] = pos;
@@ -203,6 +290,7 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
     out.n_contrib[pix] = ncon[k];
     out.last_contrib[pix] = last[k];
     if (out.n_eval) out.n_eval[pix] = nev[k];
+    if (COUNT) out.n_tested[pix] = tested[k];
   }
 }
 

@@ -106,6 +106,7 @@ struct BlendParams {
 struct BlendOut {
   float *image, *final_T;
   uint32_t *n_contrib, *last_contrib, *n_eval;
+  uint32_t *n_tested;    // set only by the counting entry point
 };
 
 int blend_kind(const Resolved &r);

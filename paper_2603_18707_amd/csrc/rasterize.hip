@@ -2,28 +2,30 @@
 //
 // One workgroup of NT threads (64, 128 or 256: a launch parameter) per 16x16
 // tile, P = 256 / NT pixels per lane: lane l owns column l % 16 and rows
-// l / 16 + (NT / 16) k, k < P. The tile's list is walked in batches of NT;
-// each lane gathers one splat record, folds the kernel's constants into it and
-// stages it in LDS, then every lane reads the batch by broadcast, so one LDS
-// read of a record serves P pixels.
+// l / 16 + (NT / 16) k, k < P, so wave w shades rows 4w..4w+3 (+ NT/16 k).
+// The tile's list is walked in batches of NT; each lane gathers one splat
+// record, folds the kernel's constants into it and stages it in LDS, then
+// every lane reads the batch by broadcast.
 //
 // Every kernel here is decreasing in the quadric Q on the part of its support
 // that matters, so "alpha >= eps" is the same decision as "Q <= x_e", where
 // x_e is the splat's opacity threshold: the root of o' p(x) = eps for a
 // polynomial (App. B) or 2 ln(o'/eps) for the exponential (Sec. 3.2, Eq. 3).
-// The inner loop therefore computes t = x_e - Q for the four pixels (a few
-// FMAs, exact differences d = pixel - mean) and evaluates the kernel itself
-// only where t >= 0. With t:
+// The inner loop therefore computes t = x_e - Q per pixel (a few FMAs, exact
+// differences d = pixel - mean) and evaluates the kernel itself only where
+// t >= 0. With t:
 //   poly order 1:  alpha = eps + (-o' c_1) t                       (one FMA)
 //   exp:           alpha = eps * 2^(t log2(e) / 2)                 (FMA + v_exp)
 //   poly 2, 3:     alpha = o' p(x_e - t) by Horner; Q <= x_e < x_0, so the
 //                  first-root cut of Eq. 6 never applies to a passing pair.
-// Pairs below the threshold, the vast majority when splats are small, cost the
-// same for every kernel; the kernels differ in how many pairs culling leaves
-// and in the arithmetic of the pairs that blend.
 //
-// A lane's rows are NT / 16 apart, so a small splat's footprint falls in one
-// or two of its per-pixel branches and divergence stays low.
+// The region t >= 0 is an ellipse, and the tighter x_e (the point of the
+// opacity-dependent radius, Sec. 3.2) the smaller it is. While staging, each
+// record gets a conservative box around that ellipse and a bit per wave
+// telling whether the box meets the wave's rows; each wave then walks only
+// its own records, in list order, four per step with one branch per step.
+// Skipped records cannot pass, so the images are those of a walk over the
+// whole list.
 #include <cmath>
 
 #include "blend_common.h"
@@ -33,7 +35,7 @@ namespace gs {
 
 namespace {
 
-template <int KIND, int NT>
+template <int KIND, int NT, bool COUNT>
 __global__ __launch_bounds__(NT) void blend_fwd(BlendParams p, const float *__restrict__ means2d,
                                                 const float *__restrict__ conic_opacity,
                                                 const float *__restrict__ rgb, const uint32_t *__restrict__ vals,
@@ -42,25 +44,33 @@ __global__ __launch_bounds__(NT) void blend_fwd(BlendParams p, const float *__re
   const int ntiles = p.gx * p.gy;
   if ((int)blockIdx.x >= ntiles) return;
   const int tile = tile_order ? (int)min(tile_order[blockIdx.x], (uint32_t)(ntiles - 1)) : (int)blockIdx.x;
-  blend_tile<KIND, NT>(p, tile % p.gx, tile / p.gx, ranges[2 * tile], ranges[2 * tile + 1], means2d, conic_opacity,
+  blend_tile<KIND, NT, COUNT>(p, tile % p.gx, tile / p.gx, ranges[2 * tile], ranges[2 * tile + 1], means2d, conic_opacity,
                        rgb, vals, out);
+}
+
+template <int KIND, bool COUNT>
+hipError_t launch_shape(const BlendParams &p, const float *means2d, const float *conic_opacity, const float *rgb,
+                        const uint32_t *vals, const uint32_t *ranges, const uint32_t *order, BlendOut out,
+                        hipStream_t s) {
+  const dim3 grid(p.gx * p.gy);
+  if (p.threads == 64)
+    hipLaunchKernelGGL((blend_fwd<KIND, 64, COUNT>), grid, dim3(64), 0, s, p, means2d, conic_opacity, rgb, vals,
+                       ranges, order, out);
+  else if (p.threads == 128)
+    hipLaunchKernelGGL((blend_fwd<KIND, 128, COUNT>), grid, dim3(128), 0, s, p, means2d, conic_opacity, rgb, vals,
+                       ranges, order, out);
+  else
+    hipLaunchKernelGGL((blend_fwd<KIND, 256, COUNT>), grid, dim3(256), 0, s, p, means2d, conic_opacity, rgb, vals,
+                       ranges, order, out);
+  return hipGetLastError();
 }
 
 template <int KIND>
 hipError_t launch_kind(const BlendParams &p, const float *means2d, const float *conic_opacity, const float *rgb,
                        const uint32_t *vals, const uint32_t *ranges, const uint32_t *order, BlendOut out,
                        hipStream_t s) {
-  const dim3 grid(p.gx * p.gy);
-  if (p.threads == 64)
-    hipLaunchKernelGGL((blend_fwd<KIND, 64>), grid, dim3(64), 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
-                       order, out);
-  else if (p.threads == 128)
-    hipLaunchKernelGGL((blend_fwd<KIND, 128>), grid, dim3(128), 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
-                       order, out);
-  else
-    hipLaunchKernelGGL((blend_fwd<KIND, 256>), grid, dim3(256), 0, s, p, means2d, conic_opacity, rgb, vals, ranges,
-                       order, out);
-  return hipGetLastError();
+  if (out.n_tested) return launch_shape<KIND, true>(p, means2d, conic_opacity, rgb, vals, ranges, order, out, s);
+  return launch_shape<KIND, false>(p, means2d, conic_opacity, rgb, vals, ranges, order, out, s);
 }
 
 }  // namespace

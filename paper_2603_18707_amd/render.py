@@ -116,17 +116,24 @@ class Rasterizer:
             raise RuntimeError(f"gs_bin_sort reported overflow flags {flag}")
         return b
 
-    def rasterize(self, proj: dict, binned: dict, cam, want_eval: bool = False, stream=None) -> dict:
+    def rasterize(self, proj: dict, binned: dict, cam, want_eval: bool = False, stream=None,
+                  want_tested: bool = False) -> dict:
+        """gs_rasterize_fwd; with want_tested, its counting build
+        gs_rasterize_fwd_count (adds n_tested, the evaluations performed)."""
         W, H = int(cam.width), int(cam.height)
         out = dict(image=self._buf("image", (3, H, W), torch.float32),
                    final_T=self._buf("final_T", (H, W), torch.float32),
                    n_contrib=self._buf("n_contrib", (H, W), torch.int32),
                    last_contrib=self._buf("last_contrib", (H, W), torch.int32),
                    n_eval=self._buf("n_eval", (H, W), torch.int32) if want_eval else None)
-        L.gs_rasterize_fwd(L.make_camera(cam), self.kernel, self.params, proj["n"], proj["means2d"],
-                           proj["conic_opacity"], proj["rgb"], binned["vals"], binned["ranges"],
-                           binned.get("tile_order"), out["image"],
-                           out["final_T"], out["n_contrib"], out["last_contrib"], out["n_eval"], stream)
+        args = (L.make_camera(cam), self.kernel, self.params, proj["n"], proj["means2d"], proj["conic_opacity"],
+                proj["rgb"], binned["vals"], binned["ranges"], binned.get("tile_order"), out["image"],
+                out["final_T"], out["n_contrib"], out["last_contrib"], out["n_eval"])
+        if want_tested:
+            out["n_tested"] = self._buf("n_tested", (H, W), torch.int32)
+            L.gs_rasterize_fwd_count(*args, out["n_tested"], stream)
+        else:
+            L.gs_rasterize_fwd(*args, stream)
         return out
 
     def render(self, scene: DeviceScene, cam, want_eval: bool = False, stream=None) -> dict:

@@ -216,3 +216,24 @@ def test_launch_shape_does_not_change_results(kind, order, radius):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("kind,order,radius", [("poly", 1, "opacity"), ("exp", 1, "sigma3")])
+def test_counting_build_matches_and_bounds(kind, order, radius):
+    """gs_rasterize_fwd_count writes the same outputs as gs_rasterize_fwd,
+    and n_contrib <= n_tested <= n_eval per pixel, for every launch shape."""
+    scene, cam = scenes.workload_tiny()
+    scene.scales *= 2.0
+    ds = render.to_device(scene)
+    for nt in (64, 128, 256):
+        r = render.Rasterizer(H.gpu_kernel(kind, order, radius), H.gpu_params(blend_threads=nt))
+        proj = r.preprocess(ds, cam)
+        binned = r.bin_sort_fit(proj, cam)
+        a = {k: _np(v).copy() for k, v in r.rasterize(proj, binned, cam, want_eval=True).items() if v is not None}
+        b = r.rasterize(proj, binned, cam, want_eval=True, want_tested=True)
+        torch.cuda.synchronize()
+        for k in ("image", "final_T", "n_contrib", "last_contrib", "n_eval"):
+            assert np.array_equal(a[k], _np(b[k])), (nt, k)
+        tested = _np(b["n_tested"]).astype(np.int64)
+        assert np.all(tested <= a["n_eval"]) and np.all(tested >= a["n_contrib"])
+        assert tested.sum() < a["n_eval"].astype(np.int64).sum()  # the box test skips something here

@@ -76,6 +76,7 @@ def lib():
         L.gs_bin_sort_workspace.argtypes = [I64, I64, I32, P]
         L.gs_bin_sort.argtypes = [I64, P, P, P, I32, I32, I64, P, ctypes.c_size_t] + [P] * 6 + [P]
         L.gs_rasterize_fwd.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 5 + [P]
+        L.gs_rasterize_fwd_count.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 6 + [P]
         L.gs_rasterize_bwd.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 3 + [P] * 3 + [P]
         L.gs_preprocess_bwd.argtypes = [P, P, P, I64] + [P] * 5 + [I32] + [P] * 4 + [P] * 5 + [P]
         L.gs_batch_layout.argtypes = [P, I32, P, I32, I64, P, P, P, P]

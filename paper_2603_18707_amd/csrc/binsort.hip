@@ -1,19 +1,20 @@
-// Tile binning: duplication of splats per covered tile, a stable LSD radix
-// sort of the 64-bit keys (tile_id << 32) | bits(depth), and per-tile ranges.
+// Tile binning: duplication of splats per covered tile, a stable sort of the
+// 64-bit keys (tile_id << 32) | bits(depth), and per-tile ranges.
 //
-// The sort is organised around the key's structure. An LSD radix sort
-// processes the low digits first, and the 32 low bits (the depth) are the
-// same for every copy of a splat. So the depth passes run once per splat
-// (N items) instead of once per copy (K items, K ~ 2-3 N at 1080p): splats
-// are sorted by depth stably in index order, copies are emitted in that
-// order (row-major tiles within each splat), and the remaining tile digits
-// are sorted stably over the copies. The result is exactly the stable sort
-// of the copies emitted in splat-index order, because within one tile each
-// splat has at most one copy.
-//
-// A radix pass is three kernels and no workgroup ever waits on another (a
-// hand-off between workgroups costs ~0.5 us through memory, and device
-// atomics on scattered addresses cost more than the pass itself):
+// The sorted order is (tile, depth, splat index): a stable sort of the copies
+// emitted in splat-index order (tiles row-major inside each splat). It is
+// reached in two steps that each sort only what varies:
+//  1. the copies, emitted in splat-index order, are grouped by tile with a
+//     stable LSD radix sort on the ceil(log2 tiles) tile bits only (two 7-bit
+//     passes at 1080p), so inside a tile they stay in index order;
+//  2. one workgroup per tile sorts its list stably by depth bits: in LDS when
+//     it holds at most SEG_CAP copies (all lists at 1080p and 1M splats), in
+//     chunks through global memory otherwise. Keys are offset by the tile's
+//     smallest depth, so only the bits that vary inside the tile are sorted
+//     (usually 3 of 4 bytes).
+// A radix pass of step 1 is three kernels and no workgroup ever waits on
+// another (a hand-off between workgroups costs ~0.5 us through memory, and
+// device atomics on scattered addresses cost more than the pass itself):
 //  * count_pass: the key array is cut into partitions of SPART items;
 //    C[d][p] = items of digit d in partition p (LDS histogram, plain stores).
 //  * scan_rows: one workgroup per digit turns its row into output offsets:
@@ -22,12 +23,10 @@
 //  * scatter_pass: each partition ranks its items stably (per-wave ballot
 //    matching of the digit, waves in index order) and writes them at
 //    C[d][p] + rank.
-// Digit totals do not depend on the order, so one read of the depths gives
-// them for all four depth passes (with the first pass's counts), and the
-// emission kernel gives them for the tile passes; they are accumulated in 8
-// striped copies (by workgroup) so no address sees more than an eighth of the
-// workgroups. The tile passes carry each copy's depth bits with it, so the
-// last one writes the 64-bit keys without gathering the depths.
+// Digit totals do not depend on the order: the emission kernel counts them
+// as it writes the copies, in 8 striped copies (by workgroup) so no address
+// sees more than an eighth of the workgroups. Each copy carries its depth
+// bits, so no pass gathers depths.
 //
 // Every kernel sized by the key count reads it from device memory and grids
 // are sized by the key capacity, so the stage runs without a host round trip
@@ -45,9 +44,10 @@ constexpr int EIPT = 4;                 // splats per thread in an emission part
 constexpr int EPART = BS * EIPT;        // splats per emission partition
 static_assert(EPART == 1024, "the emission's binary search takes 10 steps");
 constexpr int RADIX = 256;              // max buckets per pass (8-bit digits)
-constexpr int DEPTH_PASSES = 4;
 constexpr int MAX_TILE_PASSES = 4;      // tile ids < 2^30 need at most four digits of <= 8 bits
 constexpr int STRIPES = 8;              // copies of the digit totals
+constexpr int SEG_IPT = 16;             // copies per thread in a segment sort chunk
+constexpr int SEG_CAP = BS * SEG_IPT;   // copies a workgroup sorts in LDS
 
 enum : int { CTR_KEYS = 0, CTR_SLOTS = 16 };
 
@@ -87,12 +87,6 @@ __device__ inline T block_exclusive(T v, T &total) {
   return off + inc - v;
 }
 
-// visible splats have depth >= near_z > 0, where float bits order like the
-// values; splats without tiles sort last (they emit nothing)
-__device__ inline uint32_t depth_key(const float *depth, const uint32_t *tiles, uint32_t i) {
-  return tiles[i] ? __float_as_uint(depth[i]) : 0xFFFFFFFFu;
-}
-
 // Workgroup b of a G-workgroup launch runs on XCD b % 8 (round-robin
 // dispatch). Handing each XCD a contiguous run of partitions keeps the
 // neighbouring partitions, whose outputs share cache lines at every digit
@@ -118,38 +112,6 @@ __global__ __launch_bounds__(BS) void clear_state(uint4 *__restrict__ z, size_t 
   if (i == 0) {
     *num_keys = 0;
     *overflow = 0;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// depth keys: counts of the first pass per partition, totals of all passes
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BS) void depth_count(uint32_t n, const float *__restrict__ depth,
-                                                  const uint32_t *__restrict__ tiles, uint32_t *__restrict__ c0,
-                                                  size_t c_stride, uint32_t *__restrict__ tot) {
-  __shared__ uint32_t h[BS / 64][DEPTH_PASSES * RADIX];
-  for (int j = threadIdx.x; j < (BS / 64) * DEPTH_PASSES * RADIX; j += BS) (&h[0][0])[j] = 0u;
-  __syncthreads();
-  const int w = threadIdx.x >> 6;
-  const uint64_t base = (uint64_t)blockIdx.x * SPART + threadIdx.x;
-#pragma unroll
-  for (int r = 0; r < SIPT; ++r) {
-    const uint64_t i = base + (uint64_t)r * BS;
-    if (i < n) {
-      const uint32_t k = depth_key(depth, tiles, (uint32_t)i);
-#pragma unroll
-      for (int p = 0; p < DEPTH_PASSES; ++p) atomicAdd(&h[w][p * RADIX + ((k >> (8 * p)) & 255u)], 1u);
-    }
-  }
-  __syncthreads();
-  const int stripe = blockIdx.x % STRIPES;
-  for (int j = threadIdx.x; j < DEPTH_PASSES * RADIX; j += BS) {
-    uint32_t v = 0;
-#pragma unroll
-    for (int ww = 0; ww < BS / 64; ++ww) v += h[ww][j];
-    const int p = j / RADIX, d = j % RADIX;
-    if (p == 0) c0[(size_t)d * c_stride + blockIdx.x] = v;
-    if (v) atomicAdd(total_at(tot, stripe, p, d), v);
   }
 }
 
@@ -221,35 +183,24 @@ __global__ __launch_bounds__(BS) void count_pass(const uint32_t *__restrict__ ke
 }
 
 // ---------------------------------------------------------------------------
-// one stable radix pass (uint32 key, uint32 value)
+// one stable radix pass over (tile id, splat, depth bits)
 // ---------------------------------------------------------------------------
-enum { SRC_KV = 0, SRC_DEPTH = 1 };                  // where the items come from
-enum { DST_KV = 0, DST_ORDER = 1, DST_KEYS = 2 };    // what the pass writes
-
 struct Pass {
-  const uint32_t *kin, *vin;             // SRC_KV
-  const float *depth;                    // SRC_DEPTH keys; DST_KEYS low key words
-  const uint32_t *tiles;                 // SRC_DEPTH keys; DST_ORDER copy counts
-  uint32_t n;                            // splat count (bound of the values)
-  const uint32_t *count_dev;             // item count in device memory, or NULL ...
-  uint32_t count;                        // ... for this host value
+  const uint32_t *kin, *vin, *bin;       // tile ids, splats, depth bits
+  const uint32_t *count_dev;             // item count in device memory
   int shift, nbits;                      // this pass's digit
   const uint32_t *C;                     // [digit][partition] output offsets (scan_rows)
   size_t c_stride;
-  const uint32_t *bin;                   // depth bits carried with each item (tile passes), or NULL
-  uint32_t *kout, *vout, *bout;          // DST_KV; DST_ORDER / DST_KEYS write vout
-  uint32_t *cnt_out;                     // DST_ORDER: tiles[value] at the output position
-  uint64_t *k64out;                      // DST_KEYS: (key << 32) | the carried depth bits
+  uint32_t *kout, *vout, *bout;
 };
 
 // Items of a partition are ranked in index order: wave w owns a contiguous
 // run of 64 * SIPT items, taken 64 at a time; inside a wave the rank among
 // equal digits comes from matching the digit bit by bit with ballots, plus a
 // per-wave running count per digit in LDS.
-template <int SRC, int DST>
 __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
   __shared__ uint32_t wc[BS / 64][RADIX];
-  const uint32_t K = item_count(a.count_dev, a.count);
+  const uint32_t K = *a.count_dev;
   const uint32_t nparts = (uint32_t)(((uint64_t)K + SPART - 1) / SPART);
   if (blockIdx.x >= nparts) return;  // capacity-sized grids
   const uint32_t part = xcd_partition(blockIdx.x, nparts);
@@ -265,14 +216,9 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
   for (int r = 0; r < SIPT; ++r) {
     const uint64_t idx = base + (uint64_t)r * 64;
     const bool valid = idx < K;
-    if (SRC == SRC_DEPTH) {
-      key[r] = valid ? depth_key(a.depth, a.tiles, (uint32_t)idx) : 0u;
-      val[r] = (uint32_t)idx;
-    } else {
-      key[r] = valid ? a.kin[idx] : 0u;
-      val[r] = valid ? a.vin[idx] : 0u;
-    }
-    bits[r] = (a.bin && valid) ? a.bin[idx] : 0u;
+    key[r] = valid ? a.kin[idx] : 0u;
+    val[r] = valid ? a.vin[idx] : 0u;
+    bits[r] = valid ? a.bin[idx] : 0u;
   }
 #pragma unroll
   for (int r = 0; r < SIPT; ++r) {
@@ -303,39 +249,29 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
     }
   }
   __syncthreads();
-
 #pragma unroll
   for (int r = 0; r < SIPT; ++r) {
     const uint64_t idx = base + (uint64_t)r * 64;
     if (idx >= K) break;
-    const uint32_t d = (key[r] >> a.shift) & mask;
-    const uint32_t pos = wc[w][d] + rk[r];
+    const uint32_t pos = wc[w][(key[r] >> a.shift) & mask] + rk[r];
     if (pos >= K) continue;  // unreachable when the counts are consistent
-    if (DST == DST_KV) {
-      a.kout[pos] = key[r];
-      a.vout[pos] = val[r];
-      if (a.bout) a.bout[pos] = bits[r];
-    } else if (DST == DST_ORDER) {
-      a.vout[pos] = val[r];
-      a.cnt_out[pos] = val[r] < a.n ? a.tiles[val[r]] : 0u;
-    } else {
-      a.k64out[pos] = ((uint64_t)key[r] << 32) | bits[r];
-      a.vout[pos] = val[r];
-    }
+    a.kout[pos] = key[r];
+    a.vout[pos] = val[r];
+    a.bout[pos] = bits[r];
   }
 }
 
 // ---------------------------------------------------------------------------
-// copies of the splats
+// copies of the splats, in splat-index order
 // ---------------------------------------------------------------------------
 // copies per emission partition (plain stores; no inter-workgroup traffic)
-__global__ __launch_bounds__(BS) void emit_sums(uint32_t n, const uint32_t *__restrict__ cnt,
+__global__ __launch_bounds__(BS) void emit_sums(uint32_t n, const uint32_t *__restrict__ tiles,
                                                 uint64_t *__restrict__ esum) {
   const uint64_t s0 = (uint64_t)blockIdx.x * EPART + threadIdx.x;
   uint64_t s = 0;
 #pragma unroll
   for (int j = 0; j < EIPT; ++j)
-    if (s0 + (uint64_t)j * BS < n) s += cnt[s0 + (uint64_t)j * BS];
+    if (s0 + (uint64_t)j * BS < n) s += tiles[s0 + (uint64_t)j * BS];
   uint64_t total;
   block_exclusive<uint64_t>(s, total);
   if (threadIdx.x == 0) esum[blockIdx.x] = total;
@@ -343,13 +279,13 @@ __global__ __launch_bounds__(BS) void emit_sums(uint32_t n, const uint32_t *__re
 
 struct Emit {
   uint32_t n;
-  const uint32_t *order, *cnt;           // splats in depth order and their copy counts
+  const uint32_t *tiles;                 // copies per splat (rectangle areas)
   const uint64_t *esum;                  // copies per partition
   const int32_t *rect;
+  const float *depth;
   int grid_w;
   uint64_t capacity;
   uint32_t *ctr;
-  const float *depth;
   uint32_t *tkey, *tval, *tbits;         // [capacity]: tile id, splat, depth bits
   uint32_t *tot;                         // tile digit totals [stripe][pass][digit]
   int tile_passes, tile_bits;            // digits per key and bits per digit
@@ -362,7 +298,7 @@ struct Emit {
 // consecutive keys), counting the tile digits as they are written.
 __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
   __shared__ uint32_t loff[EPART + 1];   // local exclusive offsets of the partition's splats
-  __shared__ uint32_t sidx[EPART], sbits[EPART];
+  __shared__ uint32_t sbits[EPART];
   __shared__ int32_t sx[EPART], sy[EPART], sw[EPART];
   __shared__ uint32_t th[MAX_TILE_PASSES * RADIX];
   const uint32_t nparts = (uint32_t)(((uint64_t)a.n + EPART - 1) / EPART);
@@ -377,7 +313,7 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
   uint64_t sum = 0;
 #pragma unroll
   for (int j = 0; j < EIPT; ++j) {
-    c[j] = s0 + j < a.n ? a.cnt[s0 + j] : 0u;
+    c[j] = s0 + j < a.n ? a.tiles[s0 + j] : 0u;
     sum += c[j];
   }
   uint64_t total;
@@ -395,10 +331,8 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
     loff[ls] = (uint32_t)off;  // only used when the partition fits the capacity (< 2^32)
     off += c[j];
     if (c[j]) {
-      const uint32_t i = a.order[s0 + j];
-      const int4 r = i < a.n ? reinterpret_cast<const int4 *>(a.rect)[i] : make_int4(0, 0, -1, -1);
-      sidx[ls] = i;
-      sbits[ls] = i < a.n ? __float_as_uint(a.depth[i]) : 0u;
+      const int4 r = reinterpret_cast<const int4 *>(a.rect)[s0 + j];
+      sbits[ls] = __float_as_uint(a.depth[s0 + j]);
       sx[ls] = r.x;
       sy[ls] = r.y;
       sw[ls] = r.z - r.x + 1;
@@ -424,7 +358,7 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
                           (uint32_t)(sx[lo] + (int32_t)(r - q * (uint32_t)wdt));
     const uint64_t pos = pre + k;
     a.tkey[pos] = tile;
-    a.tval[pos] = sidx[lo];
+    a.tval[pos] = (uint32_t)(part * EPART + lo);
     a.tbits[pos] = sbits[lo];
     for (int p = 0; p < a.tile_passes; ++p) atomicAdd(&th[p * RADIX + ((tile >> (p * a.tile_bits)) & dmask)], 1u);
   }
@@ -436,23 +370,24 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
   }
 }
 
-// ranges from the sorted keys
-__global__ void tile_ranges(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ctr, int64_t ntiles,
+// ranges from the tile-grouped copies
+__global__ void tile_ranges(const uint32_t *__restrict__ tkey, const uint32_t *__restrict__ ctr, int64_t ntiles,
                             uint32_t *__restrict__ ranges) {
   const uint32_t K = ctr[CTR_KEYS];
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
-  const uint32_t t = (uint32_t)(keys[k] >> 32);
+  const uint32_t t = tkey[k];
   if ((int64_t)t >= ntiles) return;
-  if (k == 0 || (uint32_t)(keys[k - 1] >> 32) != t) ranges[2 * (size_t)t] = (uint32_t)k;
-  if (k + 1 == K || (uint32_t)(keys[k + 1] >> 32) != t) ranges[2 * (size_t)t + 1] = (uint32_t)(k + 1);
+  if (k == 0 || tkey[k - 1] != t) ranges[2 * (size_t)t] = (uint32_t)k;
+  if (k + 1 == K || tkey[k + 1] != t) ranges[2 * (size_t)t + 1] = (uint32_t)(k + 1);
 }
 
 // Longest-list-first dispatch order of the tiles: tiles bucketed by list
 // length on a log scale (16 buckets per doubling, so lengths within ~4% share
 // a bucket), heaviest bucket first. A workgroup's time grows with its tile's
 // list, so starting the long lists first keeps them off the tail of the blend
-// launch. The order inside a bucket is unspecified. One workgroup.
+// (and of the segment sort). The order inside a bucket is unspecified. One
+// workgroup.
 __device__ inline int length_bucket(const uint32_t *ranges, int64_t t) {
   const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
   const int b = (int)(log2f((float)len + 1.0f) * 16.0f);
@@ -488,6 +423,220 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t *__rest
 }
 
 // ---------------------------------------------------------------------------
+// per-tile stable sort by depth bits
+// ---------------------------------------------------------------------------
+// Stable ranking of a chunk of m <= SEG_CAP items held wave-contiguously in
+// registers (item i = w * 64 * SEG_IPT + r * 64 + lane) by the 8-bit digit at
+// `shift`: rk[r] = number of the wave's earlier items with the same digit,
+// wc[w][d] += the wave's count of digit d (wc zeroed by the caller).
+__device__ inline void rank_chunk(const uint32_t (&key)[SEG_IPT], uint32_t (&rk)[SEG_IPT], uint32_t m, int shift,
+                                  uint32_t (*wc)[RADIX]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint32_t wbase = (uint32_t)w * 64u * SEG_IPT;
+#pragma unroll
+  for (int r = 0; r < SEG_IPT; ++r) {
+    if (wbase + (uint32_t)r * 64u >= m) break;  // uniform over the wave
+    const bool valid = wbase + (uint32_t)r * 64u + (uint32_t)lane < m;
+    const uint32_t d = (key[r] >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t before = wc[w][d];
+    rk[r] = before + (uint32_t)__popcll(peers & lt);
+    __builtin_amdgcn_wave_barrier();
+    if (valid && (peers & lt) == 0ull) wc[w][d] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+struct Seg {
+  const uint32_t *ranges, *order;        // order may be NULL (row-major dispatch)
+  int64_t ntiles;
+  const uint32_t *bits, *vals;           // tile-grouped copies: depth bits, splat (index order in a tile)
+  uint32_t *sbits, *svals;               // scratch with the same indexing (lists longer than SEG_CAP)
+  uint64_t *keys;                        // outputs
+  uint32_t *vout;
+};
+
+// One workgroup per tile. The keys are the depth bits minus the tile's
+// smallest one (same order, same ties), and only the bytes that vary are
+// sorted, low byte first, each pass stable.
+__global__ __launch_bounds__(BS) void segment_sort(Seg a) {
+  __shared__ uint32_t Kb[SEG_CAP], Vb[SEG_CAP];
+  __shared__ uint32_t wc[BS / 64][RADIX];
+  __shared__ uint32_t run[RADIX];
+  __shared__ uint32_t s_mn[BS / 64], s_mx[BS / 64];
+  if ((int64_t)blockIdx.x >= a.ntiles) return;
+  const uint32_t t = a.order ? min(a.order[blockIdx.x], (uint32_t)(a.ntiles - 1)) : blockIdx.x;
+  const uint32_t start = a.ranges[2 * (size_t)t], end = a.ranges[2 * (size_t)t + 1];
+  if (end <= start) return;
+  const uint32_t n = end - start;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t tkey = (uint64_t)t << 32;
+
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+  for (uint32_t i = threadIdx.x; i < n; i += BS) {
+    const uint32_t k = a.bits[start + i];
+    mn = min(mn, k);
+    mx = max(mx, k);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor((int)mn, o, 64));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+  }
+  if (lane == 0) {
+    s_mn[w] = mn;
+    s_mx[w] = mx;
+  }
+  __syncthreads();
+  mn = s_mn[0];
+  mx = s_mx[0];
+#pragma unroll
+  for (int k = 1; k < BS / 64; ++k) {
+    mn = min(mn, s_mn[k]);
+    mx = max(mx, s_mx[k]);
+  }
+  const uint32_t span = mx - mn;
+  const int passes = span ? (32 - __clz(span) + 7) / 8 : 0;
+  const uint32_t wbase = (uint32_t)w * 64u * SEG_IPT + (uint32_t)lane;
+  uint32_t key[SEG_IPT], val[SEG_IPT], rk[SEG_IPT];
+
+  if (n <= SEG_CAP) {
+#pragma unroll
+    for (int r = 0; r < SEG_IPT; ++r) {
+      const uint32_t i = wbase + (uint32_t)r * 64u;
+      key[r] = i < n ? a.bits[start + i] - mn : 0u;
+      val[r] = i < n ? a.vals[start + i] : 0u;
+    }
+    for (int p = 0; p < passes; ++p) {
+      for (int j = threadIdx.x; j < (BS / 64) * RADIX; j += BS) (&wc[0][0])[j] = 0u;
+      __syncthreads();
+      rank_chunk(key, rk, n, 8 * p, wc);
+      __syncthreads();
+      {
+        const uint32_t d = threadIdx.x;  // BS == RADIX: one digit per thread
+        uint32_t tot = 0;
+#pragma unroll
+        for (int ww = 0; ww < BS / 64; ++ww) tot += wc[ww][d];
+        uint32_t unused;
+        uint32_t r0 = block_exclusive<uint32_t>(tot, unused);
+#pragma unroll
+        for (int ww = 0; ww < BS / 64; ++ww) {
+          const uint32_t c = wc[ww][d];
+          wc[ww][d] = r0;
+          r0 += c;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < SEG_IPT; ++r) {
+        if (wbase + (uint32_t)r * 64u < n) {
+          const uint32_t pos = wc[w][(key[r] >> (8 * p)) & 255u] + rk[r];
+          if (pos < n) {  // always, when the counts are consistent
+            Kb[pos] = key[r];
+            Vb[pos] = val[r];
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < SEG_IPT; ++r) {
+        const uint32_t i = wbase + (uint32_t)r * 64u;
+        if (i < n) {
+          key[r] = Kb[i];
+          val[r] = Vb[i];
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < SEG_IPT; ++r) {
+      const uint32_t i = wbase + (uint32_t)r * 64u;
+      if (i < n) {
+        a.keys[start + i] = tkey | (uint64_t)(key[r] + mn);
+        a.vout[start + i] = val[r];
+      }
+    }
+    return;
+  }
+
+  // long list: each pass is a digit count over the whole list, then the list
+  // in order, SEG_CAP at a time, ranked in registers and written to the other
+  // buffer (the last pass writes the outputs)
+  if (passes == 0) {
+    for (uint32_t i = threadIdx.x; i < n; i += BS) {
+      a.keys[start + i] = tkey | (uint64_t)a.bits[start + i];
+      a.vout[start + i] = a.vals[start + i];
+    }
+    return;
+  }
+  for (int p = 0; p < passes; ++p) {
+    const bool first = p == 0, last = p == passes - 1;
+    const uint32_t *kin = (p & 1) ? a.sbits : a.bits;  // pass 0 reads the raw bits
+    const uint32_t *vin = (p & 1) ? a.svals : a.vals;
+    uint32_t *kout = (p & 1) ? (uint32_t *)a.bits : a.sbits;
+    uint32_t *vout = (p & 1) ? (uint32_t *)a.vals : a.svals;
+    const uint32_t sub = first ? mn : 0u;
+    if (threadIdx.x < RADIX) run[threadIdx.x] = 0u;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += BS) atomicAdd(&run[((kin[start + i] - sub) >> (8 * p)) & 255u], 1u);
+    __syncthreads();
+    {
+      uint32_t unused;
+      const uint32_t excl = block_exclusive<uint32_t>(run[threadIdx.x], unused);
+      __syncthreads();
+      run[threadIdx.x] = excl;
+    }
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < n; c0 += SEG_CAP) {
+      const uint32_t m = min((uint32_t)SEG_CAP, n - c0);
+#pragma unroll
+      for (int r = 0; r < SEG_IPT; ++r) {
+        const uint32_t i = wbase + (uint32_t)r * 64u;
+        key[r] = i < m ? kin[start + c0 + i] - sub : 0u;
+        val[r] = i < m ? vin[start + c0 + i] : 0u;
+      }
+      for (int j = threadIdx.x; j < (BS / 64) * RADIX; j += BS) (&wc[0][0])[j] = 0u;
+      __syncthreads();
+      rank_chunk(key, rk, m, 8 * p, wc);
+      __syncthreads();
+      {
+        const uint32_t d = threadIdx.x;
+        uint32_t r0 = run[d];
+#pragma unroll
+        for (int ww = 0; ww < BS / 64; ++ww) {
+          const uint32_t c = wc[ww][d];
+          wc[ww][d] = r0;
+          r0 += c;
+        }
+        run[d] = r0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < SEG_IPT; ++r) {
+        if (wbase + (uint32_t)r * 64u < m) {
+          const uint32_t pos = wc[w][(key[r] >> (8 * p)) & 255u] + rk[r];
+          if (pos >= n) continue;  // unreachable when the counts are consistent
+          if (last) {
+            a.keys[start + pos] = tkey | (uint64_t)(key[r] + mn);
+            a.vout[start + pos] = val[r];
+          } else {
+            kout[start + pos] = key[r];
+            vout[start + pos] = val[r];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // workspace
 // ---------------------------------------------------------------------------
 struct TilePlan {
@@ -504,18 +653,15 @@ TilePlan tile_plan(int64_t ntiles) {
 }
 
 struct Workspace {
-  uint32_t *dk0, *dv0, *dk1, *dv1;       // depth sort ping-pong [n]
-  uint32_t *order, *cnt;                 // splats in depth order, their copy counts [n]
   uint64_t *esum;                        // copies per emission partition
-  uint32_t *tk0, *tv0, *tb0, *tk1, *tv1, *tb1;   // tile sort ping-pong [capacity]
-  uint32_t *dC;                          // depth passes' counts [pass][256][depth partitions]
+  uint32_t *tk[2], *tv[2], *tb[2];       // tile passes ping-pong [capacity]: tile id, splat, depth bits
   uint32_t *tC;                          // tile passes' counts [pass][1 << bits][key partitions]
   // zeroed at the start of every call, contiguous:
   uint32_t *ctr;                         // counters
-  uint32_t *dtot, *ttot;                 // digit totals [stripe][pass][256]
+  uint32_t *ttot;                        // tile digit totals [stripe][pass][256]
   void *zero_begin;
   size_t zero_bytes;
-  size_t dstride, tstride;               // partitions per row
+  size_t tstride;                        // partitions per row
 };
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -531,26 +677,16 @@ size_t carve(void *base, int64_t n, int64_t cap, int64_t ntiles, Workspace *w) {
     return r;
   };
   Workspace t;
-  t.dk0 = (uint32_t *)take(4 * N);
-  t.dv0 = (uint32_t *)take(4 * N);
-  t.dk1 = (uint32_t *)take(4 * N);
-  t.dv1 = (uint32_t *)take(4 * N);
-  t.order = (uint32_t *)take(4 * N);
-  t.cnt = (uint32_t *)take(4 * N);
   t.esum = (uint64_t *)take(8 * (size_t)ceil_div((int64_t)N, EPART));
-  t.tk0 = (uint32_t *)take(4 * C);
-  t.tv0 = (uint32_t *)take(4 * C);
-  t.tb0 = (uint32_t *)take(4 * C);
-  t.tk1 = (uint32_t *)take(4 * C);
-  t.tv1 = (uint32_t *)take(4 * C);
-  t.tb1 = (uint32_t *)take(4 * C);
-  t.dstride = (size_t)ceil_div((int64_t)N, SPART);
-  t.dC = (uint32_t *)take(4 * (size_t)DEPTH_PASSES * RADIX * t.dstride);
+  for (int b = 0; b < 2; ++b) {
+    t.tk[b] = (uint32_t *)take(4 * C);
+    t.tv[b] = (uint32_t *)take(4 * C);
+    t.tb[b] = (uint32_t *)take(4 * C);
+  }
   t.tstride = (size_t)ceil_div((int64_t)C, SPART);
   t.tC = (uint32_t *)take(4 * ((size_t)tp.passes << tp.bits) * t.tstride);
   const size_t z0 = o;
   t.ctr = (uint32_t *)take(4 * CTR_SLOTS);
-  t.dtot = (uint32_t *)take(4 * (size_t)STRIPES * MAX_TILE_PASSES * RADIX);
   t.ttot = (uint32_t *)take(4 * (size_t)STRIPES * MAX_TILE_PASSES * RADIX);
   t.zero_begin = p ? (void *)(p + z0) : nullptr;
   t.zero_bytes = o - z0;
@@ -572,7 +708,6 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
   Workspace w;
   carve(ws, n, capacity, ntiles, &w);
   const TilePlan tp = tile_plan(ntiles);
-  const size_t dpass = (size_t)RADIX * w.dstride;             // one depth pass's counts
   const size_t tpass = ((size_t)1 << tp.bits) * w.tstride;    // one tile pass's counts
 
   // 0. zero totals, counters and ranges; num_keys = overflow = 0
@@ -583,63 +718,22 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
     hipLaunchKernelGGL(clear_state, dim3(grid), dim3(BS), 0, s, (uint4 *)w.zero_begin, nz16, ranges, nr, num_keys,
                        overflow);
   }
-
   if (n > 0) {
-    // 1. depth keys: first pass's counts, all passes' totals
-    const unsigned dgrid = ceil_div(n, SPART);
-    hipLaunchKernelGGL(depth_count, dim3(dgrid), dim3(BS), 0, s, (uint32_t)n, depth, tiles, w.dC, w.dstride,
-                       w.dtot);
-    // 2. splats by depth (stable, index order on ties): four 8-bit passes; the
-    //    last writes the order and each splat's copy count
-    Pass a{};
-    a.depth = depth;
-    a.tiles = tiles;
-    a.n = (uint32_t)n;
-    a.count = (uint32_t)n;
-    a.nbits = 8;
-    a.c_stride = w.dstride;
-    a.cnt_out = w.cnt;
-    uint32_t *kin = nullptr, *vin = nullptr, *kb = w.dk0, *vb = w.dv0, *ka = w.dk1, *va = w.dv1;
-    for (int pass = 0; pass < DEPTH_PASSES; ++pass) {
-      uint32_t *Cp = w.dC + pass * dpass;
-      if (pass > 0)
-        hipLaunchKernelGGL(count_pass, dim3(dgrid), dim3(BS), 0, s, (const uint32_t *)kin, (const uint32_t *)nullptr,
-                           (uint32_t)n, 8 * pass, 8, Cp, w.dstride);
-      hipLaunchKernelGGL(scan_rows, dim3(RADIX), dim3(BS), 0, s, Cp, w.dstride, (const uint32_t *)nullptr,
-                         (uint32_t)n, (const uint32_t *)w.dtot, pass);
-      a.kin = kin;
-      a.vin = vin;
-      a.shift = 8 * pass;
-      a.C = Cp;
-      a.kout = kb;
-      a.vout = pass == DEPTH_PASSES - 1 ? w.order : vb;
-      if (pass == 0)
-        hipLaunchKernelGGL((scatter_pass<SRC_DEPTH, DST_KV>), dim3(dgrid), dim3(BS), 0, s, a);
-      else if (pass < DEPTH_PASSES - 1)
-        hipLaunchKernelGGL((scatter_pass<SRC_KV, DST_KV>), dim3(dgrid), dim3(BS), 0, s, a);
-      else
-        hipLaunchKernelGGL((scatter_pass<SRC_KV, DST_ORDER>), dim3(dgrid), dim3(BS), 0, s, a);
-      kin = kb;
-      vin = vb;
-      uint32_t *tk = ka, *tv = va;
-      ka = kb; va = vb; kb = tk; vb = tv;
-    }
-    // 3. copies in depth order with their depth bits, the tile passes' totals, K
+    // 1. copies in splat-index order with their depth bits, the tile digit totals, K
     const unsigned egrid = ceil_div(n, EPART);
-    hipLaunchKernelGGL(emit_sums, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, (const uint32_t *)w.cnt, w.esum);
+    hipLaunchKernelGGL(emit_sums, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, tiles, w.esum);
     Emit e{};
     e.n = (uint32_t)n;
-    e.order = w.order;
-    e.cnt = w.cnt;
+    e.tiles = tiles;
     e.esum = w.esum;
     e.rect = rect;
+    e.depth = depth;
     e.grid_w = grid_w;
     e.capacity = (uint64_t)capacity;
     e.ctr = w.ctr;
-    e.depth = depth;
-    e.tkey = w.tk0;
-    e.tval = w.tv0;
-    e.tbits = w.tb0;
+    e.tkey = w.tk[0];
+    e.tval = w.tv[0];
+    e.tbits = w.tb[0];
     e.tot = w.ttot;
     e.tile_passes = tp.passes;
     e.tile_bits = tp.bits;
@@ -651,42 +745,49 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
   if (err != hipSuccess) return err;
 
   if (capacity > 0 && n > 0) {
-    // 4. stable passes over the tile digits; the last writes the 64-bit keys
+    // 2. stable passes over the tile digits
     const unsigned kgrid = ceil_div(capacity, SPART);
-    Pass a{};
-    a.depth = depth;
-    a.n = (uint32_t)n;
-    a.count_dev = w.ctr + CTR_KEYS;
-    a.nbits = tp.bits;
-    a.c_stride = w.tstride;
-    uint32_t *ka = w.tk0, *va = w.tv0, *ba = w.tb0, *kb = w.tk1, *vb = w.tv1, *bb = w.tb1;
+    const uint32_t *count_dev = w.ctr + CTR_KEYS;
+    int cur = 0;
     for (int pass = 0; pass < tp.passes; ++pass) {
-      const bool last = pass == tp.passes - 1;
       uint32_t *Cp = w.tC + pass * tpass;
-      hipLaunchKernelGGL(count_pass, dim3(kgrid), dim3(BS), 0, s, (const uint32_t *)ka, a.count_dev, 0u,
+      hipLaunchKernelGGL(count_pass, dim3(kgrid), dim3(BS), 0, s, (const uint32_t *)w.tk[cur], count_dev, 0u,
                          tp.bits * pass, tp.bits, Cp, w.tstride);
-      hipLaunchKernelGGL(scan_rows, dim3(1u << tp.bits), dim3(BS), 0, s, Cp, w.tstride, a.count_dev, 0u,
+      hipLaunchKernelGGL(scan_rows, dim3(1u << tp.bits), dim3(BS), 0, s, Cp, w.tstride, count_dev, 0u,
                          (const uint32_t *)w.ttot, pass);
-      a.kin = ka;
-      a.vin = va;
-      a.bin = ba;
+      Pass a{};
+      a.kin = w.tk[cur];
+      a.vin = w.tv[cur];
+      a.bin = w.tb[cur];
+      a.count_dev = count_dev;
       a.shift = tp.bits * pass;
+      a.nbits = tp.bits;
       a.C = Cp;
-      a.kout = kb;
-      a.vout = last ? vals : vb;
-      a.bout = bb;
-      a.k64out = keys;
-      if (last)
-        hipLaunchKernelGGL((scatter_pass<SRC_KV, DST_KEYS>), dim3(kgrid), dim3(BS), 0, s, a);
-      else
-        hipLaunchKernelGGL((scatter_pass<SRC_KV, DST_KV>), dim3(kgrid), dim3(BS), 0, s, a);
-      uint32_t *tk = ka, *tv = va, *tb = ba;
-      ka = kb; va = vb; ba = bb; kb = tk; vb = tv; bb = tb;
+      a.c_stride = w.tstride;
+      a.kout = w.tk[cur ^ 1];
+      a.vout = w.tv[cur ^ 1];
+      a.bout = w.tb[cur ^ 1];
+      hipLaunchKernelGGL(scatter_pass, dim3(kgrid), dim3(BS), 0, s, a);
+      cur ^= 1;
     }
-    // 5. per-tile ranges
-    hipLaunchKernelGGL(tile_ranges, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, keys, w.ctr, ntiles, ranges);
+    // 3. per-tile ranges, longest-first order, then each tile's list by depth
+    hipLaunchKernelGGL(tile_ranges, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, (const uint32_t *)w.tk[cur],
+                       count_dev, ntiles, ranges);
+    if (tile_order) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order);
+    Seg g{};
+    g.ranges = ranges;
+    g.order = tile_order;
+    g.ntiles = ntiles;
+    g.bits = w.tb[cur];
+    g.vals = w.tv[cur];
+    g.sbits = w.tb[cur ^ 1];
+    g.svals = w.tv[cur ^ 1];
+    g.keys = keys;
+    g.vout = vals;
+    hipLaunchKernelGGL(segment_sort, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
+    return hipGetLastError();
   }
-  // 6. longest-first dispatch order for the blend
+  // nothing emitted (or no room): ranges stay zero
   if (tile_order) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order);
   return hipGetLastError();
 }

@@ -112,7 +112,7 @@ __device__ inline void pass_box(const float4 &s0, const float4 &s1, float &hx, f
 // (pointers to this image's planes). Called by NT threads of a workgroup.
 //
 // Splats are staged NT at a time. Each staged record gets a bit per wave of
-// the workgroup telling whether its pass box meets the rows that wave
+// the workgroup telling whether its pass box meets the pixel block that wave
 // shades; every wave then walks a compacted list of its records, still in
 // list order, so splats that cannot reach a wave's pixels cost it nothing.
 //
@@ -125,17 +125,23 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
                                   const float *__restrict__ rgb, const uint32_t *__restrict__ vals,
                                   const BlendOut &out) {
   constexpr int P = TS * TS / NT;   // pixels per lane
-  constexpr int RS = NT / TS;       // row stride between a lane's pixels
   constexpr int NW = NT / WAVE;     // waves per workgroup
-  constexpr int G = 4;              // splats tested per step
+  // each wave shades a WX x WY block of the tile (8x8 of 4 waves, 8x16 of 2,
+  // the whole tile for 1): compact blocks meet fewer splat boxes than strips
+  constexpr int WX = NW == 1 ? 16 : 8;
+  constexpr int WY = TS * TS / NW / WX;
+  constexpr int RS = WAVE / WX;     // row stride between a lane's pixels
+  constexpr int G = 8;              // splats tested per step
   static_assert(NT % G == 0, "a staged batch holds whole steps");
   __shared__ float4 L0[NT + 1], L1[NT + 1], L2[NT + 1];   // slot NT: neutral record
   __shared__ uint16_t lst[NW][NT + G];
   __shared__ uint32_t wcnt[NW][NW];                      // [staging wave][shading wave]
   const int lane = threadIdx.x, wv = lane / WAVE;
   const uint64_t lt = (1ull << (lane & (WAVE - 1))) - 1ull;
-  const int px = tx * TS + (lane & (TS - 1));
-  const int py0 = ty * TS + lane / TS;
+  const int wx0 = (wv % (TS / WX)) * WX, wy0 = (wv / (TS / WX)) * WY;
+  const int l64 = lane & (WAVE - 1);
+  const int px = tx * TS + wx0 + l64 % WX;
+  const int py0 = ty * TS + wy0 + l64 / WX;
   const float fx = (float)px + 0.5f;
   float fy[P], T[P], C0[P], C1[P], C2[P];
   uint32_t ncon[P], last[P], nev[P], tested[P];
@@ -177,15 +183,12 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
       L2[lane] = a2;
       float hx, hy;
       pass_box(a0, a1, hx, hy);
-      if (a0.x + hx >= tile_x0 && a0.x - hx <= tile_x0 + (TS - 1)) {
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
-#pragma unroll
-          for (int k = 0; k < P; ++k) {
-            const float r0 = tile_y0 + (float)(4 * w + RS * k);   // the wave's 4 rows for pixel k
-            if (a0.y + hy >= r0 && a0.y - hy <= r0 + 3.0f) mask |= 1u << w;
-          }
-        }
+      for (int w = 0; w < NW; ++w) {
+        const float bx = tile_x0 + (float)((w % (TS / WX)) * WX), by = tile_y0 + (float)((w / (TS / WX)) * WY);
+        if (a0.x + hx >= bx && a0.x - hx <= bx + (float)(WX - 1) && a0.y + hy >= by &&
+            a0.y - hy <= by + (float)(WY - 1))
+          mask |= 1u << w;
       }
     }
     uint64_t bal[NW];

@@ -1,11 +1,12 @@
 // Front-to-back blending of the sorted per-tile splat lists.
 //
 // One workgroup of NT threads (64, 128 or 256: a launch parameter) per 16x16
-// tile, P = 256 / NT pixels per lane: lane l owns column l % 16 and rows
-// l / 16 + (NT / 16) k, k < P, so wave w shades rows 4w..4w+3 (+ NT/16 k).
-// The tile's list is walked in batches of NT; each lane gathers one splat
-// record, folds the kernel's constants into it and stages it in LDS, then
-// every lane reads the batch by broadcast.
+// tile, P = 256 / NT pixels per lane. Each wave shades a compact block of the
+// tile (an 8x8 quarter with 256 threads, an 8x16 half with 128, the whole
+// tile with 64); a lane's P pixels share a column. The tile's list is walked
+// in batches of NT; each lane gathers one splat record, folds the kernel's
+// constants into it and stages it in LDS, then every lane reads the batch by
+// broadcast.
 //
 // Every kernel here is decreasing in the quadric Q on the part of its support
 // that matters, so "alpha >= eps" is the same decision as "Q <= x_e", where
@@ -22,8 +23,8 @@
 // The region t >= 0 is an ellipse, and the tighter x_e (the point of the
 // opacity-dependent radius, Sec. 3.2) the smaller it is. While staging, each
 // record gets a conservative box around that ellipse and a bit per wave
-// telling whether the box meets the wave's rows; each wave then walks only
-// its own records, in list order, four per step with one branch per step.
+// telling whether the box meets the wave's pixel block; each wave then walks
+// only its own records, in list order, eight per step with one branch per step.
 // Skipped records cannot pass, so the images are those of a walk over the
 // whole list.
 #include <cmath>

@@ -27,6 +27,22 @@ def test_exports_every_declared_symbol():
     assert "gfx950" in L.gs_version()
 
 
+def test_every_entry_point_with_parameters_declares_them():
+    """ctypes passes undeclared arguments as C int: a pointer or stream would
+    be truncated to 32 bits. Every binding declares its parameter types, and
+    their count matches the header's prototype."""
+    lib = L.lib()
+    src = open(os.path.join(ROOT, "include", "gs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    for name in L.EXPORTS:
+        proto = re.search(r"\b" + name + r"\s*\(([^)]*)\)", src).group(1).strip()
+        nparams = 0 if proto in ("", "void") else proto.count(",") + 1
+        if nparams == 0:
+            continue
+        argtypes = getattr(lib, name).argtypes
+        assert argtypes is not None and len(argtypes) == nparams, (name, nparams, argtypes)
+
+
 def test_default_coefficients():
     k1 = L.gs_kernel_default(L.KERNEL_POLY, 1, L.RADIUS_POLY_OPACITY)
     assert k1.coeffs[0] == 0.773 and abs(L.gs_kernel_root(k1) - 4.386) < 1e-12
@@ -113,8 +129,9 @@ def test_device_calls_reject_bad_arguments_on_host():
 def test_workspace_grows_with_sizes():
     a = L.gs_bin_sort_workspace(1000, 10000, 64)
     b = L.gs_bin_sort_workspace(1000, 20000, 64)
-    c = L.gs_bin_sort_workspace(2000, 10000, 64)
-    assert 0 < a < b and a < c
+    c = L.gs_bin_sort_workspace(1_000_000, 10000, 64)
+    d = L.gs_bin_sort_workspace(1000, 10000, 1 << 20)
+    assert 0 < a < b and a < c and a < d
 
 
 def test_struct_layouts_match_the_header(tmp_path):

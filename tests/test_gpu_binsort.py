@@ -2,8 +2,9 @@
 binning (oracle.binning), bit for bit: keys, values, tile ranges and the key
 count, on seeded synthetic rectangles and depths (scenes.binning_inputs) with
 depth ties, culled splats and splats spanning up to the whole grid. Grid
-shapes cover one, two and four tile-digit passes; capacities cover the exact
-fit, one short (overflow) and zero.
+shapes cover one, two and four tile-digit passes and per-tile lists longer
+than one LDS chunk; capacities cover the exact fit, one short (overflow) and
+zero.
 """
 import numpy as np
 import pytest
@@ -48,6 +49,8 @@ CASES = [  # n, grid_w, grid_h, seed, share of big splats
     (20_000, 200, 1, 5, 0.003),       # 8 tile bits: the emitted copies go straight to the last pass
     (20_000, 300, 1, 6, 0.003),       # 9 tile bits: two 5-bit passes
     (3000, 8192, 2100, 7, 0.0),       # 25 tile bits: four 7-bit passes
+    (20_000, 4, 4, 11, 0.0),          # lists up to ~6k: longer than a workgroup sorts in LDS
+    (60_000, 3, 2, 12, 0.0),          # lists up to ~29k: many chunks per depth pass
 ]
 
 

@@ -8,7 +8,7 @@
 //     stable LSD radix sort on the ceil(log2 tiles) tile bits only (two 7-bit
 //     passes at 1080p), so inside a tile they stay in index order;
 //  2. one workgroup per tile sorts its list stably by depth bits: in LDS when
-//     it holds at most SEG_CAP copies (all lists at 1080p and 1M splats), in
+//     it holds at most 4096 copies (all lists at 1080p and 1M splats), in
 //     chunks through global memory otherwise. Keys are offset by the tile's
 //     smallest depth, so only the bits that vary inside the tile are sorted
 //     (usually 3 of 4 bytes).
@@ -46,8 +46,8 @@ static_assert(EPART == 1024, "the emission's binary search takes 10 steps");
 constexpr int RADIX = 256;              // max buckets per pass (8-bit digits)
 constexpr int MAX_TILE_PASSES = 4;      // tile ids < 2^30 need at most four digits of <= 8 bits
 constexpr int STRIPES = 8;              // copies of the digit totals
-constexpr int SEG_IPT = 16;             // copies per thread in a segment sort chunk
-constexpr int SEG_CAP = BS * SEG_IPT;   // copies a workgroup sorts in LDS
+constexpr int SHORT_IPT = 4;            // copies per thread when sorting short lists (<= 1024)
+constexpr int LONG_IPT = 16;            // copies per thread in a chunk of a long list (4096)
 
 enum : int { CTR_KEYS = 0, CTR_SLOTS = 16 };
 
@@ -425,32 +425,38 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t *__rest
 // ---------------------------------------------------------------------------
 // per-tile stable sort by depth bits
 // ---------------------------------------------------------------------------
-// Stable ranking of a chunk of m <= SEG_CAP items held wave-contiguously in
-// registers (item i = w * 64 * SEG_IPT + r * 64 + lane) by the 8-bit digit at
-// `shift`: rk[r] = number of the wave's earlier items with the same digit,
-// wc[w][d] += the wave's count of digit d (wc zeroed by the caller).
-__device__ inline void rank_chunk(const uint32_t (&key)[SEG_IPT], uint32_t (&rk)[SEG_IPT], uint32_t m, int shift,
+// Stable ranking of a chunk of m <= BS * IPT items held wave-contiguously in
+// registers (item i = w * 64 * R + r * 64 + lane, R = ceil(m / 256) rounds,
+// so every wave holds a share) by the 8-bit digit at `shift`: rk[r] = number
+// of the wave's earlier items with the same digit, wc[w][d] += the wave's
+// count of digit d (wc zeroed by the caller).
+__device__ inline uint32_t chunk_rounds(uint32_t m) { return (m + BS - 1) / BS; }
+
+template <int IPT>
+__device__ inline void rank_chunk(const uint32_t (&key)[IPT], uint32_t (&rk)[IPT], uint32_t m, int shift,
                                   uint32_t (*wc)[RADIX]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = (1ull << lane) - 1ull;
-  const uint32_t wbase = (uint32_t)w * 64u * SEG_IPT;
+  const uint32_t R = chunk_rounds(m);
+  const uint32_t wbase = (uint32_t)w * 64u * R;
 #pragma unroll
-  for (int r = 0; r < SEG_IPT; ++r) {
-    if (wbase + (uint32_t)r * 64u >= m) break;  // uniform over the wave
-    const bool valid = wbase + (uint32_t)r * 64u + (uint32_t)lane < m;
-    const uint32_t d = (key[r] >> shift) & 255u;
-    uint64_t peers = __ballot(valid);
+  for (int r = 0; r < IPT; ++r) {
+    if ((uint32_t)r < R && wbase + (uint32_t)r * 64u < m) {  // uniform over the wave
+      const bool valid = wbase + (uint32_t)r * 64u + (uint32_t)lane < m;
+      const uint32_t d = (key[r] >> shift) & 255u;
+      uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      peers &= bit ? bb : ~bb;
+      for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t bb = __ballot(bit);
+        peers &= bit ? bb : ~bb;
+      }
+      const uint32_t before = wc[w][d];
+      rk[r] = before + (uint32_t)__popcll(peers & lt);
+      __builtin_amdgcn_wave_barrier();
+      if (valid && (peers & lt) == 0ull) wc[w][d] = before + (uint32_t)__popcll(peers);
+      __builtin_amdgcn_wave_barrier();
     }
-    const uint32_t before = wc[w][d];
-    rk[r] = before + (uint32_t)__popcll(peers & lt);
-    __builtin_amdgcn_wave_barrier();
-    if (valid && (peers & lt) == 0ull) wc[w][d] = before + (uint32_t)__popcll(peers);
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -458,15 +464,24 @@ struct Seg {
   const uint32_t *ranges, *order;        // order may be NULL (row-major dispatch)
   int64_t ntiles;
   const uint32_t *bits, *vals;           // tile-grouped copies: depth bits, splat (index order in a tile)
-  uint32_t *sbits, *svals;               // scratch with the same indexing (lists longer than SEG_CAP)
+  uint32_t *sbits, *svals;               // scratch with the same indexing (lists longer than 4096)
   uint64_t *keys;                        // outputs
   uint32_t *vout;
 };
 
-// One workgroup per tile. The keys are the depth bits minus the tile's
-// smallest one (same order, same ties), and only the bytes that vary are
-// sorted, low byte first, each pass stable.
+// One workgroup per tile: a stable LSD radix sort of the tile's list by depth
+// bits. The keys are the depth bits minus the tile's smallest one (same
+// order, same ties), and only the bytes that vary are sorted, low byte
+// first, with the list spread over all four waves (ceil(n / 256) rounds of
+// 64 per wave). IPT = SHORT_IPT sorts the lists of at most 1024 copies
+// (nearly all of them) with little LDS and few registers, so many tiles run
+// per CU; IPT = LONG_IPT takes the longer ones: in LDS up to 4096 copies,
+// beyond that chunk by chunk through global memory.
+template <int IPT>
 __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
+  constexpr int SEG_IPT = IPT;
+  constexpr int SEG_CAP = BS * IPT;
+  constexpr bool SHORT = IPT == SHORT_IPT;
   __shared__ uint32_t Kb[SEG_CAP], Vb[SEG_CAP];
   __shared__ uint32_t wc[BS / 64][RADIX];
   __shared__ uint32_t run[RADIX];
@@ -475,6 +490,7 @@ __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
   const uint32_t t = a.order ? min(a.order[blockIdx.x], (uint32_t)(a.ntiles - 1)) : blockIdx.x;
   const uint32_t start = a.ranges[2 * (size_t)t], end = a.ranges[2 * (size_t)t + 1];
   if (end <= start) return;
+  if (SHORT != (end - start <= (uint32_t)(BS * SHORT_IPT))) return;  // the other instance sorts it
   const uint32_t n = end - start;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t tkey = (uint64_t)t << 32;
@@ -504,20 +520,22 @@ __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
   }
   const uint32_t span = mx - mn;
   const int passes = span ? (32 - __clz(span) + 7) / 8 : 0;
-  const uint32_t wbase = (uint32_t)w * 64u * SEG_IPT + (uint32_t)lane;
   uint32_t key[SEG_IPT], val[SEG_IPT], rk[SEG_IPT];
 
   if (n <= SEG_CAP) {
+    const uint32_t R = chunk_rounds(n);
+    const uint32_t wbase = (uint32_t)w * 64u * R + (uint32_t)lane;
 #pragma unroll
     for (int r = 0; r < SEG_IPT; ++r) {
       const uint32_t i = wbase + (uint32_t)r * 64u;
-      key[r] = i < n ? a.bits[start + i] - mn : 0u;
-      val[r] = i < n ? a.vals[start + i] : 0u;
+      const bool mine = (uint32_t)r < R && i < n;
+      key[r] = mine ? a.bits[start + i] - mn : 0u;
+      val[r] = mine ? a.vals[start + i] : 0u;
     }
     for (int p = 0; p < passes; ++p) {
       for (int j = threadIdx.x; j < (BS / 64) * RADIX; j += BS) (&wc[0][0])[j] = 0u;
       __syncthreads();
-      rank_chunk(key, rk, n, 8 * p, wc);
+      rank_chunk<IPT>(key, rk, n, 8 * p, wc);
       __syncthreads();
       {
         const uint32_t d = threadIdx.x;  // BS == RADIX: one digit per thread
@@ -536,7 +554,7 @@ __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < SEG_IPT; ++r) {
-        if (wbase + (uint32_t)r * 64u < n) {
+        if ((uint32_t)r < R && wbase + (uint32_t)r * 64u < n) {
           const uint32_t pos = wc[w][(key[r] >> (8 * p)) & 255u] + rk[r];
           if (pos < n) {  // always, when the counts are consistent
             Kb[pos] = key[r];
@@ -548,7 +566,7 @@ __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
 #pragma unroll
       for (int r = 0; r < SEG_IPT; ++r) {
         const uint32_t i = wbase + (uint32_t)r * 64u;
-        if (i < n) {
+        if ((uint32_t)r < R && i < n) {
           key[r] = Kb[i];
           val[r] = Vb[i];
         }
@@ -557,7 +575,7 @@ __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
 #pragma unroll
     for (int r = 0; r < SEG_IPT; ++r) {
       const uint32_t i = wbase + (uint32_t)r * 64u;
-      if (i < n) {
+      if ((uint32_t)r < R && i < n) {
         a.keys[start + i] = tkey | (uint64_t)(key[r] + mn);
         a.vout[start + i] = val[r];
       }
@@ -565,6 +583,7 @@ __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
     return;
   }
 
+  if (SHORT) return;  // not reached: short lists fit in LDS
   // long list: each pass is a digit count over the whole list, then the list
   // in order, SEG_CAP at a time, ranked in registers and written to the other
   // buffer (the last pass writes the outputs)
@@ -595,15 +614,18 @@ __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
     __syncthreads();
     for (uint32_t c0 = 0; c0 < n; c0 += SEG_CAP) {
       const uint32_t m = min((uint32_t)SEG_CAP, n - c0);
+      const uint32_t R = chunk_rounds(m);
+      const uint32_t wbase = (uint32_t)w * 64u * R + (uint32_t)lane;
 #pragma unroll
       for (int r = 0; r < SEG_IPT; ++r) {
         const uint32_t i = wbase + (uint32_t)r * 64u;
-        key[r] = i < m ? kin[start + c0 + i] - sub : 0u;
-        val[r] = i < m ? vin[start + c0 + i] : 0u;
+        const bool mine = (uint32_t)r < R && i < m;
+        key[r] = mine ? kin[start + c0 + i] - sub : 0u;
+        val[r] = mine ? vin[start + c0 + i] : 0u;
       }
       for (int j = threadIdx.x; j < (BS / 64) * RADIX; j += BS) (&wc[0][0])[j] = 0u;
       __syncthreads();
-      rank_chunk(key, rk, m, 8 * p, wc);
+      rank_chunk<IPT>(key, rk, m, 8 * p, wc);
       __syncthreads();
       {
         const uint32_t d = threadIdx.x;
@@ -619,7 +641,7 @@ __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < SEG_IPT; ++r) {
-        if (wbase + (uint32_t)r * 64u < m) {
+        if ((uint32_t)r < R && wbase + (uint32_t)r * 64u < m) {
           const uint32_t pos = wc[w][(key[r] >> (8 * p)) & 255u] + rk[r];
           if (pos >= n) continue;  // unreachable when the counts are consistent
           if (last) {
@@ -784,7 +806,8 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
     g.svals = w.tv[cur ^ 1];
     g.keys = keys;
     g.vout = vals;
-    hipLaunchKernelGGL(segment_sort, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
+    hipLaunchKernelGGL(segment_sort<SHORT_IPT>, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
+    hipLaunchKernelGGL(segment_sort<LONG_IPT>, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
     return hipGetLastError();
   }
   // nothing emitted (or no room): ranges stay zero

@@ -44,6 +44,7 @@ constexpr int EIPT = 4;                 // splats per thread in an emission part
 constexpr int EPART = BS * EIPT;        // splats per emission partition
 static_assert(EPART == 1024, "the emission's binary search takes 10 steps");
 constexpr int RADIX = 256;              // max buckets per pass (8-bit digits)
+static_assert(BS == RADIX, "per-digit steps give one digit to each thread");
 constexpr int MAX_TILE_PASSES = 4;      // tile ids < 2^30 need at most four digits of <= 8 bits
 constexpr int STRIPES = 8;              // copies of the digit totals
 constexpr int SHORT_IPT = 4;            // copies per thread when sorting short lists (<= 1024)
@@ -200,6 +201,8 @@ struct Pass {
 // per-wave running count per digit in LDS.
 __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
   __shared__ uint32_t wc[BS / 64][RADIX];
+  __shared__ uint32_t goff[RADIX];
+  __shared__ uint32_t Ks[SPART], Vs[SPART], Bs[SPART];
   const uint32_t K = *a.count_dev;
   const uint32_t nparts = (uint32_t)(((uint64_t)K + SPART - 1) / SPART);
   if (blockIdx.x >= nparts) return;  // capacity-sized grids
@@ -237,36 +240,77 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // per digit: where each wave's items start in the output
-  if (threadIdx.x < R) {
-    const uint32_t d = threadIdx.x;
-    uint32_t run = a.C[(size_t)d * a.c_stride + part];
+  // The partition's items are first placed in digit order in LDS, then
+  // written out by consecutive threads: item i of the staged order goes to
+  // goff[d] + i, so every digit run leaves as one contiguous burst instead of
+  // one scattered 4-byte store per item.
+  {
+    const uint32_t d = threadIdx.x;  // BS == RADIX: one digit per thread
+    uint32_t tot = 0;
+    if (d < R) {
 #pragma unroll
-    for (int ww = 0; ww < BS / 64; ++ww) {
-      const uint32_t c = wc[ww][d];
-      wc[ww][d] = run;
-      run += c;
+      for (int ww = 0; ww < BS / 64; ++ww) tot += wc[ww][d];
+    }
+    uint32_t unused;
+    uint32_t run = block_exclusive<uint32_t>(tot, unused);
+    if (d < R) {
+      goff[d] = a.C[(size_t)d * a.c_stride + part] - run;
+#pragma unroll
+      for (int ww = 0; ww < BS / 64; ++ww) {
+        const uint32_t c = wc[ww][d];
+        wc[ww][d] = run;
+        run += c;
+      }
     }
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < SIPT; ++r) {
-    const uint64_t idx = base + (uint64_t)r * 64;
-    if (idx >= K) break;
-    const uint32_t pos = wc[w][(key[r] >> a.shift) & mask] + rk[r];
-    if (pos >= K) continue;  // unreachable when the counts are consistent
-    a.kout[pos] = key[r];
-    a.vout[pos] = val[r];
-    a.bout[pos] = bits[r];
+    if (base + (uint64_t)r * 64 < K) {
+      const uint32_t local = wc[w][(key[r] >> a.shift) & mask] + rk[r];
+      if (local < SPART) {  // always, when the counts are consistent
+        Ks[local] = key[r];
+        Vs[local] = val[r];
+        Bs[local] = bits[r];
+      }
+    }
+  }
+  __syncthreads();
+  const uint64_t p0 = (uint64_t)part * SPART;
+  const uint32_t m = K - p0 < (uint64_t)SPART ? (uint32_t)(K - p0) : (uint32_t)SPART;
+#pragma unroll
+  for (int r = 0; r < SIPT; ++r) {
+    const uint32_t i = threadIdx.x + (uint32_t)r * BS;
+    if (i < m) {
+      const uint32_t k = Ks[i];
+      const uint32_t pos = goff[(k >> a.shift) & mask] + i;
+      if (pos < K) {  // always, when the counts are consistent
+        a.kout[pos] = k;
+        a.vout[pos] = Vs[i];
+        a.bout[pos] = Bs[i];
+      }
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // copies of the splats, in splat-index order
 // ---------------------------------------------------------------------------
-// copies per emission partition (plain stores; no inter-workgroup traffic)
+// copies per emission partition (plain stores; no inter-workgroup traffic);
+// also resets the call's state (what clear_state does when n = 0)
 __global__ __launch_bounds__(BS) void emit_sums(uint32_t n, const uint32_t *__restrict__ tiles,
-                                                uint64_t *__restrict__ esum) {
+                                                uint64_t *__restrict__ esum, uint4 *__restrict__ z, size_t nz16,
+                                                uint32_t *__restrict__ ranges, size_t nr, int64_t *num_keys,
+                                                int32_t *overflow) {
+  {
+    const size_t i = (size_t)blockIdx.x * BS + threadIdx.x, stride = (size_t)gridDim.x * BS;
+    for (size_t j = i; j < nz16; j += stride) z[j] = make_uint4(0u, 0u, 0u, 0u);
+    for (size_t j = i; j < nr; j += stride) ranges[j] = 0u;
+    if (i == 0) {
+      *num_keys = 0;
+      *overflow = 0;
+    }
+  }
   const uint64_t s0 = (uint64_t)blockIdx.x * EPART + threadIdx.x;
   uint64_t s = 0;
 #pragma unroll
@@ -469,37 +513,64 @@ struct Seg {
   uint32_t *vout;
 };
 
-// One workgroup per tile: a stable LSD radix sort of the tile's list by depth
-// bits. The keys are the depth bits minus the tile's smallest one (same
+// A stable LSD radix sort of one tile's list by depth bits, by a workgroup. The keys are the depth bits minus the tile's smallest one (same
 // order, same ties), and only the bytes that vary are sorted, low byte
 // first, with the list spread over all four waves (ceil(n / 256) rounds of
 // 64 per wave). IPT = SHORT_IPT sorts the lists of at most 1024 copies
 // (nearly all of them) with little LDS and few registers, so many tiles run
 // per CU; IPT = LONG_IPT takes the longer ones: in LDS up to 4096 copies,
-// beyond that chunk by chunk through global memory.
+// beyond that chunk by chunk through global memory. Returns with the
+// workgroup converged.
 template <int IPT>
-__global__ __launch_bounds__(BS) void segment_sort(Seg a) {
+struct SortLds {
+  uint32_t Kb[BS * IPT], Vb[BS * IPT];
+  uint32_t wc[BS / 64][RADIX];
+  uint32_t run[RADIX];
+  uint32_t s_mn[BS / 64], s_mx[BS / 64];
+};
+
+template <int IPT>
+__device__ __forceinline__ void sort_list(const Seg &a, uint32_t t, uint32_t start, uint32_t n, SortLds<IPT> &sl) {
   constexpr int SEG_IPT = IPT;
   constexpr int SEG_CAP = BS * IPT;
   constexpr bool SHORT = IPT == SHORT_IPT;
-  __shared__ uint32_t Kb[SEG_CAP], Vb[SEG_CAP];
-  __shared__ uint32_t wc[BS / 64][RADIX];
-  __shared__ uint32_t run[RADIX];
-  __shared__ uint32_t s_mn[BS / 64], s_mx[BS / 64];
-  if ((int64_t)blockIdx.x >= a.ntiles) return;
-  const uint32_t t = a.order ? min(a.order[blockIdx.x], (uint32_t)(a.ntiles - 1)) : blockIdx.x;
-  const uint32_t start = a.ranges[2 * (size_t)t], end = a.ranges[2 * (size_t)t + 1];
-  if (end <= start) return;
-  if (SHORT != (end - start <= (uint32_t)(BS * SHORT_IPT))) return;  // the other instance sorts it
-  const uint32_t n = end - start;
+  uint32_t *Kb = sl.Kb, *Vb = sl.Vb, *run = sl.run, *s_mn = sl.s_mn, *s_mx = sl.s_mx;
+  uint32_t (*wc)[RADIX] = sl.wc;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t tkey = (uint64_t)t << 32;
+  uint32_t key[SEG_IPT], val[SEG_IPT], rk[SEG_IPT];
+  const bool in_lds = n <= SEG_CAP;
+  const uint32_t R0 = chunk_rounds(in_lds ? n : (uint32_t)SEG_CAP);
+  const uint32_t wbase0 = (uint32_t)w * 64u * R0 + (uint32_t)lane;
 
+  // the tile's depth range; a list that fits in LDS is loaded into registers
+  // here (every load in flight at once), a longer one is scanned 8 loads at a time
   uint32_t mn = 0xFFFFFFFFu, mx = 0u;
-  for (uint32_t i = threadIdx.x; i < n; i += BS) {
-    const uint32_t k = a.bits[start + i];
-    mn = min(mn, k);
-    mx = max(mx, k);
+  if (in_lds) {
+#pragma unroll
+    for (int r = 0; r < SEG_IPT; ++r) {
+      const uint32_t i = wbase0 + (uint32_t)r * 64u;
+      const bool mine = (uint32_t)r < R0 && i < n;
+      key[r] = mine ? a.bits[start + i] : 0u;
+      val[r] = mine ? a.vals[start + i] : 0u;
+      if (mine) {
+        mn = min(mn, key[r]);
+        mx = max(mx, key[r]);
+      }
+    }
+  } else {
+    for (uint32_t i0 = threadIdx.x; i0 < n; i0 += 8 * BS) {
+      uint32_t k8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) k8[u] = i0 + u * BS < n ? a.bits[start + i0 + u * BS] : 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (i0 + u * BS < n) {
+          mn = min(mn, k8[u]);
+          mx = max(mx, k8[u]);
+        }
+      }
+    }
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
@@ -520,18 +591,12 @@ __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
   }
   const uint32_t span = mx - mn;
   const int passes = span ? (32 - __clz(span) + 7) / 8 : 0;
-  uint32_t key[SEG_IPT], val[SEG_IPT], rk[SEG_IPT];
 
-  if (n <= SEG_CAP) {
-    const uint32_t R = chunk_rounds(n);
-    const uint32_t wbase = (uint32_t)w * 64u * R + (uint32_t)lane;
+  if (in_lds) {
+    const uint32_t R = R0;
+    const uint32_t wbase = wbase0;
 #pragma unroll
-    for (int r = 0; r < SEG_IPT; ++r) {
-      const uint32_t i = wbase + (uint32_t)r * 64u;
-      const bool mine = (uint32_t)r < R && i < n;
-      key[r] = mine ? a.bits[start + i] - mn : 0u;
-      val[r] = mine ? a.vals[start + i] : 0u;
-    }
+    for (int r = 0; r < SEG_IPT; ++r) key[r] -= mn;  // unused slots are never read
     for (int p = 0; p < passes; ++p) {
       for (int j = threadIdx.x; j < (BS / 64) * RADIX; j += BS) (&wc[0][0])[j] = 0u;
       __syncthreads();
@@ -658,6 +723,37 @@ __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
   }
 }
 
+constexpr uint32_t SHORT_MAX = BS * SHORT_IPT;  // longest list the short instance sorts
+// No list longer than SHORT_MAX shares a tile-order length bucket with, or
+// follows, a list shorter than LONG_STOP (buckets are 1/16 of a doubling wide).
+constexpr uint32_t LONG_STOP = 940;
+
+// lists of at most SHORT_MAX copies, one workgroup per tile
+__global__ __launch_bounds__(BS) void segment_sort_short(Seg a) {
+  __shared__ SortLds<SHORT_IPT> sl;
+  if ((int64_t)blockIdx.x >= a.ntiles) return;
+  const uint32_t t = a.order ? min(a.order[blockIdx.x], (uint32_t)(a.ntiles - 1)) : blockIdx.x;
+  const uint32_t start = a.ranges[2 * (size_t)t], end = a.ranges[2 * (size_t)t + 1];
+  if (end <= start || end - start > SHORT_MAX) return;
+  sort_list<SHORT_IPT>(a, t, start, end - start, sl);
+}
+
+// longer lists. With a longest-first tile order they come first, so a small
+// grid walks the order and stops at the first clearly short list; without
+// one it visits every tile.
+__global__ __launch_bounds__(BS) void segment_sort_long(Seg a) {
+  __shared__ SortLds<LONG_IPT> sl;
+  for (int64_t pos = blockIdx.x; pos < a.ntiles; pos += gridDim.x) {
+    const uint32_t t = a.order ? min(a.order[pos], (uint32_t)(a.ntiles - 1)) : (uint32_t)pos;
+    const uint32_t start = a.ranges[2 * (size_t)t], end = a.ranges[2 * (size_t)t + 1];
+    const uint32_t n = end > start ? end - start : 0u;
+    if (a.order && n < LONG_STOP) break;
+    if (n <= SHORT_MAX) continue;
+    sort_list<LONG_IPT>(a, t, start, n, sl);
+    __syncthreads();  // the next list reuses the LDS
+  }
+}
+
 // ---------------------------------------------------------------------------
 // workspace
 // ---------------------------------------------------------------------------
@@ -732,18 +828,18 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
   const TilePlan tp = tile_plan(ntiles);
   const size_t tpass = ((size_t)1 << tp.bits) * w.tstride;    // one tile pass's counts
 
-  // 0. zero totals, counters and ranges; num_keys = overflow = 0
-  {
-    const size_t nz16 = w.zero_bytes / 16, nr = 2 * (size_t)ntiles;
+  // 0. zero totals, counters and ranges; num_keys = overflow = 0 (with step 1 when n > 0)
+  const size_t nz16 = w.zero_bytes / 16, nr = 2 * (size_t)ntiles;
+  if (n == 0) {
     const size_t m = nz16 > nr ? nz16 : nr;
     const unsigned grid = (unsigned)(m / BS + 1 < 2048 ? m / BS + 1 : 2048);
     hipLaunchKernelGGL(clear_state, dim3(grid), dim3(BS), 0, s, (uint4 *)w.zero_begin, nz16, ranges, nr, num_keys,
                        overflow);
-  }
-  if (n > 0) {
+  } else {
     // 1. copies in splat-index order with their depth bits, the tile digit totals, K
     const unsigned egrid = ceil_div(n, EPART);
-    hipLaunchKernelGGL(emit_sums, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, tiles, w.esum);
+    hipLaunchKernelGGL(emit_sums, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, tiles, w.esum, (uint4 *)w.zero_begin,
+                       nz16, ranges, nr, num_keys, overflow);
     Emit e{};
     e.n = (uint32_t)n;
     e.tiles = tiles;
@@ -806,8 +902,9 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
     g.svals = w.tv[cur ^ 1];
     g.keys = keys;
     g.vout = vals;
-    hipLaunchKernelGGL(segment_sort<SHORT_IPT>, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
-    hipLaunchKernelGGL(segment_sort<LONG_IPT>, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
+    hipLaunchKernelGGL(segment_sort_short, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
+    const unsigned lgrid = tile_order ? (unsigned)(ntiles < 2048 ? ntiles : 2048) : (unsigned)ntiles;
+    hipLaunchKernelGGL(segment_sort_long, dim3(lgrid), dim3(BS), 0, s, g);
     return hipGetLastError();
   }
   // nothing emitted (or no room): ranges stay zero

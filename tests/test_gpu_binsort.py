@@ -17,7 +17,7 @@ from paper_2603_18707_amd import scenes
 pytestmark = pytest.mark.gpu
 
 
-def _run(depth, rect, tiles, gw, gh, capacity):
+def _run(depth, rect, tiles, gw, gh, capacity, with_order=True):
     dev = torch.device("cuda", 0)
     n = depth.shape[0]
     d = torch.from_numpy(depth).to(dev)
@@ -29,7 +29,7 @@ def _run(depth, rect, tiles, gw, gh, capacity):
     keys = torch.full((max(capacity, 1),), -1, dtype=torch.int64, device=dev)
     vals = torch.full((max(capacity, 1),), -1, dtype=torch.int32, device=dev)
     ranges = torch.full((ntiles, 2), -1, dtype=torch.int32, device=dev)
-    order = torch.full((ntiles,), -1, dtype=torch.int32, device=dev)
+    order = torch.full((ntiles,), -1, dtype=torch.int32, device=dev) if with_order else None
     num_keys = torch.full((1,), -1, dtype=torch.int64, device=dev)
     overflow = torch.full((1,), -1, dtype=torch.int32, device=dev)
     L.gs_bin_sort(n, d, r, t, gw, gh, capacity, ws, ws_bytes, keys, vals, ranges, order, num_keys, overflow)
@@ -38,7 +38,7 @@ def _run(depth, rect, tiles, gw, gh, capacity):
     kk = min(K, capacity)
     return dict(K=K, overflow=int(overflow.item()), keys=keys.cpu().numpy()[:kk].view(np.uint64),
                 vals=vals.cpu().numpy()[:kk].view(np.uint32), ranges=ranges.cpu().numpy().view(np.uint32),
-                order=order.cpu().numpy().view(np.uint32))
+                order=order.cpu().numpy().view(np.uint32) if with_order else None)
 
 
 CASES = [  # n, grid_w, grid_h, seed, share of big splats
@@ -104,3 +104,15 @@ def test_bin_sort_all_culled_and_repeatable():
     b = _run(depth, rect, tiles, gw, gh, 1 << 20)
     for k in ("keys", "vals", "ranges"):  # tile_order's order inside a length bucket is unspecified
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_bin_sort_without_tile_order():
+    """tile_order = NULL: the same keys, values and ranges (lists of every
+    length, including ones sorted in chunks)."""
+    gw, gh = 3, 2
+    depth, rect, tiles = scenes.binning_inputs(60_000, gw, gh, 12)
+    keys, vals, ranges = binning.bin_and_sort_fast(rect, depth, gw, gh)
+    g = _run(depth, rect, tiles, gw, gh, keys.shape[0], with_order=False)
+    assert g["overflow"] == 0 and g["K"] == keys.shape[0]
+    assert np.array_equal(g["keys"], keys) and np.array_equal(g["vals"], vals)
+    assert np.array_equal(g["ranges"], ranges)

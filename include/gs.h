@@ -152,7 +152,7 @@ gs_status gs_params_default(gs_params *out);
  *
  * in : means3d [n,3], scales [n,3] (standard deviations), quats [n,4]
  *      (w,x,y,z, need not be normalised), opacities [n] in [0,1],
- *      sh [n,(sh_degree+1)^2,3], sh_degree in 0..3.
+ *      sh [n,(sh_degree+1)^2,3] (16-byte aligned), sh_degree in 0..3.
  * out: means2d [n,2], conic_opacity [n,4] = (a, b, c, o') with conic
  *      [[a, b], [b, c]], rgb [n,3], depth [n], rect [n,4] int32,
  *      tiles_touched [n] uint32.

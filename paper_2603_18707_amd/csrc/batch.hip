@@ -108,7 +108,6 @@ __device__ inline int find_view_by_block(const ViewInfo *info, int nviews, int64
 template <int DEG>
 __global__ __launch_bounds__(64) void batch_preprocess(PreParams base, SceneTable st, const gs_view *__restrict__ views,
                                                        const ViewInfo *__restrict__ info, int nviews, PreOut out) {
-  __shared__ float shs[64 * SH_ROW];
   const int v = find_view_by_block(info, nviews, (int64_t)blockIdx.x);
   const ViewInfo in = info[v];
   const int s = in.scene;
@@ -129,7 +128,7 @@ __global__ __launch_bounds__(64) void batch_preprocess(PreParams base, SceneTabl
     reinterpret_cast<int4 *>(out.rect)[o] = make_int4(0, 0, -1, -1);
     out.tiles[o] = 0u;
   }
-  const float3 c = sh_colour_block<DEG>(st.sh[s], first, in.n, live, Y, shs);
+  const float3 c = sh_colour<DEG>(st.sh[s], i, live, Y);
   out.rgb[3 * o] = c.x;
   out.rgb[3 * o + 1] = c.y;
   out.rgb[3 * o + 2] = c.z;

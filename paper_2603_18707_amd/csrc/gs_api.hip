@@ -203,8 +203,8 @@ gs_status gs_preprocess(const gs_camera *cam, const gs_kernel *kernel, const gs_
   if (!means3d || !scales || !quats || !opacities || !sh || !means2d || !conic_opacity || !rgb || !depth || !rect ||
       !tiles_touched)
     return fail(GS_EINVAL, "NULL array argument");
-  if (!aligned(means2d, 8) || !aligned(conic_opacity, 16) || !aligned(rect, 16))
-    return fail(GS_EINVAL, "means2d needs 8-byte, conic_opacity and rect 16-byte alignment");
+  if (!aligned(means2d, 8) || !aligned(conic_opacity, 16) || !aligned(rect, 16) || !aligned(sh, 16))
+    return fail(GS_EINVAL, "means2d needs 8-byte, conic_opacity, rect and sh 16-byte alignment");
   PreParams p;
   std::memset(&p, 0, sizeof(p));
   make_cam(cam, params->tile, &p.cam);
@@ -389,6 +389,7 @@ static gs_status batch_check(const gs_scene *scenes, int32_t num_scenes, const g
     if (sc.reserved != 0) return fail(GS_EINVAL, "scene %d: reserved must be 0", i);
     if (sc.n > 0 && (!sc.means3d || !sc.scales || !sc.quats || !sc.opacities || !sc.sh))
       return fail(GS_EINVAL, "scene %d: NULL array", i);
+    if (sc.n > 0 && !aligned(sc.sh, 16)) return fail(GS_EINVAL, "scene %d: sh needs 16-byte alignment", i);
   }
   int64_t p = 0, rows = 0;
   int32_t cols = 1;

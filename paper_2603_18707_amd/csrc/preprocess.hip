@@ -6,7 +6,7 @@
 // culls, radius, rectangle) runs in double precision from the float inputs so
 // that depth keys and rectangles are reproducible; the record the blender
 // reads is rounded to float at the end. The stage is bound by HBM traffic
-// (236 B in, 48 B out per splat at SH degree 3), not by the FP64 arithmetic.
+// (236 B in, 60 B out per splat at SH degree 3), not by the FP64 arithmetic.
 #include <cmath>
 
 #include "gs_internal.h"
@@ -16,28 +16,21 @@ namespace gs {
 
 namespace {
 
-// One wave per 64 splats: geometry per lane, then the wave stages its
-// splats' SH coefficients (a contiguous block) through LDS chunk by chunk with
-// coalesced loads; reading 48 floats per lane straight from global memory
-// would touch 64 cache lines per load instruction.
+// One thread per splat (64-thread workgroups).
 template <int DEG>
 __global__ __launch_bounds__(64) void preprocess_kernel(PreParams p, int64_t n, const float *__restrict__ means3d,
                                                         const float *__restrict__ scales,
                                                         const float *__restrict__ quats,
                                                         const float *__restrict__ opac,
                                                         const float *__restrict__ sh, PreOut out) {
-  __shared__ float shs[64 * SH_ROW];
-  const int64_t base = (int64_t)blockIdx.x * 64;
-  const int64_t i = base + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (i >= n) return;
   float Y[16];
-  bool live = false;
-  if (i < n) live = project_one<DEG>(p, i, means3d, scales, quats, opac, i, 0, out, Y);
-  const float3 c = sh_colour_block<DEG>(sh, base, n, live, Y, shs);
-  if (i < n) {
-    out.rgb[3 * i] = c.x;
-    out.rgb[3 * i + 1] = c.y;
-    out.rgb[3 * i + 2] = c.z;
-  }
+  const bool live = project_one<DEG>(p, i, means3d, scales, quats, opac, i, 0, out, Y);
+  const float3 c = sh_colour<DEG>(sh, i, live, Y);
+  out.rgb[3 * i] = c.x;
+  out.rgb[3 * i + 1] = c.y;
+  out.rgb[3 * i + 2] = c.z;
 }
 
 }  // namespace

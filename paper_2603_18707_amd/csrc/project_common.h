@@ -98,66 +98,46 @@ __device__ inline void sh_basis(float x, float y, float z, float Y[16]) {
   }
 }
 
-// SH coefficients are staged through LDS in chunks of SH_CHUNK floats per
-// splat (rows of SH_CHUNK + 1 floats: an odd stride, so the per-lane reads hit
-// distinct banks); two chunks cover degree 3 at 6.4 KB of LDS per wave.
-constexpr int SH_CHUNK = 24;
-constexpr int SH_ROW = SH_CHUNK + 1;
-
+// rgb = max(sum_k Y_k sh_k + 0.5, 0) for splat i, 0 when culled. Each lane
+// reads its own coefficient row (16-byte loads when the row is a multiple of
+// 16 bytes, as at degree 1 and 3): the rows of a wave are one contiguous
+// block, so its cache lines are fetched once and reused across the loads,
+// and no LDS, barrier or second pass over the block is needed.
 template <int DEG>
-struct ShLayout {
-  static constexpr int NSH3 = 3 * (DEG + 1) * (DEG + 1);
-  static constexpr int CHUNKS = (NSH3 + SH_CHUNK - 1) / SH_CHUNK;
-};
-
-// Copies chunk c of the SH rows of splats [base, base + 64) of a scene of n
-// splats into LDS (coalesced: consecutive lanes read consecutive floats).
-template <int DEG>
-__device__ inline void stage_sh_chunk(const float *__restrict__ sh, int64_t base, int64_t n, int c, float *shs) {
-  constexpr int NSH3 = ShLayout<DEG>::NSH3;
-  const int k0 = c * SH_CHUNK;
-  const int cw = (NSH3 - k0) < SH_CHUNK ? (NSH3 - k0) : SH_CHUNK;
-  const int64_t cnt = (n - base) < 64 ? (n - base) : 64;
-  const int total = cnt > 0 ? (int)cnt * cw : 0;
-  for (int e = threadIdx.x; e < total; e += 64) {
-    const int s = e / cw, k = e - s * cw;
-    shs[s * SH_ROW + k] = sh[(base + s) * NSH3 + k0 + k];
-  }
-}
-
-// rgb = max(sum_k Y_k sh_k + 0.5, 0) for the 64 splats of a wave, the SH
-// block staged chunk by chunk. Every lane of the workgroup must call it.
-template <int DEG>
-__device__ inline float3 sh_colour_block(const float *__restrict__ sh, int64_t base, int64_t n, bool live,
-                                         const float Y[16], float *shs) {
-  constexpr int NSH3 = ShLayout<DEG>::NSH3;
-  float acc0 = 0.5f, acc1 = 0.5f, acc2 = 0.5f;
+__device__ inline float3 sh_colour(const float *__restrict__ sh, int64_t i, bool live, const float Y[16]) {
+  constexpr int NB = (DEG + 1) * (DEG + 1);
+  constexpr int NSH3 = 3 * NB;
+  if (!live) return make_float3(0.f, 0.f, 0.f);
+  float f[NSH3];
+  if constexpr (NSH3 % 4 == 0) {
+    const float4 *row = reinterpret_cast<const float4 *>(sh + i * NSH3);
 #pragma unroll
-  for (int c = 0; c < ShLayout<DEG>::CHUNKS; ++c) {
-    __syncthreads();  // the previous chunk has been read
-    stage_sh_chunk<DEG>(sh, base, n, c, shs);
-    __syncthreads();
-    if (live) {
-      const float *row = shs + threadIdx.x * SH_ROW;
-#pragma unroll
-      for (int k = 0; k < SH_CHUNK / 3; ++k) {
-        const int kk = c * (SH_CHUNK / 3) + k;
-        if (3 * kk < NSH3) {
-          acc0 = fmaf(Y[kk], row[3 * k + 0], acc0);
-          acc1 = fmaf(Y[kk], row[3 * k + 1], acc1);
-          acc2 = fmaf(Y[kk], row[3 * k + 2], acc2);
-        }
-      }
+    for (int q = 0; q < NSH3 / 4; ++q) {
+      const float4 v = row[q];
+      f[4 * q] = v.x;
+      f[4 * q + 1] = v.y;
+      f[4 * q + 2] = v.z;
+      f[4 * q + 3] = v.w;
     }
+  } else {
+#pragma unroll
+    for (int q = 0; q < NSH3; ++q) f[q] = sh[i * NSH3 + q];
   }
-  return live ? make_float3(fmaxf(acc0, 0.0f), fmaxf(acc1, 0.0f), fmaxf(acc2, 0.0f)) : make_float3(0.f, 0.f, 0.f);
+  float a0 = 0.5f, a1 = 0.5f, a2 = 0.5f;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    a0 = fmaf(Y[k], f[3 * k], a0);
+    a1 = fmaf(Y[k], f[3 * k + 1], a1);
+    a2 = fmaf(Y[k], f[3 * k + 2], a2);
+  }
+  return make_float3(fmaxf(a0, 0.0f), fmaxf(a1, 0.0f), fmaxf(a2, 0.0f));
 }
 
 // Projects splat i of a scene and writes output record o. Tile rows are
 // offset by row_base (non-zero when several views share one virtual grid).
 // Returns whether the splat survived the culls; then Y holds its SH basis
 // values along the ray from the camera centre (rgb is written by the caller,
-// see sh_colour_block).
+// see sh_colour).
 template <int DEG>
 __device__ inline bool project_one(const PreParams &p, int64_t i, const float *__restrict__ means3d,
                                    const float *__restrict__ scales, const float *__restrict__ quats,
@@ -165,7 +145,13 @@ __device__ inline bool project_one(const PreParams &p, int64_t i, const float *_
                                    float Y[16]) {
   bool live = false;
   const CamD &cam = p.cam;
-  const double mx = means3d[3 * i], my = means3d[3 * i + 1], mz = means3d[3 * i + 2];
+  // every input of the splat is loaded up front, so the loads are in flight
+  // together instead of one round trip after each cull test
+  const float fmx = means3d[3 * i], fmy = means3d[3 * i + 1], fmz = means3d[3 * i + 2];
+  const float fqw = quats[4 * i], fqx = quats[4 * i + 1], fqy = quats[4 * i + 2], fqz = quats[4 * i + 3];
+  const float fs0 = scales[3 * i], fs1 = scales[3 * i + 1], fs2 = scales[3 * i + 2];
+  const float fop = opac[i];
+  const double mx = fmx, my = fmy, mz = fmz;
   double t[3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) t[r] = cam.R[3 * r] * mx + cam.R[3 * r + 1] * my + cam.R[3 * r + 2] * mz + cam.t[r];
@@ -179,13 +165,13 @@ __device__ inline bool project_one(const PreParams &p, int64_t i, const float *_
   do {
     if (t[2] < p.near_z) break;
     // 3D covariance R(q) diag(s)^2 R(q)^T
-    double qw = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
+    double qw = fqw, qx = fqx, qy = fqy, qz = fqz;
     const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
     qw *= qn; qx *= qn; qy *= qn; qz *= qn;
     const double Rq[3][3] = {{1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
                              {2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)},
                              {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
-    const double s0 = scales[3 * i], s1 = scales[3 * i + 1], s2 = scales[3 * i + 2];
+    const double s0 = fs0, s1 = fs1, s2 = fs2;
     const double ss[3] = {s0 * s0, s1 * s1, s2 * s2};
     // EWA: T = J W (2x3), S' = T Sigma T^T computed as (T Rq) diag(ss) (T Rq)^T
     const double tz = t[2], iz = 1.0 / tz;
@@ -216,7 +202,7 @@ __device__ inline bool project_one(const PreParams &p, int64_t i, const float *_
     if (!(deta > 0.0)) break;
     const double ideta = 1.0 / deta;
     const double ratio = det0 * ideta;
-    const double o = (double)opac[i] * sqrt(ratio > 0.0 ? ratio : 0.0);
+    const double o = (double)fop * sqrt(ratio > 0.0 ? ratio : 0.0);
 
     // bounding radius multiplier
     double k;
@@ -238,9 +224,10 @@ __device__ inline bool project_one(const PreParams &p, int64_t i, const float *_
     const double r = k * sqrt(lmax) * p.pad;
     const double u = cam.fx * t[0] * iz + cam.cx;
     const double v = cam.fy * t[1] * iz + cam.cy;
-    const double T = (double)p.tile;
-    const long xlo = clamp_floor((u - r) / T, 0, cam.gx), xhi = clamp_floor((u + r) / T, -1, cam.gx - 1);
-    const long ylo = clamp_floor((v - r) / T, 0, cam.gy), yhi = clamp_floor((v + r) / T, -1, cam.gy - 1);
+    // x / T as x * (1 / T): exact, T being a power of two (16, checked on the host)
+    const double iT = 1.0 / (double)p.tile;
+    const long xlo = clamp_floor((u - r) * iT, 0, cam.gx), xhi = clamp_floor((u + r) * iT, -1, cam.gx - 1);
+    const long ylo = clamp_floor((v - r) * iT, 0, cam.gy), yhi = clamp_floor((v + r) * iT, -1, cam.gy - 1);
     if (xhi >= xlo && yhi >= ylo) {
       rc = make_int4((int)xlo, (int)ylo + row_base, (int)xhi, (int)yhi + row_base);
       ntiles = (uint32_t)((xhi - xlo + 1) * (yhi - ylo + 1));

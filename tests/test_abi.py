@@ -113,6 +113,8 @@ def test_device_calls_reject_bad_arguments_on_host():
     _expect(L.GS_EINVAL, L.gs_preprocess, c2, k, p, 0, *null8, 0, *out6)
     # misaligned outputs
     _expect(L.GS_EINVAL, L.gs_preprocess, cam, k, p, 1, 16, 16, 16, 16, 16, 0, 16, 20, 16, 16, 16, 16)
+    msg = _expect(L.GS_EINVAL, L.gs_preprocess, cam, k, p, 1, 16, 16, 16, 16, 20, 3, 16, 16, 16, 16, 16, 16)
+    assert "sh" in msg  # 16-byte SH rows are read with 16-byte loads
     # n = 0 is a no-op that enqueues nothing
     L.gs_preprocess(cam, k, p, 0, *null8, 0, *out6)
     # bin sort: workspace too small, capacity too large, grid invalid

@@ -257,21 +257,19 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
 #pragma unroll
             for (int k = 0; k < P; ++k) {
               if (COUNT && js[q] != NT && alive[k]) ++tested[k];
-              if (t[q][k] >= 0.0f && alive[k]) {
+              if (t[q][k] >= 0.0f && alive[k]) {  // the stop-or-blend choice below is by selects
                 const float a = alpha_from<KIND>(t[q][k], s1v[q], p);
                 const float Tn = T[k] * (1.0f - a);
-                if (Tn < p.t_min) {
-                  alive[k] = false;
-                  nev[k] = pos;
-                } else {
-                  const float w = a * T[k];
-                  C0[k] = fmaf(s2v[q].x, w, C0[k]);
-                  C1[k] = fmaf(s2v[q].y, w, C1[k]);
-                  C2[k] = fmaf(s2v[q].z, w, C2[k]);
-                  T[k] = Tn;
-                  ++ncon[k];
-                  last[k] = pos;
-                }
+                const bool stop = Tn < p.t_min;
+                const float w = stop ? 0.0f : a * T[k];
+                C0[k] = fmaf(s2v[q].x, w, C0[k]);
+                C1[k] = fmaf(s2v[q].y, w, C1[k]);
+                C2[k] = fmaf(s2v[q].z, w, C2[k]);
+                T[k] = stop ? T[k] : Tn;
+                ncon[k] += stop ? 0u : 1u;
+                last[k] = stop ? last[k] : pos;
+                nev[k] = stop ? pos : nev[k];
+                alive[k] = !stop;
               }
             }
           }

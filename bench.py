@@ -239,7 +239,7 @@ def cpu_baseline(scene_np, cam, gpu_image, target_s):
 
     c = (0.773, -0.773 / 4.386)
     cfg = ocore.Cfg(kind=ocore.KERNEL_POLY, order=1, radius_mode=ocore.RADIUS_POLY_OPACITY, coeffs=c,
-                    alpha_band=2e-6)
+                    alpha_band=2e-6).float_params()
     t0 = time.perf_counter()
     proj = ocore.project(scene_np, cam, cfg)
     rec = ocore.round_records(proj)

@@ -202,7 +202,11 @@ gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const 
  * in : means2d, conic_opacity, rgb (gs_preprocess), vals, ranges and
  *      tile_order (gs_bin_sort; tile_order may be NULL for row-major order,
  *      it only changes which workgroup renders which tile), n = number of
- *      splats the values index.
+ *      splats the values index. A splat whose conic is not positive definite
+ *      (a > 0, c > 0, a c > b^2; gs_preprocess culls the others) is never
+ *      blended. Q is evaluated in float as c (dy + dx b/c)^2 + dx^2 (ac - b^2)/c,
+ *      a sum of two non-negative terms, so its rounding stays a few ulps of Q
+ *      however elongated the footprint.
  * out: image [3,H,W] planar, final_T [H,W], n_contrib [H,W] = splats
  *      blended, last_contrib [H,W] = 1 + list position (within the tile)
  *      of the last blended splat, 0 if none (the backward pass starts there),

@@ -18,7 +18,7 @@ Pins (tests/test_oracle_*.py, all run without a GPU):
 """
 import ctypes
 import os
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -71,6 +71,16 @@ class Cfg:
     alpha_band: float = 2e-6
     t_band_rel: float = 1e-4
 
+    def float_params(self) -> "Cfg":
+        """A copy whose scalar parameters (eps, alpha_max, t_min, aa_v, near_z,
+        radius_pad, bg) are rounded to float: a renderer that takes them as
+        float computes with those values, and so must the reference it is
+        compared with (0.3 as a float is 0.3 + 1.2e-8, enough to move
+        conic floats by an ulp)."""
+        f = lambda x: float(np.float32(x))
+        return replace(self, eps=f(self.eps), alpha_max=f(self.alpha_max), t_min=f(self.t_min), aa_v=f(self.aa_v),
+                       near_z=f(self.near_z), radius_pad=f(self.radius_pad), bg=tuple(f(b) for b in self.bg))
+
     def _c(self) -> _Cfg:
         c = _Cfg()
         c.kind, c.order, c.radius_mode, c.tile = self.kind, self.order, self.radius_mode, self.tile
@@ -121,7 +131,7 @@ def lib():
         L.orc_sh_basis.restype = None
         L.orc_sh_basis.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, P]
         L.orc_project.restype = None
-        L.orc_project.argtypes = [P, P, ctypes.c_int64] + [P] * 5 + [ctypes.c_int32] + [P] * 10
+        L.orc_project.argtypes = [P, P, ctypes.c_int64] + [P] * 5 + [ctypes.c_int32] + [P] * 13
         L.orc_depth_order.restype = None
         L.orc_depth_order.argtypes = [ctypes.c_int64, P, P]
         L.orc_render_pixels.restype = None
@@ -180,6 +190,11 @@ def project(scene, cam, cfg: Cfg) -> dict:
     ``scene`` needs means3d [n,3], scales [n,3], quats [n,4] (w,x,y,z),
     opacities [n], sh [n,(d+1)^2,3] and sh_degree; arrays are read as float64
     (float32 scenes convert exactly, finite differences may pass float64).
+    Besides the record: rec_err [n,6], a running bound on the FP64 error of
+    (u, v, a, b, c, o), and rec_amb [n], bit k set when entry k has a float
+    rounding midpoint within twice that bound (two correct evaluations may
+    round it one ulp apart), and rec_alt [n,6], the float on the other side
+    of that midpoint (both are correct roundings).
     """
     L = lib()
     n = int(scene.means3d.shape[0])
@@ -188,12 +203,14 @@ def project(scene, cam, cfg: Cfg) -> dict:
                           f64(scene.opacities), f64(scene.sh))
     out = dict(means2d=np.zeros((n, 2)), conic=np.zeros((n, 3)), opac=np.zeros(n), rgb=np.zeros((n, 3)),
                depth=np.zeros(n), depth32=np.zeros(n, np.float32), radius=np.zeros(n),
-               rect=np.zeros((n, 4), np.int32), tiles=np.zeros(n, np.int64), flags=np.zeros(n, np.uint8))
+               rect=np.zeros((n, 4), np.int32), tiles=np.zeros(n, np.int64), flags=np.zeros(n, np.uint8),
+               rec_amb=np.zeros(n, np.uint8), rec_err=np.zeros((n, 6)), rec_alt=np.zeros((n, 6)))
     cc, cm = cfg._c(), _cam(cam)
     L.orc_project(ctypes.byref(cc), ctypes.byref(cm), n, _p(m3), _p(sc), _p(qu), _p(op), _p(sh),
                   int(scene.sh_degree), _p(out["means2d"]), _p(out["conic"]), _p(out["opac"]),
                   _p(out["rgb"]), _p(out["depth"]), _p(out["depth32"]), _p(out["radius"]),
-                  _p(out["rect"]), _p(out["tiles"]), _p(out["flags"]))
+                  _p(out["rect"]), _p(out["tiles"]), _p(out["flags"]), _p(out["rec_amb"]), _p(out["rec_err"]),
+                  _p(out["rec_alt"]))
     return out
 
 

@@ -186,6 +186,27 @@ static long clamp_floor(double e, long lo, long hi) {
   return f;
 }
 
+/* Could another FP64 evaluation of X, at most w away from this one, round
+ * to a different float? When a float rounding midpoint (or X itself being
+ * one) lies within w of X, returns 1 and the float on the far side of that
+ * midpoint in *alt; otherwise 0 and the float of X. */
+static int float_rounding_alt(double X, double w, double *alt) {
+  float f = (float)X;
+  *alt = (double)f;
+  if (!isfinite(X)) return 0;
+  double up = (double)nextafterf(f, INFINITY), dn = (double)nextafterf(f, -INFINITY);
+  double mu = 0.5 * ((double)f + up), md = 0.5 * ((double)f + dn); /* exact in double */
+  if (fabs(X - mu) <= w && fabs(X - mu) <= fabs(X - md)) {
+    *alt = up;
+    return 1;
+  }
+  if (fabs(X - md) <= w) {
+    *alt = dn;
+    return 1;
+  }
+  return 0;
+}
+
 /* Projects n splats. Inputs (double; the single-precision scene converts
  * exactly) are the scene in activated form: scales are
  * standard deviations, quats are (w, x, y, z) and need not be normalised,
@@ -194,13 +215,30 @@ static long clamp_floor(double e, long lo, long hi) {
  * the inverse of the anti-aliased covariance, opac = anti-aliased opacity,
  * rgb[3], depth (camera z), depth32 (z rounded to float), radius (pixels),
  * rect[4] = inclusive tile rectangle (x_lo, y_lo, x_hi, y_hi) or
- * (0, 0, -1, -1) when empty, tiles = tiles in the rectangle, flags. */
+ * (0, 0, -1, -1) when empty, tiles = tiles in the rectangle, flags.
+ *
+ * Record rounding. The renderer consumes the record rounded to float, and
+ * any FP64 evaluation of it (this one or another program's, by another
+ * route) carries rounding error; where a float rounding midpoint lies that
+ * close, two correct programs may hold floats one ulp apart. A first-order
+ * running error bound E is carried through the computation of each of
+ * u, v, a, b, c and o (unit roundoff 2^-53 times 16 per step, above the
+ * n u of a sum of n <= 11 rounded products,
+ * applied to sums of absolute values, so it bounds any evaluation order of
+ * the same formulas); rec_err [n][6] receives E (may be NULL), and bit k of
+ * rec_amb [n] is set when entry k (u, v, a, b, c, o) has a rounding
+ * midpoint within 2 E: two evaluations each within E of the exact value
+ * can round that entry apart, no others can. rec_alt [n][6] (may be NULL)
+ * holds the float on the other side of that midpoint (the entry's own
+ * float where the bit is clear): for such an entry both floats are correct. The thin footprints of large
+ * anisotropic splats are where this matters: their conic comes from a
+ * cancelling determinant (condition A00 A11 / det up to ~1e7). */
 void orc_project(const orc_cfg *cfg, const orc_cam *cam, int64_t n,
                  const double *means3d, const double *scales, const double *quats,
                  const double *opacity, const double *sh, int32_t sh_degree,
                  double *means2d, double *conic, double *opac, double *rgb,
                  double *depth, float *depth32, double *radius, int32_t *rect,
-                 int64_t *tiles, uint8_t *flags) {
+                 int64_t *tiles, uint8_t *flags, uint8_t *rec_amb, double *rec_err, double *rec_alt) {
   const int T = cfg->tile;
   const long gx = (cam->width + T - 1) / T, gy = (cam->height + T - 1) / T;
   const int nsh = (sh_degree + 1) * (sh_degree + 1);
@@ -231,6 +269,11 @@ void orc_project(const orc_cfg *cfg, const orc_cam *cam, int64_t n,
     rect[4 * i] = 0; rect[4 * i + 1] = 0; rect[4 * i + 2] = -1; rect[4 * i + 3] = -1;
     tiles[i] = 0;
     flags[i] = 0;
+    if (rec_amb) rec_amb[i] = 0;
+    if (rec_err)
+      for (int k2 = 0; k2 < 6; ++k2) rec_err[6 * i + k2] = 0.0;
+    if (rec_alt)
+      for (int k2 = 0; k2 < 6; ++k2) rec_alt[6 * i + k2] = 0.0;
 
     if (tc[2] < cfg->near_z) continue;
 
@@ -331,6 +374,86 @@ void orc_project(const orc_cfg *cfg, const orc_cam *cam, int64_t n,
     long ylo = clamp_floor(ey0, 0, gy), yhi = clamp_floor(ey1, -1, gy - 1);
     long nt = (xhi >= xlo && yhi >= ylo) ? (xhi - xlo + 1) * (yhi - ylo + 1) : 0;
 
+    /* running error bounds of the record (see the comment above) */
+    {
+      const double g = 16.0 * 0x1p-53;
+      double etc[3];
+      for (int r2 = 0; r2 < 3; ++r2)
+        etc[r2] = g * (fabs(Rc[3 * r2]) * fabs(m[0]) + fabs(Rc[3 * r2 + 1]) * fabs(m[1]) +
+                       fabs(Rc[3 * r2 + 2]) * fabs(m[2]) + fabs(cam->t[r2]));
+      const double az = fabs(tz);
+      /* x/z, y/z and their bounds; a clamped one is a constant */
+      double etxz = (fabs(tc[0] / tz) >= limx) ? g * limx : etc[0] / az + fabs(tc[0]) * etc[2] / (az * az) + g * fabs(txz);
+      double etyz = (fabs(tc[1] / tz) >= limy) ? g * limy : etc[1] / az + fabs(tc[1]) * etc[2] / (az * az) + g * fabs(tyz);
+      double eJ[2][3] = {{cam->fx * etc[2] / (az * az) + g * fabs(J[0][0]), 0.0,
+                          cam->fx * (etxz / az + fabs(txz) * etc[2] / (az * az)) + g * fabs(J[0][2])},
+                         {0.0, cam->fy * etc[2] / (az * az) + g * fabs(J[1][1]),
+                          cam->fy * (etyz / az + fabs(tyz) * etc[2] / (az * az)) + g * fabs(J[1][2])}};
+      double eTW[2][3], aTW[2][3];
+      for (int a2 = 0; a2 < 2; ++a2)
+        for (int b2 = 0; b2 < 3; ++b2) {
+          double e = 0.0, sa = 0.0;
+          for (int k2 = 0; k2 < 3; ++k2) {
+            e += eJ[a2][k2] * fabs(Rc[3 * k2 + b2]);
+            sa += fabs(J[a2][k2]) * fabs(Rc[3 * k2 + b2]);
+          }
+          eTW[a2][b2] = e + g * sa;
+          aTW[a2][b2] = fabs(TW[a2][b2]) + eTW[a2][b2];
+        }
+      /* Sigma: every rotation entry within 4 g of its value (normalised quaternion) */
+      double eSig[3][3], aSig[3][3];
+      for (int a2 = 0; a2 < 3; ++a2)
+        for (int b2 = 0; b2 < 3; ++b2) {
+          double e = 0.0, sa = 0.0;
+          for (int k2 = 0; k2 < 3; ++k2) {
+            e += 4.0 * g * (fabs(Rq[a2][k2]) + fabs(Rq[b2][k2]) + 4.0 * g) * s2[k2];
+            sa += fabs(Rq[a2][k2]) * s2[k2] * fabs(Rq[b2][k2]);
+          }
+          eSig[a2][b2] = e + 2.0 * g * sa;
+          aSig[a2][b2] = fabs(Sig[a2][b2]) + eSig[a2][b2];
+        }
+      double eS2[2][2];
+      for (int a2 = 0; a2 < 2; ++a2)
+        for (int b2 = 0; b2 < 2; ++b2) {
+          double e = 0.0, sa = 0.0;
+          for (int k2 = 0; k2 < 3; ++k2)
+            for (int l2 = 0; l2 < 3; ++l2) {
+              e += eTW[a2][k2] * aSig[k2][l2] * aTW[b2][l2] + fabs(TW[a2][k2]) * eSig[k2][l2] * aTW[b2][l2] +
+                   fabs(TW[a2][k2]) * fabs(Sig[k2][l2]) * eTW[b2][l2];
+              sa += fabs(TW[a2][k2]) * fabs(Sig[k2][l2]) * fabs(TW[b2][l2]);
+            }
+          eS2[a2][b2] = e + g * sa;
+        }
+      const double exy = 0.5 * (eS2[0][1] + eS2[1][0]) + g * fabs(sxy);
+      const double eA00 = eS2[0][0] + g * A00, eA11 = eS2[1][1] + g * A11;
+      const double edeta = eA00 * A11 + A00 * eA11 + 2.0 * fabs(sxy) * exy + g * (A00 * A11 + sxy * sxy);
+      const double edet0 = eS2[0][0] * fabs(S2[1][1]) + fabs(S2[0][0]) * eS2[1][1] + 2.0 * fabs(sxy) * exy +
+                           g * (fabs(S2[0][0] * S2[1][1]) + sxy * sxy);
+      double E[6];
+      E[0] = cam->fx * (etc[0] / az + fabs(tc[0]) * etc[2] / (az * az)) + g * (fabs(u) + fabs(cam->cx));
+      E[1] = cam->fy * (etc[1] / az + fabs(tc[1]) * etc[2] / (az * az)) + g * (fabs(v) + fabs(cam->cy));
+      if (edeta < 0.5 * deta) {
+        const double id2 = 1.0 / (deta * deta);
+        E[2] = eA11 / deta + A11 * edeta * id2 + g * fabs(A11 / deta);
+        E[3] = exy / deta + fabs(sxy) * edeta * id2 + g * fabs(sxy / deta);
+        E[4] = eA00 / deta + A00 * edeta * id2 + g * fabs(A00 / deta);
+        const double eratio = edet0 / deta + fabs(det0) * edeta * id2 + g * fabs(ratio);
+        const double rhi = ratio + eratio, rlo = ratio - eratio;
+        E[5] = opacity[i] * (sqrt(rhi > 0.0 ? rhi : 0.0) - sqrt(rlo > 0.0 ? rlo : 0.0)) + g * o;
+      } else {
+        E[2] = E[3] = E[4] = E[5] = INFINITY;
+      }
+      const double X[6] = {u, v, A11 / deta, -sxy / deta, A00 / deta, o};
+      uint8_t amb = 0;
+      for (int k2 = 0; k2 < 6; ++k2) {
+        double alt;
+        if (float_rounding_alt(X[k2], 2.0 * E[k2], &alt)) amb |= (uint8_t)(1u << k2);
+        if (rec_alt) rec_alt[6 * i + k2] = alt;
+        if (rec_err) rec_err[6 * i + k2] = E[k2];
+      }
+      if (rec_amb) rec_amb[i] = amb;
+    }
+
     means2d[2 * i] = u;
     means2d[2 * i + 1] = v;
     conic[3 * i] = A11 / deta;
@@ -423,7 +546,8 @@ void orc_render_pixels(const orc_cfg *cfg, int64_t n, const int64_t *order,
       if (!(tx >= rc[0] && tx <= rc[2] && ty >= rc[1] && ty <= rc[3])) continue;
       ++nev;
       double dx = cx - means2d[2 * i], dy = cy - means2d[2 * i + 1];
-      double Q = conic[3 * i] * dx * dx + 2.0 * conic[3 * i + 1] * dx * dy + conic[3 * i + 2] * dy * dy;
+      double A = conic[3 * i], B = conic[3 * i + 1], Cc = conic[3 * i + 2];
+      double Q = A * dx * dx + 2.0 * B * dx * dy + Cc * dy * dy;
       double a = opac[i] * orc_kernel(cfg, x0, Q);
       if (a > cfg->alpha_max) a = cfg->alpha_max;
       if (fabs(a - cfg->eps) <= cfg->alpha_band) fl |= ORC_PIX_ALPHA_NEAR;

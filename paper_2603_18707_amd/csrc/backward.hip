@@ -65,6 +65,7 @@ __global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__
                                                   const float *__restrict__ dL_dimage, float *__restrict__ dmeans2d,
                                                   float *__restrict__ dconic, float *__restrict__ drgb) {
   __shared__ float4 L0[WAVE], L1[WAVE], L2[WAVE];
+  __shared__ float2 L3[WAVE];  // (a, b) of the conic, for the gradients
   __shared__ uint32_t Lid[WAVE];
   constexpr int ORDER = KIND == BLEND_POLY2 ? 2 : (KIND == BLEND_POLY3 ? 3 : 1);
   const int ntiles = p.gx * p.gy;
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__
   const int tx = tile % p.gx, ty = tile / p.gx;
   const int px = tx * TS + (lane & (TS - 1));
   const int py0 = ty * TS + (lane >> 4);
-  const float fx = (float)px + 0.5f;
+  const float fx = (float)(lane & (TS - 1)) + 0.5f;  // pixel centres relative to the tile corner
   const size_t plane = (size_t)p.W * p.H;
   float fy[PIX], T[PIX], Tf[PIX], S0[PIX], S1[PIX], S2[PIX], g0[PIX], g1[PIX], g2[PIX], bgg[PIX];
   uint32_t lastc[PIX];
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__
 #pragma unroll
   for (int k = 0; k < PIX; ++k) {
     const int py = py0 + 4 * k;
-    fy[k] = (float)py + 0.5f;
+    fy[k] = (float)((lane >> 4) + 4 * k) + 0.5f;
     S0[k] = S1[k] = S2[k] = 0.0f;
     if (px < p.W && py < p.H) {
       const size_t pix = (size_t)py * p.W + px;
@@ -117,10 +118,11 @@ __global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__
       const float4 co = reinterpret_cast<const float4 *>(conic_opacity)[id];
       const float3 c = make_float3(rgb[3 * id], rgb[3 * id + 1], rgb[3 * id + 2]);
       float4 a0, a1, a2;
-      fold<KIND>(m, co, c, p, a0, a1, a2);
+      fold<KIND>(m, co, c, (float)(tx * TS), (float)(ty * TS), p, a0, a1, a2);
       L0[lane] = a0;
       L1[lane] = a1;
       L2[lane] = a2;
+      L3[lane] = make_float2(co.x, co.y);
       Lid[lane] = id;
     }
     __syncthreads();
@@ -128,16 +130,10 @@ __global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__
       const uint32_t pos = (uint32_t)(lo + 1 + j);
       const float4 r0 = L0[j];
       const float4 r1 = L1[j];
-      const float dx = fx - r0.x;
-      const float adx = r0.z * dx;
-      const float R0 = fmaf(-adx, dx, r1.y);
-      const float P = r0.w * dx;
+      const RowPart rp = row_part(r0, r1.y, fx);
       float t[PIX];
 #pragma unroll
-      for (int k = 0; k < PIX; ++k) {
-        const float dy = fy[k] - r0.y;
-        t[k] = fmaf(-dy, fmaf(r1.x, dy, P), R0);
-      }
+      for (int k = 0; k < PIX; ++k) t[k] = t_at(rp, r1.x, fy[k]);
       bool inc[PIX];
       bool anyinc = false;
 #pragma unroll
@@ -147,7 +143,9 @@ __global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__
       }
       if (__ballot(anyinc) == 0ull) continue;
       const float4 r2 = L2[j];
+      const float2 ab = L3[j];
       const float o = r1.w;
+      const float dx = fx - r0.x;
       float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
 #pragma unroll
       for (int k = 0; k < PIX; ++k) {
@@ -164,9 +162,9 @@ __global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__
         S0[k] = fmaf(a, r2.x - S0[k], S0[k]);
         S1[k] = fmaf(a, r2.y - S1[k], S1[k]);
         S2[k] = fmaf(a, r2.z - S2[k], S2[k]);
-        // alpha = o' k(Q) unless clamped
+        // alpha = o' k(Q) unless clamped; Q from the same t the decisions used
         const float dy = fy[k] - r0.y;
-        const float Q = fmaf(dx, fmaf(r0.z, dx, r0.w * dy), r1.x * dy * dy);
+        const float Q = r1.y - t[k];
         float kq, dk;
         if (KIND == BLEND_EXP) {
           kq = __expf(-0.5f * Q);
@@ -182,8 +180,8 @@ __global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__
         gb = fmaf(dLdQ, 2.0f * dx * dy, gb);
         gc = fmaf(dLdQ, dy * dy, gc);
         // Q depends on the mean through d = pixel - mean
-        gu = fmaf(dLdQ, -(2.0f * r0.z * dx + r0.w * dy), gu);
-        gv = fmaf(dLdQ, -(r0.w * dx + 2.0f * r1.x * dy), gv);
+        gu = fmaf(dLdQ, -2.0f * (ab.x * dx + ab.y * dy), gu);
+        gv = fmaf(dLdQ, -2.0f * (ab.y * dx + r1.x * dy), gv);
       }
       gu = wave_sum(gu);
       gv = wave_sum(gv);

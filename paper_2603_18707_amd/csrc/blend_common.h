@@ -48,10 +48,22 @@ __device__ inline float opacity_threshold64(const BlendParams &p, int order, flo
   return (float)x;
 }
 
-// staged record: s0 = (u, v, a, 2b), s1 = (c, x_e, S, o'), s2 = (r, g, b, 0)
+// Staged record, positions relative to the tile's corner (x0, y0):
+//   s0 = (u - x0, v - y0, g, h), s1 = (c, x_e, S, o'), s2 = (r, g, b, 0)
+// with the quadratic form of the conic (a, b, c) completed in dy:
+//   Q = a dx^2 + 2 b dx dy + c dy^2 = c (dy + h dx)^2 + g dx^2,
+//   h = b / c, g = (a c - b^2) / c.
+// For a positive-definite conic both terms are non-negative, so the float
+// evaluation of t = x_e - Q suffers no cancellation: its error stays a few
+// ulps of x_e and Q. Long, thin footprints make the expanded terms orders of
+// magnitude larger than Q at pixels near their axis (1e5 against 1 in large
+// scenes), and an expanded evaluation loses that many ulps. The tile-local
+// positions keep the pixel offsets free of the rounding of absolute image
+// coordinates. A conic that is not positive definite gets x_e = -1 and a zero
+// quadric: it never passes.
 template <int KIND>
-__device__ inline void fold(float2 m, float4 co, float3 c, const BlendParams &p, float4 &s0, float4 &s1,
-                            float4 &s2) {
+__device__ inline void fold(float2 m, float4 co, float3 c, float x0, float y0, const BlendParams &p, float4 &s0,
+                            float4 &s1, float4 &s2) {
   const float o = co.w;
   float xe, S = 0.0f;
   if (KIND == BLEND_POLY1) {
@@ -62,9 +74,28 @@ __device__ inline void fold(float2 m, float4 co, float3 c, const BlendParams &p,
   } else {
     xe = opacity_threshold64(p, KIND == BLEND_POLY2 ? 2 : 3, o);
   }
-  s0 = make_float4(m.x, m.y, co.x, 2.0f * co.y);
-  s1 = make_float4(co.z, xe, S, o);
+  // a c - b^2 in double: both products of floats are exact there
+  const double det = fma((double)co.x, (double)co.z, -((double)co.y * (double)co.y));
+  const bool pd = co.x > 0.0f && co.z > 0.0f && det > 0.0;
+  const float rc = __builtin_amdgcn_rcpf(co.z);
+  s0 = make_float4(m.x - x0, m.y - y0, pd ? (float)(det * (double)rc) : 0.0f, pd ? co.y * rc : 0.0f);
+  s1 = make_float4(pd ? co.z : 0.0f, pd ? xe : -1.0f, S, o);
   s2 = make_float4(c.x, c.y, c.z, 0.0f);
+}
+
+// t = x_e - Q of a staged record at the tile-local pixel (fx, fy), in the
+// order both blend directions use (they must take identical decisions).
+// The dx-only part is split out for loops that reuse it over a column.
+struct RowPart {
+  float h, R0;  // h dx - v, x_e - g dx^2
+};
+__device__ inline RowPart row_part(const float4 &s0, float s1y, float fx) {
+  const float dx = fx - s0.x;
+  return RowPart{fmaf(s0.w, dx, -s0.y), fmaf(-s0.z * dx, dx, s1y)};
+}
+__device__ inline float t_at(const RowPart &r, float s1x, float fy) {
+  const float e = fy + r.h;  // dy + h dx
+  return fmaf(-s1x * e, e, r.R0);
 }
 
 template <int KIND>
@@ -83,22 +114,23 @@ __device__ inline float alpha_from(float t, const float4 &s1, const BlendParams 
   return fminf(a, p.alpha_max);
 }
 
-// Conservative box around the pixels a staged record can pass: the region
+// Conservative box around the pixels a record can pass: the region
 // t = x_e - Q >= 0 is an ellipse with half extents sqrt(x_e a / det) in y and
-// sqrt(x_e c / det) in x (det = a c - b^2, in double from the float record).
+// sqrt(x_e c / det) in x (det = a c - b^2, in double from the float conic).
 // The box is widened by a margin that covers the float rounding of t: near
 // the edge, t falls with distance at a rate ~2 x_e / extent, and its rounding
-// error is a few ulps of the largest term in the box. Degenerate records get
-// an unbounded box (no culling); records that never pass get an empty one.
-__device__ inline void pass_box(const float4 &s0, const float4 &s1, float &hx, float &hy) {
-  const double a = s0.z, b = 0.5 * (double)s0.w, c = s1.x, xe = s1.y;
-  if (!(xe >= 0.0)) {
+// error is below a few ulps of the largest expanded term in the box.
+// Records that never pass get an empty box; a margin too wide to matter
+// leaves the box unbounded (no culling).
+__device__ inline void pass_box(const float4 &co, float xe_f, float &hx, float &hy) {
+  const double a = co.x, b = co.y, c = co.z, xe = xe_f;
+  const double det = a * c - b * b;
+  if (!(xe >= 0.0) || !(det > 0.0) || !(a > 0.0) || !(c > 0.0)) {
     hx = hy = -__builtin_inff();
     return;
   }
-  const double det = a * c - b * b;
   hx = hy = __builtin_inff();
-  if (!(det > 0.0) || !(a > 0.0) || !(c > 0.0) || !(xe > 1e-12)) return;
+  if (!(xe > 1e-12)) return;
   const double ey = sqrt(xe * a / det), ex = sqrt(xe * c / det);
   const double big = (a + 2.0 * fabs(b) + c) * (ex + ey) * (ex + ey) + xe;
   const double rel = 1e-3 + 1e-6 * big / xe;
@@ -142,14 +174,14 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
   const int l64 = lane & (WAVE - 1);
   const int px = tx * TS + wx0 + l64 % WX;
   const int py0 = ty * TS + wy0 + l64 / WX;
-  const float fx = (float)px + 0.5f;
+  const float fx = (float)(wx0 + l64 % WX) + 0.5f;  // pixel centres relative to the tile corner
   float fy[P], T[P], C0[P], C1[P], C2[P];
   uint32_t ncon[P], last[P], nev[P], tested[P];
   bool alive[P];
 #pragma unroll
   for (int k = 0; k < P; ++k) {
     tested[k] = 0u;
-    fy[k] = (float)(py0 + RS * k) + 0.5f;
+    fy[k] = (float)(wy0 + l64 / WX + RS * k) + 0.5f;
     T[k] = 1.0f;
     C0[k] = C1[k] = C2[k] = 0.0f;
     ncon[k] = last[k] = 0u;
@@ -161,7 +193,7 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
     L0[NT] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     L1[NT] = make_float4(0.0f, -1.0f, 0.0f, 0.0f);
   }
-  const float tile_x0 = (float)(tx * TS) + 0.5f, tile_y0 = (float)(ty * TS) + 0.5f;
+  const float tile_x0 = (float)(tx * TS), tile_y0 = (float)(ty * TS);
 
   for (uint32_t b = start; b < end; b += NT) {
     bool any = false;
@@ -177,15 +209,16 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
       const float4 co = reinterpret_cast<const float4 *>(conic_opacity)[id];
       const float3 c = make_float3(rgb[3 * id], rgb[3 * id + 1], rgb[3 * id + 2]);
       float4 a0, a1, a2;
-      fold<KIND>(m, co, c, p, a0, a1, a2);
+      fold<KIND>(m, co, c, tile_x0, tile_y0, p, a0, a1, a2);
       L0[lane] = a0;
       L1[lane] = a1;
       L2[lane] = a2;
       float hx, hy;
-      pass_box(a0, a1, hx, hy);
+      pass_box(co, a1.y, hx, hy);
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
-        const float bx = tile_x0 + (float)((w % (TS / WX)) * WX), by = tile_y0 + (float)((w / (TS / WX)) * WY);
+        // first pixel centre of wave w's block, tile-local like the record
+        const float bx = 0.5f + (float)((w % (TS / WX)) * WX), by = 0.5f + (float)((w / (TS / WX)) * WY);
         if (a0.x + hx >= bx && a0.x - hx <= bx + (float)(WX - 1) && a0.y + hy >= by &&
             a0.y - hy <= by + (float)(WY - 1))
           mask |= 1u << w;
@@ -226,14 +259,10 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
         for (int q = 0; q < G; ++q) {
           const float4 r0 = L0[js[q]];
           const float2 r1 = *reinterpret_cast<const float2 *>(&L1[js[q]]);  // (c, x_e)
-          const float dx = fx - r0.x;
-          const float adx = r0.z * dx;
-          const float R0 = fmaf(-adx, dx, r1.y);
-          const float Pq = r0.w * dx;
+          const RowPart rp = row_part(r0, r1.y, fx);
 #pragma unroll
           for (int k = 0; k < P; ++k) {
-            const float dy = fy[k] - r0.y;
-            t[q][k] = fmaf(-dy, fmaf(r1.x, dy, Pq), R0);
+            t[q][k] = t_at(rp, r1.x, fy[k]);
             mx = fmaxf(mx, t[q][k]);
           }
         }

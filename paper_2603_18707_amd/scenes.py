@@ -251,3 +251,29 @@ def binning_inputs(n: int, grid_w: int, grid_h: int, seed: int, culled: float = 
     rect[dead] = (0, 0, -1, -1)
     tiles = np.where(dead, 0, w * h).astype(np.uint32)
     return depth, rect.astype(np.int32), tiles
+
+
+def thin_footprint_records(width: int, height: int, n: int = 12, seed: int = 7) -> dict:
+    """Projected records (the float values, held as float64) of n footprints
+    150-250 px long (standard deviation) and 0.4-1.2 px wide at angles spread
+    over (0, pi), centred in the middle of the image, depths ascending in
+    index order, each rectangle covering the whole tile grid. Near their axis
+    the expanded terms of the quadratic form reach 1e5 while the form itself
+    stays O(1). Keys: means2d, conic (a, b, c), opac, rgb, depth32, rect,
+    flags."""
+    rng = np.random.default_rng(seed)
+    ang = np.linspace(0.1, math.pi - 0.1, n)
+    s1, s2 = rng.uniform(150, 250, n), rng.uniform(0.4, 1.2, n)
+    cs, sn = np.cos(ang), np.sin(ang)
+    # inverse of R diag(s1^2, s2^2) R^T
+    a = cs * cs / s1 ** 2 + sn * sn / s2 ** 2
+    b = cs * sn * (1 / s1 ** 2 - 1 / s2 ** 2)
+    c = sn * sn / s1 ** 2 + cs * cs / s2 ** 2
+    gw, gh = (width + 15) // 16, (height + 15) // 16
+    rec = dict(means2d=np.stack([rng.uniform(0.3, 0.7, n) * width, rng.uniform(0.3, 0.7, n) * height], 1),
+               conic=np.stack([a, b, c], 1), opac=rng.uniform(0.5, 0.99, n), rgb=rng.uniform(0, 1, (n, 3)),
+               depth32=np.sort(rng.uniform(1, 5, n)).astype(np.float32),
+               rect=np.tile(np.array([0, 0, gw - 1, gh - 1], np.int32), (n, 1)), flags=np.zeros(n, np.uint8))
+    for k in ("means2d", "conic", "opac", "rgb"):
+        rec[k] = rec[k].astype(np.float32).astype(np.float64)
+    return rec

@@ -28,8 +28,11 @@ def coeffs_for(order):
 
 
 def oracle_cfg(kind, order, radius, **kw):
+    """The oracle's configuration for a GPU comparison: the library takes its
+    scalar parameters as float, so the oracle gets the same float values."""
     return ocore.Cfg(kind=0 if kind == "exp" else 1, order=order, radius_mode=RADIUS[radius],
-                     coeffs=coeffs_for(order), alpha_band=ALPHA_BAND[(kind, order if kind == "poly" else 1)], **kw)
+                     coeffs=coeffs_for(order), alpha_band=ALPHA_BAND[(kind, order if kind == "poly" else 1)],
+                     **kw).float_params()
 
 
 def gpu_kernel(kind, order, radius):
@@ -59,3 +62,36 @@ def edge_flagged_tiles(proj, gx, gy):
         y0, y1 = int(np.floor((v - r) / 16)) - 1, int(np.floor((v + r) / 16)) + 1
         bad[max(0, y0):max(0, min(gy, y1 + 1)), max(0, x0):max(0, min(gx, x1 + 1))] = True
     return bad
+
+
+def records_chosen_by(o, g_means2d, g_conic_opacity, live):
+    """The float records the GPU projection chose among the correct ones.
+
+    The oracle bounds the FP64 error of each record entry X (u, v, a, b, c,
+    o') by E; any correct evaluation lies within 2 E of X, so its float lies
+    between fl(X - 2 E) and fl(X + 2 E), rounding being monotone. Outside the
+    entries the oracle flags as ambiguous that interval holds only the
+    oracle's own float; inside, usually also one neighbour (the oracle's
+    alternative), more where E is wide. Each entry of a live splat must lie
+    in its interval, else this fails. Returns the oracle's projection with
+    the records set to those members of the oracle's intervals (held as
+    float64) and the number of entries that are not the oracle's own float.
+    """
+    X = np.concatenate([o["means2d"], o["conic"], o["opac"][:, None]], axis=1)
+    own = X.astype(np.float32)
+    amb = ((o["rec_amb"][:, None].astype(np.int64) >> np.arange(6)) & 1).astype(bool)
+    w = 2.0 * o["rec_err"]
+    lo, hi = (X - w).astype(np.float32), (X + w).astype(np.float32)
+    got = np.concatenate([g_means2d, g_conic_opacity[:, :3], g_conic_opacity[:, 3:4]], axis=1).astype(np.float32)
+    same = got == own
+    other = amb & (got >= lo) & (got <= hi) & ~same & live[:, None]
+    bad = live[:, None] & ~(same | other)
+    if bad.any():
+        i, k = np.argwhere(bad)[0]
+        raise AssertionError(f"{int(bad.sum())} record entries outside the oracle's interval of correct floats; "
+                             f"first: splat {i} entry {'uvabco'[k]} gpu {got[i, k]!r} oracle {own[i, k]!r} "
+                             f"interval [{lo[i, k]!r}, {hi[i, k]!r}] ambiguous {bool(amb[i, k])}")
+    chosen = np.where(other, got, own).astype(np.float64)
+    rec = ocore.round_records(o)
+    rec["means2d"], rec["conic"], rec["opac"] = chosen[:, 0:2].copy(), chosen[:, 2:5].copy(), chosen[:, 5].copy()
+    return rec, int(other.sum())

@@ -38,18 +38,20 @@ def _gpu_frame(scene, cam, kind, order, radius, params=None, capacity=None, want
 
 
 def _check_projection(g, o, rect_exempt):
-    """GPU preprocess against the oracle projection."""
+    """GPU preprocess against the oracle projection. Returns the records for
+    compositing: the oracle's floats, with the other correct rounding where
+    the GPU took it (see helpers.records_chosen_by)."""
     ok = ~rect_exempt
     assert np.array_equal(_np(g["depth"]), o["depth32"]), "depth"
     assert np.array_equal(_np(g["rect"])[ok], o["rect"][ok]), "rect"
     assert np.array_equal(_np(g["tiles"]).astype(np.int64)[ok], o["tiles"][ok]), "tiles"
     vis = ok & (o["tiles"] > 0)
-    gm, gc, gr = _np(g["means2d"]), _np(g["conic_opacity"]), _np(g["rgb"])
-    assert np.allclose(gm[vis], o["means2d"][vis], rtol=2e-7, atol=1e-5)
-    scale = np.abs(o["conic"][vis]).max(axis=1, keepdims=True)
-    assert np.all(np.abs(gc[vis, :3] - o["conic"][vis]) <= 1e-6 * scale + 1e-30)
-    assert np.allclose(gc[vis, 3], o["opac"][vis], rtol=1e-6, atol=1e-9)
+    rec, nalt = H.records_chosen_by(o, _np(g["means2d"]), _np(g["conic_opacity"]), vis)
+    if nalt:
+        print(f"[proj] {nalt} record entries took the other correct rounding")
+    gr = _np(g["rgb"])
     assert np.allclose(gr[vis], o["rgb"][vis], rtol=1e-6, atol=4e-6)  # colour is evaluated in float32
+    return rec
 
 
 def _check_binning(g, o, gx, gy, exempt):
@@ -90,10 +92,10 @@ def test_tiny_full_frame(kind, order, radius):
     o = ocore.project(scene, cam, cfg)
     g = _gpu_frame(scene, cam, kind, order, radius)
     exempt = (o["flags"] & ocore.SPLAT_EDGE_NEAR) != 0
-    _check_projection(g["proj"], o, exempt)
+    rec = _check_projection(g["proj"], o, exempt)
     _check_binning(g, o, 8, 8, exempt)
     pix = ocore.all_pixels(128, 128)
-    ores = ocore.render_pixels(ocore.round_records(o), cfg, pix)
+    ores = ocore.render_pixels(rec, cfg, pix)
     nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, 8, 8))
     assert nflag <= 0.002 * pix.shape[0]
     assert float(np.abs(ores["color"]).max()) > 0.5  # not an empty frame
@@ -138,10 +140,10 @@ def test_ragged_image_sizes(size):
     g = _gpu_frame(scene, cam, "poly", 1, "opacity")
     gx, gy = (W + 15) // 16, (Hh + 15) // 16
     exempt = (o["flags"] & ocore.SPLAT_EDGE_NEAR) != 0
-    _check_projection(g["proj"], o, exempt)
+    rec = _check_projection(g["proj"], o, exempt)
     _check_binning(g, o, gx, gy, exempt)
     pix = ocore.all_pixels(W, Hh)
-    ores = ocore.render_pixels(ocore.round_records(o), cfg, pix)
+    ores = ocore.render_pixels(rec, cfg, pix)
     _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, gx, gy))
 
 
@@ -178,8 +180,9 @@ def test_background_colour():
     cfg = H.oracle_cfg("poly", 1, "opacity", bg=bg)
     g = _gpu_frame(scene, cam, "poly", 1, "opacity", params=H.gpu_params(bg=bg))
     o = ocore.project(scene, cam, cfg)
+    rec = _check_projection(g["proj"], o, (o["flags"] & ocore.SPLAT_EDGE_NEAR) != 0)
     pix = ocore.all_pixels(128, 128)
-    ores = ocore.render_pixels(ocore.round_records(o), cfg, pix)
+    ores = ocore.render_pixels(rec, cfg, pix)
     _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, 8, 8))
 
 
@@ -194,11 +197,11 @@ def test_scene_scale_sampled(kind, order, radius):
     g = _gpu_frame(scene, cam, kind, order, radius)
     exempt = (o["flags"] & ocore.SPLAT_EDGE_NEAR) != 0
     assert exempt.sum() <= 4
-    _check_projection(g["proj"], o, exempt)
+    rec = _check_projection(g["proj"], o, exempt)
     K = _check_binning(g, o, 120, 68, exempt)
     assert K > 1_000_000
     pix = scenes.sample_pixels(1920, 1080, 4096, seed=21)
-    ores = ocore.render_pixels(ocore.round_records(o), cfg, pix)
+    ores = ocore.render_pixels(rec, cfg, pix)
     nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, 120, 68))
     print(f"K={K} flagged={nflag} max_err={err:.3g}")
     assert nflag <= 0.01 * pix.shape[0]
@@ -237,3 +240,57 @@ def test_counting_build_matches_and_bounds(kind, order, radius):
         tested = _np(b["n_tested"]).astype(np.int64)
         assert np.all(tested <= a["n_eval"]) and np.all(tested >= a["n_contrib"])
         assert tested.sum() < a["n_eval"].astype(np.int64).sum()  # the box test skips something here
+
+
+def _records_frame(rec, cam, kind, order, radius, nt=256):
+    """Blends hand-made projected records (dict of numpy arrays) through gs_bin_sort and gs_rasterize_fwd."""
+    r = render.Rasterizer(H.gpu_kernel(kind, order, radius), H.gpu_params(blend_threads=nt))
+    dev = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).cuda()
+    co = np.concatenate([rec["conic"], rec["opac"][:, None]], axis=1)
+    proj = dict(n=rec["opac"].shape[0], means2d=dev(rec["means2d"], np.float32), conic_opacity=dev(co, np.float32),
+                rgb=dev(rec["rgb"], np.float32), depth=dev(rec["depth32"], np.float32),
+                rect=dev(rec["rect"], np.int32), tiles=dev(binning.tile_count(rec["rect"]), np.int32))
+    b = r.bin_sort_fit(proj, cam)
+    out = r.rasterize(proj, b, cam, want_eval=True)
+    torch.cuda.synchronize()
+    return {k: _np(v).copy() for k, v in out.items() if v is not None}
+
+
+@pytest.mark.parametrize("kind,order,radius", [("poly", 1, "opacity"), ("exp", 1, "sigma3"), ("poly", 3, "opacity")])
+def test_long_thin_footprints_every_pixel(kind, order, radius):
+    """Every pixel within 2e-4 of the oracle for footprints whose quadratic
+    form, expanded, cancels by five orders of magnitude along their axis."""
+    W, Hh = 320, 256
+    cam = scenes.tiny_camera(W, Hh)
+    rec = scenes.thin_footprint_records(W, Hh)
+    g = _records_frame(rec, cam, kind, order, radius)
+    cfg = H.oracle_cfg(kind, order, radius)
+    pix = ocore.all_pixels(W, Hh)
+    ores = ocore.render_pixels(rec, cfg, pix)
+    good = ores["flags"] == 0
+    err = np.abs(g["image"].reshape(3, -1).T - ores["color"]).max(axis=1)
+    print(f"flagged={int((~good).sum())} max_err={err[good].max():.3g}")
+    assert (~good).sum() <= 0.01 * pix.shape[0]
+    assert err[good].max() <= 2e-4
+    assert np.array_equal(g["n_contrib"].ravel()[good], ores["n_contrib"][good])
+
+
+def test_conic_not_positive_definite_is_never_blended():
+    """Records whose conic is indefinite, singular or NaN blend nothing: the
+    frame equals the one with their opacity at zero (which never passes)."""
+    W, Hh = 320, 256
+    cam = scenes.tiny_camera(W, Hh)
+    rec = scenes.thin_footprint_records(W, Hh)
+    bad = dict(rec)
+    bad["conic"] = rec["conic"].copy()
+    bad["conic"][2] = (1.0, 2.0, 1.0)        # indefinite
+    bad["conic"][5] = (0.5, 0.0, 0.0)        # c = 0
+    bad["conic"][8] = (np.nan, 0.0, 1.0)
+    off = dict(rec)
+    off["opac"] = rec["opac"].copy()
+    off["opac"][[2, 5, 8]] = 0.0
+    for kind, order, radius in (("poly", 1, "opacity"), ("exp", 1, "sigma3")):
+        a = _records_frame(bad, cam, kind, order, radius)
+        b = _records_frame(off, cam, kind, order, radius)
+        for k in ("image", "final_T", "n_contrib", "last_contrib", "n_eval"):
+            assert np.array_equal(a[k], b[k]), k

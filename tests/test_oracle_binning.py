@@ -45,3 +45,29 @@ def test_invariants_and_fast_path():
         inside = np.nonzero((r[:, 0] <= tx) & (tx <= r[:, 2]) & (r[:, 1] <= ty) & (ty <= r[:, 3]))[0]
         got = vals[ranges[t, 0]:ranges[t, 1]]
         assert sorted(got.tolist()) == inside.tolist()
+
+
+def test_tile_histogram_and_tile_list_match_the_full_binning():
+    """The per-tile helpers used at frame sizes too large to bin whole agree
+    with the full loop binning (ties in depth included)."""
+    sc, cam = scenes.workload_tiny()
+    sc.scales *= 2.0
+    p = core.project(sc, cam, core.Cfg(kind=core.KERNEL_EXP, radius_mode=core.RADIUS_SIGMA3))
+    depth = p["depth32"].copy()
+    depth[1::7] = depth[0]  # equal depths must fall back to index order
+    gx, gy = 8, 8
+    keys, vals, ranges = binning.bin_and_sort(p["rect"], depth, gx, gy)
+    hist = binning.tile_histogram(p["rect"], gx, gy)
+    assert np.array_equal(hist, (ranges[:, 1].astype(np.int64) - ranges[:, 0]))
+    assert hist.sum() == keys.shape[0]
+    for t in range(gx * gy):
+        kb, v = binning.tile_list(p["rect"], depth, t % gx, t // gx)
+        lo, hi = ranges[t]
+        assert np.array_equal(v, vals[lo:hi])
+        assert np.array_equal(kb.astype(np.uint64), keys[lo:hi] & np.uint64(0xFFFFFFFF))
+
+
+def test_tile_histogram_edges():
+    rect = np.array([[0, 0, 2, 1], [2, 1, 2, 1], [1, 0, 0, 0], [0, 0, -1, -1]], np.int32)
+    h = binning.tile_histogram(rect, 3, 2).reshape(2, 3)
+    assert h.tolist() == [[1, 1, 1], [1, 1, 2]]

@@ -164,9 +164,9 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
   constexpr int WY = TS * TS / NW / WX;
   constexpr int RS = WAVE / WX;     // row stride between a lane's pixels
   constexpr int G = 8;              // splats tested per step
-  static_assert(NT % G == 0, "a staged batch holds whole steps");
+  static_assert(NT % G == 0 && G == 8, "a staged batch holds whole steps of eight 16-bit slots");
   __shared__ float4 L0[NT + 1], L1[NT + 1], L2[NT + 1];   // slot NT: neutral record
-  __shared__ uint16_t lst[NW][NT + G];
+  __shared__ __align__(16) uint16_t lst[NW][NT + G];  // rows of 16-byte multiples, read 8 slots at a time
   __shared__ uint32_t wcnt[NW][NW];                      // [staging wave][shading wave]
   const int lane = threadIdx.x, wv = lane / WAVE;
   const uint64_t lt = (1ull << (lane & (WAVE - 1))) - 1ull;
@@ -249,10 +249,14 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
       // G splats per step: all G records are read and tested before the one
       // branch that skips the step when no pixel of the lane passes (most
       // steps); the blend then visits the G splats in list order
+      // the next step's eight list slots are read while this step computes,
+      // so a step starts with one LDS round trip (its records), not two
+      uint4 jn = *reinterpret_cast<const uint4 *>(&lst[wv][0]);
       for (uint32_t i = 0; i < len; i += G) {
-        int js[G];
-#pragma unroll
-        for (int q = 0; q < G; ++q) js[q] = lst[wv][i + q];
+        const uint4 jc = jn;
+        if (i + G < len) jn = *reinterpret_cast<const uint4 *>(&lst[wv][i + G]);
+        const int js[G] = {(int)(jc.x & 0xFFFFu), (int)(jc.x >> 16), (int)(jc.y & 0xFFFFu), (int)(jc.y >> 16),
+                           (int)(jc.z & 0xFFFFu), (int)(jc.z >> 16), (int)(jc.w & 0xFFFFu), (int)(jc.w >> 16)};
         float t[G][P];
         float mx = -1.0f;
 #pragma unroll

@@ -50,7 +50,7 @@ constexpr int STRIPES = 8;              // copies of the digit totals
 constexpr int SHORT_IPT = 4;            // copies per thread when sorting short lists (<= 1024)
 constexpr int LONG_IPT = 16;            // copies per thread in a chunk of a long list (4096)
 
-enum : int { CTR_KEYS = 0, CTR_SLOTS = 16 };
+enum : int { CTR_KEYS = 0, CTR_SPLIT = 1, CTR_SLOTS = 16 };
 
 // totals[stripe][pass][digit]
 __device__ inline uint32_t *total_at(uint32_t *tot, int stripe, int pass, int d) {
@@ -432,6 +432,13 @@ __global__ void tile_ranges(const uint32_t *__restrict__ tkey, const uint32_t *_
 // list, so starting the long lists first keeps them off the tail of the blend
 // (and of the segment sort). The order inside a bucket is unspecified. One
 // workgroup.
+// Lists of at most WAVE_MAX copies are sorted by one wave alone. Length
+// buckets are floor(16 log2(len + 1)): 254 copies fall in bucket 127 and
+// 255 in bucket 128, so in the longest-first order every longer list comes
+// before every such one, and the order kernel records where they start.
+constexpr uint32_t WAVE_MAX = 254;
+constexpr int WAVE_BUCKET = 127;
+
 __device__ inline int length_bucket(const uint32_t *ranges, int64_t t) {
   const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
   const int b = (int)(log2f((float)len + 1.0f) * 16.0f);
@@ -439,7 +446,7 @@ __device__ inline int length_bucket(const uint32_t *ranges, int64_t t) {
 }
 
 __global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t *__restrict__ ranges, int64_t ntiles,
-                                                          uint32_t *__restrict__ order) {
+                                                          uint32_t *__restrict__ order, uint32_t *__restrict__ split) {
   constexpr int NB = 256;
   __shared__ uint32_t hist[NB];
   __shared__ uint32_t wsum[NB / 64];
@@ -458,6 +465,7 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t *__rest
     uint32_t off = inc - v;
     for (int k = 0; k < (int)(threadIdx.x >> 6); ++k) off += wsum[k];
     hist[threadIdx.x] = off;
+    if (split && threadIdx.x == 255 - WAVE_BUCKET) *split = off;  // first position of a list <= WAVE_MAX
   }
   __syncthreads();
   for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
@@ -511,6 +519,7 @@ struct Seg {
   uint32_t *sbits, *svals;               // scratch with the same indexing (lists longer than 4096)
   uint64_t *keys;                        // outputs
   uint32_t *vout;
+  const uint32_t *split;                 // with an order: first position of a list <= WAVE_MAX
 };
 
 // A stable LSD radix sort of one tile's list by depth bits, by a workgroup. The keys are the depth bits minus the tile's smallest one (same
@@ -728,14 +737,169 @@ constexpr uint32_t SHORT_MAX = BS * SHORT_IPT;  // longest list the short instan
 // follows, a list shorter than LONG_STOP (buckets are 1/16 of a doubling wide).
 constexpr uint32_t LONG_STOP = 940;
 
-// lists of at most SHORT_MAX copies, one workgroup per tile
+// LDS of one wave sorting a list of at most WAVE_MAX copies
+struct WaveLds {
+  uint32_t Kb[WAVE_MAX], Vb[WAVE_MAX], wc[RADIX];
+};
+
+// orders a wave's LDS writes before its later reads by other lanes
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The same stable LSD sort as sort_list for a list of n <= WAVE_MAX copies,
+// by one wave and without workgroup barriers: copy i = r * 64 + lane is held
+// by lane `lane` in round r, rounds are ranked in order (earlier copies
+// first, so equal keys keep their order), and the 256 digit counts are
+// scanned by the wave, four per lane.
+__device__ inline void sort_list_wave(const Seg &a, uint32_t t, uint32_t start, uint32_t n, WaveLds &wl) {
+  constexpr int IPT = 4;
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const uint32_t R = (n + 63) / 64;
+  uint32_t key[IPT], val[IPT], rk[IPT];
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const uint32_t i = (uint32_t)r * 64u + (uint32_t)lane;
+    const bool mine = i < n;
+    key[r] = mine ? a.bits[start + i] : 0u;
+    val[r] = mine ? a.vals[start + i] : 0u;
+    if (mine) {
+      mn = min(mn, key[r]);
+      mx = max(mx, key[r]);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor((int)mn, o, 64));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+  }
+  const uint32_t span = mx - mn;
+  const int passes = span ? (32 - __clz(span) + 7) / 8 : 0;
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) key[r] -= mn;  // unused slots are never read
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+#pragma unroll
+    for (int j = 0; j < RADIX / 64; ++j) wl.wc[j * 64 + lane] = 0u;
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      if ((uint32_t)r < R) {  // uniform over the wave
+        const bool valid = (uint32_t)r * 64u + (uint32_t)lane < n;
+        const uint32_t d = (key[r] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const bool bit = (d >> b) & 1u;
+          const uint64_t bb = __ballot(bit);
+          peers &= bit ? bb : ~bb;
+        }
+        const uint32_t before = wl.wc[d];
+        rk[r] = before + (uint32_t)__popcll(peers & lt);
+        wave_sync();
+        if (valid && (peers & lt) == 0ull) wl.wc[d] = before + (uint32_t)__popcll(peers);
+        wave_sync();
+      }
+    }
+    {  // exclusive offsets of the 256 digits: lane takes digits 4 lane .. 4 lane + 3
+      uint32_t c[4], sum = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        c[j] = wl.wc[4 * lane + j];
+        sum += c[j];
+      }
+      uint32_t off = wave_inclusive<uint32_t>(sum) - sum;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        wl.wc[4 * lane + j] = off;
+        off += c[j];
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      if ((uint32_t)r * 64u + (uint32_t)lane < n) {
+        const uint32_t pos = wl.wc[(key[r] >> shift) & 255u] + rk[r];
+        if (pos < n) {  // always, when the counts are consistent
+          wl.Kb[pos] = key[r];
+          wl.Vb[pos] = val[r];
+        }
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const uint32_t i = (uint32_t)r * 64u + (uint32_t)lane;
+      if (i < n) {
+        key[r] = wl.Kb[i];
+        val[r] = wl.Vb[i];
+      }
+    }
+    wave_sync();
+  }
+  const uint64_t tkey = (uint64_t)t << 32;
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const uint32_t i = (uint32_t)r * 64u + (uint32_t)lane;
+    if (i < n) {
+      a.keys[start + i] = tkey | (uint64_t)(key[r] + mn);
+      a.vout[start + i] = val[r];
+    }
+  }
+}
+
+// Lists of at most SHORT_MAX copies. With a longest-first order, workgroup
+// b < S (S = the first position of a list of at most WAVE_MAX copies) takes
+// position b alone and sorts it with all its waves; the later workgroups
+// take four consecutive positions from S on, one wave each, side by side.
+// Without an order every workgroup takes one tile. Either way a list is
+// sorted by the whole workgroup when it is longer than WAVE_MAX, else by
+// one wave; the grid has one workgroup per tile and the spare ones exit.
 __global__ __launch_bounds__(BS) void segment_sort_short(Seg a) {
-  __shared__ SortLds<SHORT_IPT> sl;
-  if ((int64_t)blockIdx.x >= a.ntiles) return;
-  const uint32_t t = a.order ? min(a.order[blockIdx.x], (uint32_t)(a.ntiles - 1)) : blockIdx.x;
-  const uint32_t start = a.ranges[2 * (size_t)t], end = a.ranges[2 * (size_t)t + 1];
-  if (end <= start || end - start > SHORT_MAX) return;
-  sort_list<SHORT_IPT>(a, t, start, end - start, sl);
+  __shared__ union {
+    SortLds<SHORT_IPT> sl;
+    WaveLds wl[BS / 64];
+  } lds;
+  constexpr int NQ = BS / 64;
+  const int w = threadIdx.x >> 6;
+  const int64_t S = a.split ? min((int64_t)*a.split, a.ntiles) : a.ntiles;
+  const int64_t b = blockIdx.x;
+  int64_t first;
+  int cnt;
+  if (b < S) {
+    first = b;
+    cnt = 1;
+  } else {
+    first = S + NQ * (b - S);
+    cnt = NQ;
+  }
+  if (first >= a.ntiles) return;
+  uint32_t tt[NQ], st[NQ], nn[NQ];
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {
+    const int64_t pos = first + j;
+    nn[j] = 0u;
+    tt[j] = 0u;
+    st[j] = 0u;
+    if (j < cnt && pos < a.ntiles) {
+      tt[j] = a.order ? min(a.order[pos], (uint32_t)(a.ntiles - 1)) : (uint32_t)pos;
+      st[j] = a.ranges[2 * (size_t)tt[j]];
+      const uint32_t e = a.ranges[2 * (size_t)tt[j] + 1];
+      nn[j] = e > st[j] ? e - st[j] : 0u;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NQ; ++j) {  // uniform over the workgroup
+    if (nn[j] > WAVE_MAX && nn[j] <= SHORT_MAX) {
+      sort_list<SHORT_IPT>(a, tt[j], st[j], nn[j], lds.sl);
+      __syncthreads();  // the LDS is reused
+    }
+  }
+  if (nn[w] > 0u && nn[w] <= WAVE_MAX) sort_list_wave(a, tt[w], st[w], nn[w], lds.wl[w]);
 }
 
 // longer lists. With a longest-first tile order they come first, so a small
@@ -891,7 +1055,8 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
     // 3. per-tile ranges, longest-first order, then each tile's list by depth
     hipLaunchKernelGGL(tile_ranges, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, (const uint32_t *)w.tk[cur],
                        count_dev, ntiles, ranges);
-    if (tile_order) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order);
+    if (tile_order)
+      hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order, w.ctr + CTR_SPLIT);
     Seg g{};
     g.ranges = ranges;
     g.order = tile_order;
@@ -902,13 +1067,15 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
     g.svals = w.tv[cur ^ 1];
     g.keys = keys;
     g.vout = vals;
+    g.split = tile_order ? w.ctr + CTR_SPLIT : nullptr;
     hipLaunchKernelGGL(segment_sort_short, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
     const unsigned lgrid = tile_order ? (unsigned)(ntiles < 2048 ? ntiles : 2048) : (unsigned)ntiles;
     hipLaunchKernelGGL(segment_sort_long, dim3(lgrid), dim3(BS), 0, s, g);
     return hipGetLastError();
   }
   // nothing emitted (or no room): ranges stay zero
-  if (tile_order) hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order);
+  if (tile_order)
+    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order, (uint32_t *)nullptr);
   return hipGetLastError();
 }
 

@@ -7,11 +7,12 @@
 //  1. the copies, emitted in splat-index order, are grouped by tile with a
 //     stable LSD radix sort on the ceil(log2 tiles) tile bits only (two 7-bit
 //     passes at 1080p), so inside a tile they stay in index order;
-//  2. one workgroup per tile sorts its list stably by depth bits: in LDS when
-//     it holds at most 4096 copies (all lists at 1080p and 1M splats), in
-//     chunks through global memory otherwise. Keys are offset by the tile's
-//     smallest depth, so only the bits that vary inside the tile are sorted
-//     (usually 3 of 4 bytes).
+//  2. each tile's list is sorted stably by depth bits: by one wave when it
+//     holds at most 254 copies, by a workgroup in LDS up to 1024 copies and
+//     in 1024-copy chunks through global memory beyond that, all in one
+//     kernel (longest lists dispatched first, so they overlap the rest).
+//     Keys are offset by the tile's smallest depth, so only the bits that
+//     vary inside the tile are sorted (usually 3 of 4 bytes).
 // A radix pass of step 1 is three kernels and no workgroup ever waits on
 // another (a hand-off between workgroups costs ~0.5 us through memory, and
 // device atomics on scattered addresses cost more than the pass itself):
@@ -47,8 +48,7 @@ constexpr int RADIX = 256;              // max buckets per pass (8-bit digits)
 static_assert(BS == RADIX, "per-digit steps give one digit to each thread");
 constexpr int MAX_TILE_PASSES = 4;      // tile ids < 2^30 need at most four digits of <= 8 bits
 constexpr int STRIPES = 8;              // copies of the digit totals
-constexpr int SHORT_IPT = 4;            // copies per thread when sorting short lists (<= 1024)
-constexpr int LONG_IPT = 16;            // copies per thread in a chunk of a long list (4096)
+constexpr int SEG_IPT = 4;              // copies per thread of a workgroup's list sort (1024 in LDS)
 
 enum : int { CTR_KEYS = 0, CTR_SPLIT = 1, CTR_SLOTS = 16 };
 
@@ -522,14 +522,14 @@ struct Seg {
   const uint32_t *split;                 // with an order: first position of a list <= WAVE_MAX
 };
 
-// A stable LSD radix sort of one tile's list by depth bits, by a workgroup. The keys are the depth bits minus the tile's smallest one (same
-// order, same ties), and only the bytes that vary are sorted, low byte
-// first, with the list spread over all four waves (ceil(n / 256) rounds of
-// 64 per wave). IPT = SHORT_IPT sorts the lists of at most 1024 copies
-// (nearly all of them) with little LDS and few registers, so many tiles run
-// per CU; IPT = LONG_IPT takes the longer ones: in LDS up to 4096 copies,
-// beyond that chunk by chunk through global memory. Returns with the
-// workgroup converged.
+// A stable LSD radix sort of one tile's list by depth bits, by a workgroup.
+// The keys are the depth bits minus the tile's smallest one (same order,
+// same ties), and only the bytes that vary are sorted, low byte first, with
+// the list spread over all four waves (ceil(n / 256) rounds of 64 per wave).
+// Up to BS * IPT copies are sorted in LDS; a longer list is sorted chunk by
+// chunk through global memory (per pass a digit count over the whole list,
+// then the chunks in order, ranked in registers and written to the other
+// buffer). Returns with the workgroup converged.
 template <int IPT>
 struct SortLds {
   uint32_t Kb[BS * IPT], Vb[BS * IPT];
@@ -542,7 +542,6 @@ template <int IPT>
 __device__ __forceinline__ void sort_list(const Seg &a, uint32_t t, uint32_t start, uint32_t n, SortLds<IPT> &sl) {
   constexpr int SEG_IPT = IPT;
   constexpr int SEG_CAP = BS * IPT;
-  constexpr bool SHORT = IPT == SHORT_IPT;
   uint32_t *Kb = sl.Kb, *Vb = sl.Vb, *run = sl.run, *s_mn = sl.s_mn, *s_mx = sl.s_mx;
   uint32_t (*wc)[RADIX] = sl.wc;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -657,7 +656,6 @@ __device__ __forceinline__ void sort_list(const Seg &a, uint32_t t, uint32_t sta
     return;
   }
 
-  if (SHORT) return;  // not reached: short lists fit in LDS
   // long list: each pass is a digit count over the whole list, then the list
   // in order, SEG_CAP at a time, ranked in registers and written to the other
   // buffer (the last pass writes the outputs)
@@ -731,11 +729,6 @@ __device__ __forceinline__ void sort_list(const Seg &a, uint32_t t, uint32_t sta
     }
   }
 }
-
-constexpr uint32_t SHORT_MAX = BS * SHORT_IPT;  // longest list the short instance sorts
-// No list longer than SHORT_MAX shares a tile-order length bucket with, or
-// follows, a list shorter than LONG_STOP (buckets are 1/16 of a doubling wide).
-constexpr uint32_t LONG_STOP = 940;
 
 // LDS of one wave sorting a list of at most WAVE_MAX copies
 struct WaveLds {
@@ -852,16 +845,16 @@ __device__ inline void sort_list_wave(const Seg &a, uint32_t t, uint32_t start, 
   }
 }
 
-// Lists of at most SHORT_MAX copies. With a longest-first order, workgroup
-// b < S (S = the first position of a list of at most WAVE_MAX copies) takes
-// position b alone and sorts it with all its waves; the later workgroups
-// take four consecutive positions from S on, one wave each, side by side.
-// Without an order every workgroup takes one tile. Either way a list is
-// sorted by the whole workgroup when it is longer than WAVE_MAX, else by
-// one wave; the grid has one workgroup per tile and the spare ones exit.
-__global__ __launch_bounds__(BS) void segment_sort_short(Seg a) {
+// Every tile's list. With a longest-first order, workgroup b < S (S = the
+// first position of a list of at most WAVE_MAX copies) takes position b
+// alone and sorts it with all its waves; the later workgroups take four
+// consecutive positions from S on, one wave each, side by side. Without an
+// order every workgroup takes one tile. Either way a list is sorted by the
+// whole workgroup when it is longer than WAVE_MAX, else by one wave; the
+// grid has one workgroup per tile and the spare ones exit.
+__global__ __launch_bounds__(BS) void segment_sort(Seg a) {
   __shared__ union {
-    SortLds<SHORT_IPT> sl;
+    SortLds<SEG_IPT> sl;
     WaveLds wl[BS / 64];
   } lds;
   constexpr int NQ = BS / 64;
@@ -894,28 +887,12 @@ __global__ __launch_bounds__(BS) void segment_sort_short(Seg a) {
   }
 #pragma unroll
   for (int j = 0; j < NQ; ++j) {  // uniform over the workgroup
-    if (nn[j] > WAVE_MAX && nn[j] <= SHORT_MAX) {
-      sort_list<SHORT_IPT>(a, tt[j], st[j], nn[j], lds.sl);
+    if (nn[j] > WAVE_MAX) {
+      sort_list<SEG_IPT>(a, tt[j], st[j], nn[j], lds.sl);
       __syncthreads();  // the LDS is reused
     }
   }
   if (nn[w] > 0u && nn[w] <= WAVE_MAX) sort_list_wave(a, tt[w], st[w], nn[w], lds.wl[w]);
-}
-
-// longer lists. With a longest-first tile order they come first, so a small
-// grid walks the order and stops at the first clearly short list; without
-// one it visits every tile.
-__global__ __launch_bounds__(BS) void segment_sort_long(Seg a) {
-  __shared__ SortLds<LONG_IPT> sl;
-  for (int64_t pos = blockIdx.x; pos < a.ntiles; pos += gridDim.x) {
-    const uint32_t t = a.order ? min(a.order[pos], (uint32_t)(a.ntiles - 1)) : (uint32_t)pos;
-    const uint32_t start = a.ranges[2 * (size_t)t], end = a.ranges[2 * (size_t)t + 1];
-    const uint32_t n = end > start ? end - start : 0u;
-    if (a.order && n < LONG_STOP) break;
-    if (n <= SHORT_MAX) continue;
-    sort_list<LONG_IPT>(a, t, start, n, sl);
-    __syncthreads();  // the next list reuses the LDS
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1068,9 +1045,7 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
     g.keys = keys;
     g.vout = vals;
     g.split = tile_order ? w.ctr + CTR_SPLIT : nullptr;
-    hipLaunchKernelGGL(segment_sort_short, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
-    const unsigned lgrid = tile_order ? (unsigned)(ntiles < 2048 ? ntiles : 2048) : (unsigned)ntiles;
-    hipLaunchKernelGGL(segment_sort_long, dim3(lgrid), dim3(BS), 0, s, g);
+    hipLaunchKernelGGL(segment_sort, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
     return hipGetLastError();
   }
   // nothing emitted (or no room): ranges stay zero

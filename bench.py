@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--only", default=None, help="time one configuration: poly1|exp")
     ap.add_argument("--blend-threads", type=int, default=0, help="64|128|256; 0 = autotune")
+    ap.add_argument("--rect", default="box", choices=("box", "square"),
+                    help="tile rectangles of the headline frames: the ellipse's bounding box or the bounding square")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-view measurement")
     ap.add_argument("--no-train", action="store_true", help="skip the forward+backward step measurement")
     ap.add_argument("--copy-probe", action="store_true",
@@ -73,11 +75,16 @@ def kernel_source_hash():
     return h.hexdigest()[:12]
 
 
-def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, threads=0):
+RECT_MODES = {"square": 0, "box": 1}
+RECT_NAMES = {"square": "bounding-square tile rectangles", "box": "ellipse-box tile rectangles"}
+
+
+def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, threads=0, rect="box"):
     """Times `steps` frames; per-stage HIP events inside the same timed loop.
     threads = 0 lets the autotuner pick the blend launch shape during warm-up."""
     from paper_2603_18707_amd import autotune
     r = render.Rasterizer(render.kernel_spec(kind, order, radius))
+    r.params.rect_mode = RECT_MODES[rect]
     stream = torch.cuda.current_stream()
     # warm-up frames also size the key capacity (host readback happens here only)
     for _ in range(max(warmup, 1)):
@@ -233,13 +240,13 @@ def time_train_step(torch, render, scenes, steps):
             "ms_per_step": round(ms, 3), "views_per_s": round(4 / (ms * 1e-3), 1), "loss": float(loss)}
 
 
-def cpu_baseline(scene_np, cam, gpu_image, target_s):
+def cpu_baseline(scene_np, cam, gpu_image, target_s, rect_mode):
     """The FP64 oracle on a bounded pixel sample of the same frame (poly-1, opacity radius)."""
     from oracle import core as ocore
 
     c = (0.773, -0.773 / 4.386)
     cfg = ocore.Cfg(kind=ocore.KERNEL_POLY, order=1, radius_mode=ocore.RADIUS_POLY_OPACITY, coeffs=c,
-                    alpha_band=2e-6).float_params()
+                    alpha_band=2e-6, rect_mode=rect_mode).float_params()
     t0 = time.perf_counter()
     proj = ocore.project(scene_np, cam, cfg)
     rec = ocore.round_records(proj)
@@ -293,9 +300,10 @@ def main():
         configs = [c for c in configs if c[0] == a.only]
     res = {}
     for name, kind, order, radius in configs:
-        res[name] = time_config(torch, render, scene, cam, kind, order, radius, a.steps, a.warmup, a.blend_threads)
+        res[name] = time_config(torch, render, scene, cam, kind, order, radius, a.steps, a.warmup, a.blend_threads,
+                                a.rect)
         r = res[name]
-        print(f"[bench] {name}: {r['ms']:.3f} ms/frame (pre {r['stage_ms'][0]:.3f}, sort {r['stage_ms'][1]:.3f},"
+        print(f"[bench] {name} ({a.rect}): {r['ms']:.3f} ms/frame (pre {r['stage_ms'][0]:.3f}, sort {r['stage_ms'][1]:.3f},"
               f" blend {r['stage_ms'][2]:.3f}) K={r['K']} E={r['E']} threads={r['threads']} tuned={r['tuned']}",
               file=sys.stderr, flush=True)
 
@@ -319,9 +327,10 @@ def main():
         "metric": METRIC, "value": round(mpix, 2), "unit": "Mpix/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "1M splats (64 clusters, SH3), 1920x1080, poly-1 kernel, opacity-dependent radius",
+        "config": {"workload": "1M splats (64 clusters, SH3), 1920x1080, poly-1 kernel, opacity-dependent radius, "
+                               + RECT_NAMES[a.rect],
                    "splats": scene.n, "width": W, "height": H, "kernel": "poly1", "radius": "opacity",
-                   "blend_threads": head["threads"]},
+                   "rect": RECT_NAMES[a.rect], "blend_threads": head["threads"]},
         "splat_pixel_evals_per_s": round(evals, 1),
         "keys": head["K"], "evals": head["E"], "list_entries": head["E_list"], "blended": head["B"],
         "stage_ms": {"preprocess": round(head["stage_ms"][0], 4), "bin_sort": round(head["stage_ms"][1], 4),
@@ -339,6 +348,21 @@ def main():
                                           "bin_sort": round(e["stage_ms"][1], 4),
                                           "blend": round(e["stage_ms"][2], 4)}}
         out["speedup_vs_exp_sigma3"] = round(e["ms"] / ms, 4)
+    if not a.only:
+        other = "square" if a.rect == "box" else "box"
+        alt = {"rect": RECT_NAMES[other]}
+        for name, kind, order, radius in configs:
+            t = time_config(torch, render, scene, cam, kind, order, radius, a.steps, a.warmup, a.blend_threads, other)
+            print(f"[bench] {name} ({other}): {t['ms']:.3f} ms/frame (pre {t['stage_ms'][0]:.3f}, sort "
+                  f"{t['stage_ms'][1]:.3f}, blend {t['stage_ms'][2]:.3f}) K={t['K']} E={t['E']}", file=sys.stderr,
+                  flush=True)
+            alt[name] = {"ms_per_step": round(t["ms"], 4), "Mpix_per_s": round(W * H / (t["ms"] * 1e-3) / 1e6, 2),
+                         "keys": t["K"], "evals": t["E"],
+                         "stage_ms": {"preprocess": round(t["stage_ms"][0], 4), "bin_sort": round(t["stage_ms"][1], 4),
+                                      "blend": round(t["stage_ms"][2], 4)}}
+        if "exp" in alt and "poly1" in alt:
+            alt["speedup_poly1_vs_exp"] = round(alt["exp"]["ms_per_step"] / alt["poly1"]["ms_per_step"], 4)
+        out["other_rect"] = alt
     if not a.no_batched and not a.only:
         print("[bench] batched multi-view ...", file=sys.stderr, flush=True)
         out["batched"] = time_batched(torch, render, scenes, max(2, a.steps // 10))
@@ -349,7 +373,7 @@ def main():
         print(f"[bench] train: {out['train_step']}", file=sys.stderr, flush=True)
     if not a.no_cpu and hname == "poly1":
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
-        cb, err, nflag, m = cpu_baseline(scene_np, cam, head["image"].cpu().numpy(), a.cpu_seconds)
+        cb, err, nflag, m = cpu_baseline(scene_np, cam, head["image"].cpu().numpy(), a.cpu_seconds, RECT_MODES[a.rect])
         out["cpu_baseline"] = cb
         out["max_abs_err_vs_oracle"] = err
         out["oracle_flagged_pixels"] = f"{nflag} of {m}"

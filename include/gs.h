@@ -71,6 +71,18 @@ typedef enum {
   GS_RADIUS_EXP_OPACITY = 3
 } gs_radius_mode;
 
+/* Tile rectangle of a splat (rect and tiles_touched of gs_preprocess).
+ *   SQUARE:      the tiles met by the square of half side r = k sqrt(lambda_max)
+ *                around the mean (the bounding square of Sec. 2.1).
+ *   ELLIPSE_BOX: the tiles met by the axis-aligned bounding box of the
+ *                ellipse Q = k^2, half sides k sqrt(S_a,xx) and k sqrt(S_a,yy)
+ *                (times radius_pad), a subset of SQUARE's: the tighter
+ *                rectangle of the bounds the paper surveys (Sec. 2.2). With
+ *                the POLY_* and EXP_OPACITY radii, k^2 bounds where alpha >= eps,
+ *                so images do not change, only the copies that cannot
+ *                contribute are dropped. */
+typedef enum { GS_RECT_SQUARE = 0, GS_RECT_ELLIPSE_BOX = 1 } gs_rect_mode;
+
 typedef struct {
   int32_t kind;        /* gs_kernel_kind */
   int32_t order;       /* polynomial order N in 1..3 (read for POLY and for POLY_* radii) */
@@ -93,6 +105,7 @@ typedef struct {
   int32_t blend_threads; /* launch shape of the blend: threads per 16x16 tile, 64, 128 or 256
                             (4, 2 or 1 pixels per thread); 0 = the library's default. Results
                             do not depend on it. */
+  int32_t rect_mode;     /* gs_rect_mode */
 } gs_params;
 
 typedef struct {
@@ -123,7 +136,7 @@ gs_status gs_kernel_default(int32_t kind, int32_t order, int32_t radius_mode, gs
 gs_status gs_kernel_root(const gs_kernel *kernel, double *x0_out);
 
 /* eps 1/255, alpha_max 0.99, t_min 1e-4, aa_v 0.3, near_z 0.2,
- * radius_pad 1 + 2^-20, bg 0, tile 16, blend_threads 0. */
+ * radius_pad 1 + 2^-20, bg 0, tile 16, blend_threads 0, rect_mode SQUARE. */
 gs_status gs_params_default(gs_params *out);
 
 /* ---------------------------------------------------------------------- */
@@ -139,9 +152,11 @@ gs_status gs_params_default(gs_params *out);
  *   view); anti-aliasing S_a = S' + aa_v I, o' = o sqrt(|S'| / |S_a|);
  *   conic = S_a^-1; mean2d = (fx t.x/t.z + cx, fy t.y/t.z + cy);
  *   r = k sqrt(lambda_max(S_a)) * radius_pad (k per gs_radius_mode);
+ *   half sides (hx, hy) = (r, r) for GS_RECT_SQUARE, else
+ *   k (sqrt(S_a,xx), sqrt(S_a,yy)) * radius_pad (gs_rect_mode);
  *   rect = inclusive tile rectangle (x_lo, y_lo, x_hi, y_hi) with
- *   x_lo = clamp(floor((u - r)/tile), 0, gx), x_hi = clamp(floor((u + r)/tile), -1, gx - 1)
- *   and likewise in y, stored as (0, 0, -1, -1) when empty;
+ *   x_lo = clamp(floor((u - hx)/tile), 0, gx), x_hi = clamp(floor((u + hx)/tile), -1, gx - 1)
+ *   and likewise in y with hy, stored as (0, 0, -1, -1) when empty;
  *   tiles_touched = tiles in rect;
  *   rgb = max(sum_k Y_k(d) sh_k + 0.5, 0) with real SH of degree sh_degree at
  *   d = normalize(mu - camera centre).

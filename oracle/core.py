@@ -26,6 +26,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 KERNEL_EXP, KERNEL_POLY = 0, 1
+RECT_SQUARE, RECT_ELLIPSE_BOX = 0, 1
 RADIUS_SIGMA3, RADIUS_POLY_UNIVERSAL, RADIUS_POLY_OPACITY, RADIUS_EXP_OPACITY = 0, 1, 2, 3
 
 SPLAT_EDGE_NEAR, SPLAT_CULL_NEAR = 1, 2
@@ -37,7 +38,7 @@ class _Cfg(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("c", ctypes.c_double * 4), ("eps", ctypes.c_double),
                 ("alpha_max", ctypes.c_double), ("t_min", ctypes.c_double), ("aa_v", ctypes.c_double),
                 ("near_z", ctypes.c_double), ("radius_pad", ctypes.c_double), ("bg", ctypes.c_double * 3),
-                ("alpha_band", ctypes.c_double), ("t_band_rel", ctypes.c_double)]
+                ("alpha_band", ctypes.c_double), ("t_band_rel", ctypes.c_double), ("rect_mode", ctypes.c_int32)]
 
 
 class _Cam(ctypes.Structure):
@@ -70,6 +71,9 @@ class Cfg:
     # widths of the "too close to call in single precision" bands
     alpha_band: float = 2e-6
     t_band_rel: float = 1e-4
+    # tile rectangle: 0 = bounding square of radius r (Sec. 2.1), 1 = the
+    # ellipse Q = k^2's axis-aligned bounding box
+    rect_mode: int = 0
 
     def float_params(self) -> "Cfg":
         """A copy whose scalar parameters (eps, alpha_max, t_min, aa_v, near_z,
@@ -91,7 +95,7 @@ class Cfg:
         c.near_z, c.radius_pad = self.near_z, self.radius_pad
         for i in range(3):
             c.bg[i] = float(self.bg[i])
-        c.alpha_band, c.t_band_rel = self.alpha_band, self.t_band_rel
+        c.alpha_band, c.t_band_rel, c.rect_mode = self.alpha_band, self.t_band_rel, self.rect_mode
         return c
 
 

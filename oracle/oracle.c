@@ -36,6 +36,7 @@
 #include <string.h>
 
 enum { ORC_KERNEL_EXP = 0, ORC_KERNEL_POLY = 1 };
+enum { ORC_RECT_SQUARE = 0, ORC_RECT_ELLIPSE_BOX = 1 };
 enum {
   ORC_RADIUS_SIGMA3 = 0,
   ORC_RADIUS_POLY_UNIVERSAL = 1,
@@ -63,6 +64,7 @@ typedef struct {
   double bg[3];        /* background colour */
   double alpha_band;   /* |alpha - eps| below this flags a pixel */
   double t_band_rel;   /* |T' - t_min| below t_min * this flags a pixel */
+  int32_t rect_mode;   /* ORC_RECT_*: bounding square of radius r, or the ellipse's own box */
 } orc_cfg;
 
 typedef struct {
@@ -366,8 +368,17 @@ void orc_project(const orc_cfg *cfg, const orc_cam *cam, int64_t n,
     if (cull_near) flags[i] |= ORC_SPLAT_CULL_NEAR;
     if (cull) continue;
     double r = k * sqrt(lmax) * cfg->radius_pad;
+    /* the rectangle's half sides: the square of radius r around the mean
+     * (Sec. 2.1), or the axis-aligned box of the ellipse Q = k^2, whose half
+     * sides are k times the standard deviations along x and y (the square
+     * roots of the anti-aliased covariance's diagonal) */
+    double hx = r, hy = r;
+    if (cfg->rect_mode == ORC_RECT_ELLIPSE_BOX) {
+      hx = k * sqrt(A00) * cfg->radius_pad;
+      hy = k * sqrt(A11) * cfg->radius_pad;
+    }
 
-    double ex0 = (u - r) / T, ex1 = (u + r) / T, ey0 = (v - r) / T, ey1 = (v + r) / T;
+    double ex0 = (u - hx) / T, ex1 = (u + hx) / T, ey0 = (v - hy) / T, ey1 = (v + hy) / T;
     if (near_integer(ex0) || near_integer(ex1) || near_integer(ey0) || near_integer(ey1))
       flags[i] |= ORC_SPLAT_EDGE_NEAR;
     long xlo = clamp_floor(ex0, 0, gx), xhi = clamp_floor(ex1, -1, gx - 1);

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libgs.so")
 GS_OK, GS_EINVAL, GS_EUNSUPPORTED, GS_ECAPACITY, GS_EHIP = 0, -1, -2, -3, -4
 KERNEL_EXP, KERNEL_POLY = 0, 1
 RADIUS_SIGMA3, RADIUS_POLY_UNIVERSAL, RADIUS_POLY_OPACITY, RADIUS_EXP_OPACITY = 0, 1, 2, 3
+RECT_SQUARE, RECT_ELLIPSE_BOX = 0, 1
 
 
 class GsKernel(ctypes.Structure):
@@ -25,7 +26,8 @@ class GsKernel(ctypes.Structure):
 class GsParams(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
                 ("aa_v", ctypes.c_float), ("near_z", ctypes.c_float), ("radius_pad", ctypes.c_float),
-                ("bg", ctypes.c_float * 3), ("tile", ctypes.c_int32), ("blend_threads", ctypes.c_int32)]
+                ("bg", ctypes.c_float * 3), ("tile", ctypes.c_int32), ("blend_threads", ctypes.c_int32),
+                ("rect_mode", ctypes.c_int32)]
 
 
 class GsCamera(ctypes.Structure):

@@ -78,6 +78,8 @@ gs_status check_params(const gs_params *p) {
     if (!std::isfinite(p->bg[i])) return fail(GS_EINVAL, "bg must be finite");
   if (p->blend_threads != 0 && p->blend_threads != 64 && p->blend_threads != 128 && p->blend_threads != 256)
     return fail(GS_EINVAL, "blend_threads %d must be 0, 64, 128 or 256", p->blend_threads);
+  if (p->rect_mode != GS_RECT_SQUARE && p->rect_mode != GS_RECT_ELLIPSE_BOX)
+    return fail(GS_EINVAL, "rect_mode %d must be 0 (square) or 1 (ellipse box)", p->rect_mode);
   return GS_OK;
 }
 
@@ -186,6 +188,7 @@ gs_status gs_params_default(gs_params *out) {
   out->bg[0] = out->bg[1] = out->bg[2] = 0.0f;
   out->tile = 16;
   out->blend_threads = 0;
+  out->rect_mode = GS_RECT_SQUARE;
   return GS_OK;
 }
 
@@ -212,6 +215,7 @@ gs_status gs_preprocess(const gs_camera *cam, const gs_kernel *kernel, const gs_
   p.order = r.order;
   p.sh_degree = sh_degree;
   p.tile = params->tile;
+  p.rect_mode = params->rect_mode;
   for (int i = 0; i < 4; ++i) p.c[i] = r.c[i];
   p.k_universal = std::sqrt(r.x0);
   p.eps = params->eps;
@@ -363,6 +367,7 @@ gs_status gs_preprocess_bwd(const gs_camera *cam, const gs_kernel *kernel, const
   p.order = r.order;
   p.sh_degree = sh_degree;
   p.tile = params->tile;
+  p.rect_mode = params->rect_mode;
   for (int i = 0; i < 4; ++i) p.c[i] = r.c[i];
   p.k_universal = std::sqrt(r.x0);
   p.eps = params->eps;
@@ -458,6 +463,7 @@ gs_status gs_render_batched(const gs_kernel *kernel, const gs_params *params, co
   p.order = r.order;
   p.sh_degree = scenes[0].sh_degree;
   p.tile = params->tile;
+  p.rect_mode = params->rect_mode;
   for (int i = 0; i < 4; ++i) p.c[i] = r.c[i];
   p.k_universal = std::sqrt(r.x0);
   p.eps = params->eps;

@@ -43,7 +43,7 @@ struct CamD {
 
 struct PreParams {
   CamD cam;
-  int radius_mode, order, sh_degree, tile;
+  int radius_mode, order, sh_degree, tile, rect_mode;
   double c[4];
   double k_universal;    // sqrt(x0) for POLY_UNIVERSAL
   double eps, aa_v, near_z, pad;

@@ -222,12 +222,15 @@ __device__ inline bool project_one(const PreParams &p, int64_t i, const float *_
     const double disc = mid * mid - deta;
     const double lmax = mid + sqrt(disc > 0.0 ? disc : 0.0);
     const double r = k * sqrt(lmax) * p.pad;
+    // half sides: the bounding square of radius r, or the ellipse Q = k^2's own box
+    const double hx = p.rect_mode == GS_RECT_ELLIPSE_BOX ? k * sqrt(Axx) * p.pad : r;
+    const double hy = p.rect_mode == GS_RECT_ELLIPSE_BOX ? k * sqrt(Ayy) * p.pad : r;
     const double u = cam.fx * t[0] * iz + cam.cx;
     const double v = cam.fy * t[1] * iz + cam.cy;
     // x / T as x * (1 / T): exact, T being a power of two (16, checked on the host)
     const double iT = 1.0 / (double)p.tile;
-    const long xlo = clamp_floor((u - r) * iT, 0, cam.gx), xhi = clamp_floor((u + r) * iT, -1, cam.gx - 1);
-    const long ylo = clamp_floor((v - r) * iT, 0, cam.gy), yhi = clamp_floor((v + r) * iT, -1, cam.gy - 1);
+    const long xlo = clamp_floor((u - hx) * iT, 0, cam.gx), xhi = clamp_floor((u + hx) * iT, -1, cam.gx - 1);
+    const long ylo = clamp_floor((v - hy) * iT, 0, cam.gy), yhi = clamp_floor((v + hy) * iT, -1, cam.gy - 1);
     if (xhi >= xlo && yhi >= ylo) {
       rc = make_int4((int)xlo, (int)ylo + row_base, (int)xhi, (int)yhi + row_base);
       ntiles = (uint32_t)((xhi - xlo + 1) * (yhi - ylo + 1));

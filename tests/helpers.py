@@ -53,14 +53,14 @@ def gpu_params(**kw):
 
 
 def edge_flagged_tiles(proj, gx, gy):
-    """Tiles next to an edge of a splat the oracle flagged (edge on a tile boundary)."""
+    """Tiles next to an edge of a splat the oracle flagged (edge on a tile
+    boundary): its rectangle (kept, clamped, for such splats) grown by one."""
     bad = np.zeros((gy, gx), bool)
     for i in np.nonzero(proj["flags"] & ocore.SPLAT_EDGE_NEAR)[0]:
-        u, v = proj["means2d"][i]
-        r = proj["radius"][i]
-        x0, x1 = int(np.floor((u - r) / 16)) - 1, int(np.floor((u + r) / 16)) + 1
-        y0, y1 = int(np.floor((v - r) / 16)) - 1, int(np.floor((v + r) / 16)) + 1
-        bad[max(0, y0):max(0, min(gy, y1 + 1)), max(0, x0):max(0, min(gx, x1 + 1))] = True
+        x0, y0, x1, y1 = (int(v) for v in proj["rect"][i])
+        xa, xb = min(x0, x1) - 1, max(x0, x1) + 1
+        ya, yb = min(y0, y1) - 1, max(y0, y1) + 1
+        bad[max(0, ya):max(0, min(gy, yb + 1)), max(0, xa):max(0, min(gx, xb + 1))] = True
     return bad
 
 

@@ -294,3 +294,43 @@ def test_conic_not_positive_definite_is_never_blended():
         b = _records_frame(off, cam, kind, order, radius)
         for k in ("image", "final_T", "n_contrib", "last_contrib", "n_eval"):
             assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("kind,order,radius", [("exp", 1, "sigma3"), ("poly", 1, "opacity"), ("poly", 2, "universal"),
+                                               ("exp", 1, "exp_opacity")])
+def test_ellipse_box_rectangles_full_frame(kind, order, radius):
+    """GS_RECT_ELLIPSE_BOX: rectangles, keys and every pixel against the oracle
+    in the same mode."""
+    scene, cam = scenes.workload_tiny()
+    scene.scales *= 2.0
+    cfg = H.oracle_cfg(kind, order, radius, rect_mode=ocore.RECT_ELLIPSE_BOX)
+    o = ocore.project(scene, cam, cfg)
+    g = _gpu_frame(scene, cam, kind, order, radius, params=H.gpu_params(rect_mode=1))
+    exempt = (o["flags"] & ocore.SPLAT_EDGE_NEAR) != 0
+    rec = _check_projection(g["proj"], o, exempt)
+    _check_binning(g, o, 8, 8, exempt)
+    pix = ocore.all_pixels(128, 128)
+    ores = ocore.render_pixels(rec, cfg, pix)
+    nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, 8, 8))
+    assert nflag <= 0.002 * pix.shape[0]
+
+
+@pytest.mark.parametrize("kind,order,radius", [("exp", 1, "sigma3"), ("poly", 1, "opacity")])
+def test_ellipse_box_scene_scale_sampled(kind, order, radius):
+    """1M splats at 1080p with ellipse-box rectangles: keys bit-exact, fewer
+    keys than the square's, sampled pixels against the oracle."""
+    scene, cam = scenes.workload_scene()
+    cfg = H.oracle_cfg(kind, order, radius, rect_mode=ocore.RECT_ELLIPSE_BOX)
+    o = ocore.project(scene, cam, cfg)
+    g = _gpu_frame(scene, cam, kind, order, radius, params=H.gpu_params(rect_mode=1))
+    exempt = (o["flags"] & ocore.SPLAT_EDGE_NEAR) != 0
+    assert exempt.sum() <= 4
+    rec = _check_projection(g["proj"], o, exempt)
+    K = _check_binning(g, o, 120, 68, exempt)
+    square = ocore.project(scene, cam, H.oracle_cfg(kind, order, radius))
+    assert K < 0.85 * int(square["tiles"].sum())
+    pix = scenes.sample_pixels(1920, 1080, 4096, seed=22)
+    ores = ocore.render_pixels(rec, cfg, pix)
+    nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, 120, 68))
+    print(f"K={K} flagged={nflag} max_err={err:.3g}")
+    assert nflag <= 0.01 * pix.shape[0]

@@ -320,7 +320,7 @@ def main():
     if os.path.exists(prof):
         with open(prof) as f:
             pc = json.load(f)
-        if pc.get("kernel_source_sha1") == kernel_source_hash():
+        if pc.get("kernel_source_sha1") == kernel_source_hash() and pc.get("rect") == a.rect:
             traffic = pc.get("hbm_bytes_per_launch")
 
     out = {

@@ -77,7 +77,7 @@ typedef enum {
  *   ELLIPSE_BOX: the tiles met by the axis-aligned bounding box of the
  *                ellipse Q = k^2, half sides k sqrt(S_a,xx) and k sqrt(S_a,yy)
  *                (times radius_pad), a subset of SQUARE's: the tighter
- *                rectangle of the bounds the paper surveys (Sec. 2.2). With
+ *                rectangle of the bounds the paper surveys (Sec. 2.1). With
  *                the POLY_* and EXP_OPACITY radii, k^2 bounds where alpha >= eps,
  *                so images do not change, only the copies that cannot
  *                contribute are dropped. */

@@ -132,13 +132,15 @@ def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, t
                 threads=int(r.params.blend_threads), tuned=tuned)
 
 
-def time_batched(torch, render, scenes, steps):
+def time_batched(torch, render, scenes, steps, rect):
     """96 views of 6 scenes (100k-2M splats): per-view sequential frames against
     one batched frame (eager, then replayed from a captured HIP graph)."""
-    from paper_2603_18707_amd import batch
+    from paper_2603_18707_amd import _lib, batch
     sc_np, views = scenes.workload_batched()
     dev = [render.to_device(s) for s in sc_np]
     kern = render.kernel_spec("poly", 1, "opacity")
+    params = _lib.gs_params_default()
+    params.rect_mode = RECT_MODES[rect]
     stream = torch.cuda.current_stream()
     npix = sum(int(c.width) * int(c.height) for _, c in views)
 
@@ -146,6 +148,7 @@ def time_batched(torch, render, scenes, steps):
     rs = []
     for si, cam in views:
         r = render.Rasterizer(kern)
+        r.params.rect_mode = RECT_MODES[rect]
         f = r.render(dev[si], cam)
         r.capacity = int(int(f["binned"]["num_keys"].item()) * 1.05) + 4096
         rs.append(r)
@@ -164,7 +167,7 @@ def time_batched(torch, render, scenes, steps):
     seq_ms = a.elapsed_time(b) / steps
     del rs
 
-    br = batch.BatchRenderer(dev, views, kern)
+    br = batch.BatchRenderer(dev, views, kern, params)
     K = br.render_fit()
     br.capacity = int(K * 1.05) + 4096
     br._layout()
@@ -186,7 +189,8 @@ def time_batched(torch, render, scenes, steps):
     torch.cuda.synchronize()
     graph_ms = a.elapsed_time(b) / steps
     assert int(br.overflow.item()) == 0
-    return {"workload": "6 scenes (100k-2M splats, SH3), 96 views 640x360..1920x1080, poly-1/opacity",
+    return {"workload": "6 scenes (100k-2M splats, SH3), 96 views 640x360..1920x1080, poly-1/opacity, "
+                        + RECT_NAMES[rect],
             "pixels": npix, "keys": K, "pairs": br.pairs,
             "per_view_sequential_ms": round(seq_ms, 3), "batched_eager_ms": round(eager_ms, 3),
             "batched_graph_ms": round(graph_ms, 3),
@@ -365,7 +369,7 @@ def main():
         out["other_rect"] = alt
     if not a.no_batched and not a.only:
         print("[bench] batched multi-view ...", file=sys.stderr, flush=True)
-        out["batched"] = time_batched(torch, render, scenes, max(2, a.steps // 10))
+        out["batched"] = time_batched(torch, render, scenes, max(2, a.steps // 10), a.rect)
         print(f"[bench] batched: {out['batched']}", file=sys.stderr, flush=True)
     if not a.no_train and not a.only:
         print("[bench] training step ...", file=sys.stderr, flush=True)

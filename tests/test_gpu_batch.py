@@ -102,3 +102,17 @@ def test_full_size_batched_workload_sampled_views():
         o = br.view_outputs(i)
         for k in ref[j]:
             assert np.array_equal(o[k].cpu().numpy(), ref[j][k]), (i, k)
+
+
+@pytest.mark.parametrize("kind,order,radius", [("poly", 1, "opacity"), ("exp", 1, "sigma3")])
+def test_batched_equals_per_view_ellipse_box(kind, order, radius):
+    """Ellipse-box tile rectangles in the batched path: bit-identical to the
+    per-view frames in the same mode."""
+    sc, views = _small_batch()
+    dev = [render.to_device(s) for s in sc]
+    print(f"[gpu] batch {kind}{order}/{radius} ellipse box", flush=True)
+    ref = _per_view(dev, views, (kind, order, radius), {"rect_mode": 1})
+    br = batch.BatchRenderer(dev, views, H.gpu_kernel(kind, order, radius), H.gpu_params(rect_mode=1))
+    br.render_fit()
+    torch.cuda.synchronize()
+    _compare(br, ref)

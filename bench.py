@@ -57,6 +57,7 @@ def parse():
                     help="tile rectangles of the headline frames: the ellipse's bounding box or the bounding square")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-view measurement")
     ap.add_argument("--no-train", action="store_true", help="skip the forward+backward step measurement")
+    ap.add_argument("--no-heavy", action="store_true", help="skip the 4M-splat heavy-tailed scene")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -198,6 +199,31 @@ def time_batched(torch, render, scenes, steps, rect):
             "speedup_graph_vs_sequential": round(seq_ms / graph_ms, 3),
             "tuned": {"blend_threads": int(br.params.blend_threads), "workgroups": int(br.workgroups),
                       "candidates_ms": {f"{k[0]}x{k[1]}": round(v, 3) for k, v in tuned.items()}}}
+
+
+def time_heavy(torch, render, scenes, steps, rect):
+    """The 4M-splat heavy-tailed scene (Student-t log-scales), one orbit view at
+    1920x1080 and one at 3840x2160: poly-1/opacity against exp/3 sigma, in the
+    headline's rectangle mode, and at 4K also in the other one."""
+    import math
+    sc, _ = scenes.workload_heavy()
+    dev = render.to_device(sc)
+    out = {"workload": "4M splats (Student-t log-scales, SH3), orbit views 0 (1920x1080) and 1 (3840x2160)"}
+    other = "square" if rect == "box" else "box"
+    for label, (w, h, view), modes in (("1080p", (1920, 1080, 0), (rect,)), ("4k", (3840, 2160, 1), (rect, other))):
+        cam = scenes.orbit_camera(w, h, 2.0 * math.pi * view / 8)
+        for mode in modes:
+            row = {}
+            for name, kind, order, radius in (("poly1", "poly", 1, "opacity"), ("exp", "exp", 1, "sigma3")):
+                t = time_config(torch, render, dev, cam, kind, order, radius, steps, 2, 0, mode)
+                row[name] = {"ms_per_step": round(t["ms"], 3), "Mpix_per_s": round(w * h / (t["ms"] * 1e-3) / 1e6, 1),
+                             "keys": t["K"], "stage_ms": [round(x, 3) for x in t["stage_ms"]]}
+                print(f"[bench] heavy {label} {mode} {name}: {t['ms']:.3f} ms K={t['K']}", file=sys.stderr, flush=True)
+                del t
+                torch.cuda.empty_cache()
+            row["speedup_poly1_vs_exp"] = round(row["exp"]["ms_per_step"] / row["poly1"]["ms_per_step"], 4)
+            out[f"{label}_{'ellipse_box' if mode == 'box' else 'square'}"] = row
+    return out
 
 
 def time_train_step(torch, render, scenes, steps):
@@ -371,6 +397,9 @@ def main():
         print("[bench] batched multi-view ...", file=sys.stderr, flush=True)
         out["batched"] = time_batched(torch, render, scenes, max(2, a.steps // 10), a.rect)
         print(f"[bench] batched: {out['batched']}", file=sys.stderr, flush=True)
+    if not a.no_heavy and not a.only:
+        print("[bench] heavy scene ...", file=sys.stderr, flush=True)
+        out["heavy"] = time_heavy(torch, render, scenes, max(3, a.steps // 5), a.rect)
     if not a.no_train and not a.only:
         print("[bench] training step ...", file=sys.stderr, flush=True)
         out["train_step"] = time_train_step(torch, render, scenes, max(3, a.steps // 10))

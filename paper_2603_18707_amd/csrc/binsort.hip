@@ -49,6 +49,12 @@ static_assert(BS == RADIX, "per-digit steps give one digit to each thread");
 constexpr int MAX_TILE_PASSES = 4;      // tile ids < 2^30 need at most four digits of <= 8 bits
 constexpr int STRIPES = 8;              // copies of the digit totals
 constexpr int SEG_IPT = 4;              // copies per thread of a workgroup's list sort (1024 in LDS)
+constexpr int DEPTH_PASSES = 4;         // 8-bit digits of a float's bits
+// Average list length from which the splats are sorted by depth before the
+// emission (no per-tile sort): lists this long are sorted by the per-tile
+// kernel in chunks through global memory, at a fraction of the HBM rate.
+constexpr int64_t PRESORT_MIN_AVG = 1024;
+static_assert(DEPTH_PASSES <= MAX_TILE_PASSES, "the depth totals share the tile totals' layout");
 
 enum : int { CTR_KEYS = 0, CTR_SPLIT = 1, CTR_SLOTS = 16 };
 
@@ -187,12 +193,16 @@ __global__ __launch_bounds__(BS) void count_pass(const uint32_t *__restrict__ ke
 // one stable radix pass over (tile id, splat, depth bits)
 // ---------------------------------------------------------------------------
 struct Pass {
-  const uint32_t *kin, *vin, *bin;       // tile ids, splats, depth bits
-  const uint32_t *count_dev;             // item count in device memory
+  const uint32_t *kin, *vin, *bin;       // keys (tile ids or depth bits), splats, depth bits;
+                                         // vin NULL: the value is the item's index; bin may be NULL
+  const uint32_t *count_dev;             // item count in device memory, or NULL for `count`
+  uint32_t count;
   int shift, nbits;                      // this pass's digit
   const uint32_t *C;                     // [digit][partition] output offsets (scan_rows)
   size_t c_stride;
-  uint32_t *kout, *vout, *bout;
+  uint32_t *kout, *vout, *bout;          // bout may be NULL
+  uint64_t *keys_final;                  // non-NULL: write (key << 32 | bits) and the value here instead
+  uint32_t *vals_final;
 };
 
 // Items of a partition are ranked in index order: wave w owns a contiguous
@@ -203,7 +213,7 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
   __shared__ uint32_t wc[BS / 64][RADIX];
   __shared__ uint32_t goff[RADIX];
   __shared__ uint32_t Ks[SPART], Vs[SPART], Bs[SPART];
-  const uint32_t K = *a.count_dev;
+  const uint32_t K = item_count(a.count_dev, a.count);
   const uint32_t nparts = (uint32_t)(((uint64_t)K + SPART - 1) / SPART);
   if (blockIdx.x >= nparts) return;  // capacity-sized grids
   const uint32_t part = xcd_partition(blockIdx.x, nparts);
@@ -220,8 +230,8 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
     const uint64_t idx = base + (uint64_t)r * 64;
     const bool valid = idx < K;
     key[r] = valid ? a.kin[idx] : 0u;
-    val[r] = valid ? a.vin[idx] : 0u;
-    bits[r] = valid ? a.bin[idx] : 0u;
+    val[r] = valid ? (a.vin ? a.vin[idx] : (uint32_t)idx) : 0u;
+    bits[r] = valid && a.bin ? a.bin[idx] : 0u;
   }
 #pragma unroll
   for (int r = 0; r < SIPT; ++r) {
@@ -285,9 +295,14 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
       const uint32_t k = Ks[i];
       const uint32_t pos = goff[(k >> a.shift) & mask] + i;
       if (pos < K) {  // always, when the counts are consistent
-        a.kout[pos] = k;
-        a.vout[pos] = Vs[i];
-        a.bout[pos] = Bs[i];
+        if (a.keys_final) {
+          a.keys_final[pos] = ((uint64_t)k << 32) | (uint64_t)Bs[i];
+          a.vals_final[pos] = Vs[i];
+        } else {
+          a.kout[pos] = k;
+          a.vout[pos] = Vs[i];
+          if (a.bout) a.bout[pos] = Bs[i];
+        }
       }
     }
   }
@@ -297,12 +312,14 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
 // copies of the splats, in splat-index order
 // ---------------------------------------------------------------------------
 // copies per emission partition (plain stores; no inter-workgroup traffic);
-// also resets the call's state (what clear_state does when n = 0)
+// also resets the call's state (what clear_state does when n = 0) unless z
+// is NULL (it was reset before). The emission order is perm[0..n) when perm
+// is given (splats sorted by depth), else splat-index order.
 __global__ __launch_bounds__(BS) void emit_sums(uint32_t n, const uint32_t *__restrict__ tiles,
-                                                uint64_t *__restrict__ esum, uint4 *__restrict__ z, size_t nz16,
-                                                uint32_t *__restrict__ ranges, size_t nr, int64_t *num_keys,
-                                                int32_t *overflow) {
-  {
+                                                const uint32_t *__restrict__ perm, uint64_t *__restrict__ esum,
+                                                uint4 *__restrict__ z, size_t nz16, uint32_t *__restrict__ ranges,
+                                                size_t nr, int64_t *num_keys, int32_t *overflow) {
+  if (z) {
     const size_t i = (size_t)blockIdx.x * BS + threadIdx.x, stride = (size_t)gridDim.x * BS;
     for (size_t j = i; j < nz16; j += stride) z[j] = make_uint4(0u, 0u, 0u, 0u);
     for (size_t j = i; j < nr; j += stride) ranges[j] = 0u;
@@ -314,8 +331,10 @@ __global__ __launch_bounds__(BS) void emit_sums(uint32_t n, const uint32_t *__re
   const uint64_t s0 = (uint64_t)blockIdx.x * EPART + threadIdx.x;
   uint64_t s = 0;
 #pragma unroll
-  for (int j = 0; j < EIPT; ++j)
-    if (s0 + (uint64_t)j * BS < n) s += tiles[s0 + (uint64_t)j * BS];
+  for (int j = 0; j < EIPT; ++j) {
+    const uint64_t i = s0 + (uint64_t)j * BS;
+    if (i < n) s += tiles[perm ? perm[i] : i];
+  }
   uint64_t total;
   block_exclusive<uint64_t>(s, total);
   if (threadIdx.x == 0) esum[blockIdx.x] = total;
@@ -323,6 +342,7 @@ __global__ __launch_bounds__(BS) void emit_sums(uint32_t n, const uint32_t *__re
 
 struct Emit {
   uint32_t n;
+  const uint32_t *perm;                  // emission order (NULL: splat-index order)
   const uint32_t *tiles;                 // copies per splat (rectangle areas)
   const uint64_t *esum;                  // copies per partition
   const int32_t *rect;
@@ -344,6 +364,7 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
   __shared__ uint32_t loff[EPART + 1];   // local exclusive offsets of the partition's splats
   __shared__ uint32_t sbits[EPART];
   __shared__ int32_t sx[EPART], sy[EPART], sw[EPART];
+  __shared__ uint32_t ssp[EPART];        // splat of each emission position
   __shared__ uint32_t th[MAX_TILE_PASSES * RADIX];
   const uint32_t nparts = (uint32_t)(((uint64_t)a.n + EPART - 1) / EPART);
   const uint32_t part = blockIdx.x;
@@ -355,9 +376,11 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
   const uint64_t s0 = (uint64_t)part * EPART + (uint64_t)threadIdx.x * EIPT;
   uint32_t c[EIPT];
   uint64_t sum = 0;
+  uint32_t sp[EIPT];  // the splats at these emission positions
 #pragma unroll
   for (int j = 0; j < EIPT; ++j) {
-    c[j] = s0 + j < a.n ? a.tiles[s0 + j] : 0u;
+    sp[j] = s0 + j < a.n ? (a.perm ? a.perm[s0 + j] : (uint32_t)(s0 + j)) : 0u;
+    c[j] = s0 + j < a.n ? a.tiles[sp[j]] : 0u;
     sum += c[j];
   }
   uint64_t total;
@@ -375,8 +398,9 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
     loff[ls] = (uint32_t)off;  // only used when the partition fits the capacity (< 2^32)
     off += c[j];
     if (c[j]) {
-      const int4 r = reinterpret_cast<const int4 *>(a.rect)[s0 + j];
-      sbits[ls] = __float_as_uint(a.depth[s0 + j]);
+      const int4 r = reinterpret_cast<const int4 *>(a.rect)[sp[j]];
+      sbits[ls] = __float_as_uint(a.depth[sp[j]]);
+      ssp[ls] = sp[j];
       sx[ls] = r.x;
       sy[ls] = r.y;
       sw[ls] = r.z - r.x + 1;
@@ -402,7 +426,7 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
                           (uint32_t)(sx[lo] + (int32_t)(r - q * (uint32_t)wdt));
     const uint64_t pos = pre + k;
     a.tkey[pos] = tile;
-    a.tval[pos] = (uint32_t)(part * EPART + lo);
+    a.tval[pos] = ssp[lo];
     a.tbits[pos] = sbits[lo];
     for (int p = 0; p < a.tile_passes; ++p) atomicAdd(&th[p * RADIX + ((tile >> (p * a.tile_bits)) & dmask)], 1u);
   }
@@ -414,24 +438,42 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
   }
 }
 
-// ranges from the tile-grouped copies
-__global__ void tile_ranges(const uint32_t *__restrict__ tkey, const uint32_t *__restrict__ ctr, int64_t ntiles,
+// per-byte histograms of the splats' depth bits: the digit totals of the
+// depth passes, in striped copies like the tile digit totals
+__global__ __launch_bounds__(BS) void depth_hist(const float *__restrict__ depth, uint32_t n, uint32_t *__restrict__ tot) {
+  __shared__ uint32_t h[DEPTH_PASSES * RADIX];
+  for (int j = threadIdx.x; j < DEPTH_PASSES * RADIX; j += BS) h[j] = 0u;
+  __syncthreads();
+  for (uint64_t i = (uint64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (uint64_t)gridDim.x * BS) {
+    const uint32_t b = __float_as_uint(depth[i]);
+#pragma unroll
+    for (int p = 0; p < DEPTH_PASSES; ++p) atomicAdd(&h[p * RADIX + ((b >> (8 * p)) & 255u)], 1u);
+  }
+  __syncthreads();
+  const int stripe = blockIdx.x % STRIPES;
+  for (int j = threadIdx.x; j < DEPTH_PASSES * RADIX; j += BS) {
+    const uint32_t v = h[j];
+    if (v) atomicAdd(total_at(tot, stripe, j / RADIX, j % RADIX), v);
+  }
+}
+
+// ranges from the tile-grouped copies: tile ids in 32-bit keys, or in the
+// high half of the final 64-bit keys (WIDE)
+template <bool WIDE>
+__global__ void tile_ranges(const void *__restrict__ tkey, const uint32_t *__restrict__ ctr, int64_t ntiles,
                             uint32_t *__restrict__ ranges) {
   const uint32_t K = ctr[CTR_KEYS];
   const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= K) return;
-  const uint32_t t = tkey[k];
+  auto at = [&](uint64_t i) -> uint32_t {
+    return WIDE ? (uint32_t)(reinterpret_cast<const uint64_t *>(tkey)[i] >> 32) : reinterpret_cast<const uint32_t *>(tkey)[i];
+  };
+  const uint32_t t = at(k);
   if ((int64_t)t >= ntiles) return;
-  if (k == 0 || tkey[k - 1] != t) ranges[2 * (size_t)t] = (uint32_t)k;
-  if (k + 1 == K || tkey[k + 1] != t) ranges[2 * (size_t)t + 1] = (uint32_t)(k + 1);
+  if (k == 0 || at(k - 1) != t) ranges[2 * (size_t)t] = (uint32_t)k;
+  if (k + 1 == K || at(k + 1) != t) ranges[2 * (size_t)t + 1] = (uint32_t)(k + 1);
 }
 
-// Longest-list-first dispatch order of the tiles: tiles bucketed by list
-// length on a log scale (16 buckets per doubling, so lengths within ~4% share
-// a bucket), heaviest bucket first. A workgroup's time grows with its tile's
-// list, so starting the long lists first keeps them off the tail of the blend
-// (and of the segment sort). The order inside a bucket is unspecified. One
-// workgroup.
 // Lists of at most WAVE_MAX copies are sorted by one wave alone. Length
 // buckets are floor(16 log2(len + 1)): 254 copies fall in bucket 127 and
 // 255 in bucket 128, so in the longest-first order every longer list comes
@@ -915,12 +957,16 @@ struct Workspace {
   uint64_t *esum;                        // copies per emission partition
   uint32_t *tk[2], *tv[2], *tb[2];       // tile passes ping-pong [capacity]: tile id, splat, depth bits
   uint32_t *tC;                          // tile passes' counts [pass][1 << bits][key partitions]
+  uint32_t *dk[2], *dv[2];               // depth passes ping-pong [n]: depth bits, splat
+  uint32_t *dC;                          // a depth pass's counts [256][splat partitions]
   // zeroed at the start of every call, contiguous:
   uint32_t *ctr;                         // counters
   uint32_t *ttot;                        // tile digit totals [stripe][pass][256]
+  uint32_t *dtot;                        // depth digit totals [stripe][pass][256]
   void *zero_begin;
   size_t zero_bytes;
   size_t tstride;                        // partitions per row
+  size_t dstride;                        // splat partitions per row of dC
 };
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -944,9 +990,16 @@ size_t carve(void *base, int64_t n, int64_t cap, int64_t ntiles, Workspace *w) {
   }
   t.tstride = (size_t)ceil_div((int64_t)C, SPART);
   t.tC = (uint32_t *)take(4 * ((size_t)tp.passes << tp.bits) * t.tstride);
+  for (int b = 0; b < 2; ++b) {
+    t.dk[b] = (uint32_t *)take(4 * N);
+    t.dv[b] = (uint32_t *)take(4 * N);
+  }
+  t.dstride = (size_t)ceil_div((int64_t)N, SPART);
+  t.dC = (uint32_t *)take(4 * (size_t)RADIX * t.dstride);
   const size_t z0 = o;
   t.ctr = (uint32_t *)take(4 * CTR_SLOTS);
   t.ttot = (uint32_t *)take(4 * (size_t)STRIPES * MAX_TILE_PASSES * RADIX);
+  t.dtot = (uint32_t *)take(4 * (size_t)STRIPES * MAX_TILE_PASSES * RADIX);
   t.zero_begin = p ? (void *)(p + z0) : nullptr;
   t.zero_bytes = o - z0;
   if (w) *w = t;
@@ -969,20 +1022,57 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
   const TilePlan tp = tile_plan(ntiles);
   const size_t tpass = ((size_t)1 << tp.bits) * w.tstride;    // one tile pass's counts
 
+  // Long lists (a capacity of PRESORT_MIN_AVG copies per tile or more): the
+  // splats are sorted by depth first and their copies emitted in that order,
+  // so the stable tile passes leave every tile's list in (depth, splat) order
+  // and no per-tile sort runs. Shorter lists: copies in splat-index order,
+  // then each tile's list sorted by depth. Both give the same keys and values.
+  const bool presort = n > 0 && capacity > 0 && capacity >= PRESORT_MIN_AVG * ntiles;
+
   // 0. zero totals, counters and ranges; num_keys = overflow = 0 (with step 1 when n > 0)
   const size_t nz16 = w.zero_bytes / 16, nr = 2 * (size_t)ntiles;
-  if (n == 0) {
+  if (n == 0 || presort) {
     const size_t m = nz16 > nr ? nz16 : nr;
     const unsigned grid = (unsigned)(m / BS + 1 < 2048 ? m / BS + 1 : 2048);
     hipLaunchKernelGGL(clear_state, dim3(grid), dim3(BS), 0, s, (uint4 *)w.zero_begin, nz16, ranges, nr, num_keys,
                        overflow);
-  } else {
-    // 1. copies in splat-index order with their depth bits, the tile digit totals, K
+  }
+  const uint32_t *perm = nullptr;
+  if (presort) {
+    // 0b. stable LSD sort of the splats by depth bits (four 8-bit passes over n)
+    const unsigned hgrid = (unsigned)(ceil_div(n, BS * 16) < 1024 ? ceil_div(n, BS * 16) : 1024);
+    hipLaunchKernelGGL(depth_hist, dim3(hgrid), dim3(BS), 0, s, depth, (uint32_t)n, w.dtot);
+    const unsigned ngrid = ceil_div(n, SPART);
+    int dc = 0;
+    for (int pass = 0; pass < DEPTH_PASSES; ++pass) {
+      const uint32_t *kin = pass == 0 ? reinterpret_cast<const uint32_t *>(depth) : w.dk[dc];
+      hipLaunchKernelGGL(count_pass, dim3(ngrid), dim3(BS), 0, s, kin, (const uint32_t *)nullptr, (uint32_t)n,
+                         8 * pass, 8, w.dC, w.dstride);
+      hipLaunchKernelGGL(scan_rows, dim3(RADIX), dim3(BS), 0, s, w.dC, w.dstride, (const uint32_t *)nullptr,
+                         (uint32_t)n, (const uint32_t *)w.dtot, pass);
+      Pass a{};
+      a.kin = kin;
+      a.vin = pass == 0 ? nullptr : w.dv[dc];  // splat index on the first pass
+      a.count = (uint32_t)n;
+      a.shift = 8 * pass;
+      a.nbits = 8;
+      a.C = w.dC;
+      a.c_stride = w.dstride;
+      a.kout = w.dk[dc ^ 1];
+      a.vout = w.dv[dc ^ 1];
+      hipLaunchKernelGGL(scatter_pass, dim3(ngrid), dim3(BS), 0, s, a);
+      dc ^= 1;
+    }
+    perm = w.dv[dc];
+  }
+  if (n > 0) {
+    // 1. copies (in splat-index or depth order) with their depth bits, the tile digit totals, K
     const unsigned egrid = ceil_div(n, EPART);
-    hipLaunchKernelGGL(emit_sums, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, tiles, w.esum, (uint4 *)w.zero_begin,
-                       nz16, ranges, nr, num_keys, overflow);
+    hipLaunchKernelGGL(emit_sums, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, tiles, perm, w.esum,
+                       presort ? (uint4 *)nullptr : (uint4 *)w.zero_begin, nz16, ranges, nr, num_keys, overflow);
     Emit e{};
     e.n = (uint32_t)n;
+    e.perm = perm;
     e.tiles = tiles;
     e.esum = w.esum;
     e.rect = rect;
@@ -1026,11 +1116,22 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
       a.kout = w.tk[cur ^ 1];
       a.vout = w.tv[cur ^ 1];
       a.bout = w.tb[cur ^ 1];
+      if (presort && pass == tp.passes - 1) {  // already in (tile, depth, splat) order: the outputs
+        a.keys_final = keys;
+        a.vals_final = vals;
+      }
       hipLaunchKernelGGL(scatter_pass, dim3(kgrid), dim3(BS), 0, s, a);
       cur ^= 1;
     }
-    // 3. per-tile ranges, longest-first order, then each tile's list by depth
-    hipLaunchKernelGGL(tile_ranges, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, (const uint32_t *)w.tk[cur],
+    // 3. per-tile ranges, longest-first order, then (in index order) each tile's list by depth
+    if (presort) {
+      hipLaunchKernelGGL(tile_ranges<true>, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, (const void *)keys,
+                         count_dev, ntiles, ranges);
+      if (tile_order)
+        hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order, (uint32_t *)nullptr);
+      return hipGetLastError();
+    }
+    hipLaunchKernelGGL(tile_ranges<false>, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, (const void *)w.tk[cur],
                        count_dev, ntiles, ranges);
     if (tile_order)
       hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order, w.ctr + CTR_SPLIT);

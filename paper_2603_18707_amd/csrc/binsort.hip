@@ -41,6 +41,7 @@ namespace {
 constexpr int BS = 256;                 // threads per workgroup
 constexpr int SIPT = 4;                 // items per thread in a sort partition
 constexpr int SPART = BS * SIPT;        // items per sort partition
+constexpr int LONG_SIPT = 8;            // the same on the long lists' route
 constexpr int EIPT = 4;                 // splats per thread in an emission partition
 constexpr int EPART = BS * EIPT;        // splats per emission partition
 static_assert(EPART == 1024, "the emission's binary search takes 10 steps");
@@ -126,11 +127,13 @@ __global__ __launch_bounds__(BS) void clear_state(uint4 *__restrict__ z, size_t 
 // one row per digit: C[d][p] <- items of smaller digits + items of digit d in
 // partitions before p
 // ---------------------------------------------------------------------------
+template <int IPT>
 __global__ __launch_bounds__(BS) void scan_rows(uint32_t *__restrict__ C, size_t c_stride,
                                                 const uint32_t *count_dev, uint32_t count,
                                                 const uint32_t *__restrict__ tot, int pass) {
+  constexpr int PART = BS * IPT;
   const uint32_t K = item_count(count_dev, count);
-  const uint32_t P = (uint32_t)(((uint64_t)K + SPART - 1) / SPART);
+  const uint32_t P = (uint32_t)(((uint64_t)K + PART - 1) / PART);
   const int d = blockIdx.x;
   uint32_t mine = 0;
   if ((int)threadIdx.x < d) {
@@ -163,20 +166,22 @@ __global__ __launch_bounds__(BS) void scan_rows(uint32_t *__restrict__ C, size_t
 // ---------------------------------------------------------------------------
 // C[d][p]: items of digit d in partition p
 // ---------------------------------------------------------------------------
+template <int IPT>
 __global__ __launch_bounds__(BS) void count_pass(const uint32_t *__restrict__ keys, const uint32_t *count_dev,
                                                  uint32_t count, int shift, int nbits, uint32_t *__restrict__ C,
                                                  size_t c_stride) {
+  constexpr int PART = BS * IPT;
   __shared__ uint32_t h[BS / 64][RADIX];
   const uint32_t K = item_count(count_dev, count);
-  const uint32_t nparts = (uint32_t)(((uint64_t)K + SPART - 1) / SPART);
+  const uint32_t nparts = (uint32_t)(((uint64_t)K + PART - 1) / PART);
   if (blockIdx.x >= nparts) return;  // capacity-sized grids
   for (int j = threadIdx.x; j < (BS / 64) * RADIX; j += BS) (&h[0][0])[j] = 0u;
   __syncthreads();
   const uint32_t R = 1u << nbits, mask = R - 1u;
   const int w = threadIdx.x >> 6;
-  const uint64_t base = (uint64_t)blockIdx.x * SPART + threadIdx.x;
+  const uint64_t base = (uint64_t)blockIdx.x * PART + threadIdx.x;
 #pragma unroll
-  for (int r = 0; r < SIPT; ++r) {
+  for (int r = 0; r < IPT; ++r) {
     const uint64_t i = base + (uint64_t)r * BS;
     if (i < K) atomicAdd(&h[w][(keys[i] >> shift) & mask], 1u);
   }
@@ -205,16 +210,18 @@ struct Pass {
   uint32_t *vals_final;
 };
 
-// Items of a partition are ranked in index order: wave w owns a contiguous
-// run of 64 * SIPT items, taken 64 at a time; inside a wave the rank among
+// Items of a partition (BS * IPT of them) are ranked in index order: wave w
+// owns a contiguous run of 64 * IPT items, taken 64 at a time; inside a wave the rank among
 // equal digits comes from matching the digit bit by bit with ballots, plus a
 // per-wave running count per digit in LDS.
+template <int IPT>
 __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
+  constexpr int PART = BS * IPT;
   __shared__ uint32_t wc[BS / 64][RADIX];
   __shared__ uint32_t goff[RADIX];
-  __shared__ uint32_t Ks[SPART], Vs[SPART], Bs[SPART];
+  __shared__ uint32_t Ks[PART], Vs[PART], Bs[PART];
   const uint32_t K = item_count(a.count_dev, a.count);
-  const uint32_t nparts = (uint32_t)(((uint64_t)K + SPART - 1) / SPART);
+  const uint32_t nparts = (uint32_t)(((uint64_t)K + PART - 1) / PART);
   if (blockIdx.x >= nparts) return;  // capacity-sized grids
   const uint32_t part = xcd_partition(blockIdx.x, nparts);
   const uint32_t R = 1u << a.nbits, mask = R - 1u;
@@ -223,10 +230,10 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = (1ull << lane) - 1ull;
-  const uint64_t base = (uint64_t)part * SPART + (uint64_t)w * (64 * SIPT) + lane;
-  uint32_t key[SIPT], val[SIPT], bits[SIPT], rk[SIPT];
+  const uint64_t base = (uint64_t)part * PART + (uint64_t)w * (64 * IPT) + lane;
+  uint32_t key[IPT], val[IPT], bits[IPT], rk[IPT];
 #pragma unroll
-  for (int r = 0; r < SIPT; ++r) {
+  for (int r = 0; r < IPT; ++r) {
     const uint64_t idx = base + (uint64_t)r * 64;
     const bool valid = idx < K;
     key[r] = valid ? a.kin[idx] : 0u;
@@ -234,7 +241,7 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
     bits[r] = valid && a.bin ? a.bin[idx] : 0u;
   }
 #pragma unroll
-  for (int r = 0; r < SIPT; ++r) {
+  for (int r = 0; r < IPT; ++r) {
     const bool valid = base + (uint64_t)r * 64 < K;
     const uint32_t d = (key[r] >> a.shift) & mask;
     uint64_t peers = __ballot(valid);
@@ -275,10 +282,10 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < SIPT; ++r) {
+  for (int r = 0; r < IPT; ++r) {
     if (base + (uint64_t)r * 64 < K) {
       const uint32_t local = wc[w][(key[r] >> a.shift) & mask] + rk[r];
-      if (local < SPART) {  // always, when the counts are consistent
+      if (local < PART) {  // always, when the counts are consistent
         Ks[local] = key[r];
         Vs[local] = val[r];
         Bs[local] = bits[r];
@@ -286,10 +293,10 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
     }
   }
   __syncthreads();
-  const uint64_t p0 = (uint64_t)part * SPART;
-  const uint32_t m = K - p0 < (uint64_t)SPART ? (uint32_t)(K - p0) : (uint32_t)SPART;
+  const uint64_t p0 = (uint64_t)part * PART;
+  const uint32_t m = K - p0 < (uint64_t)PART ? (uint32_t)(K - p0) : (uint32_t)PART;
 #pragma unroll
-  for (int r = 0; r < SIPT; ++r) {
+  for (int r = 0; r < IPT; ++r) {
     const uint32_t i = threadIdx.x + (uint32_t)r * BS;
     if (i < m) {
       const uint32_t k = Ks[i];
@@ -1012,6 +1019,20 @@ size_t binsort_workspace_bytes(int64_t n, int64_t capacity, int32_t num_tiles) {
   return carve(nullptr, n, capacity, num_tiles, nullptr);
 }
 
+namespace {
+// count, scan and scatter of one stable digit pass over the keys of `a`
+// (count in device memory), in partitions of BS * IPT items
+template <int IPT>
+void radix_pass(const Pass &a, int64_t capacity, const uint32_t *tot, int pass, hipStream_t s) {
+  const unsigned grid = ceil_div(capacity, BS * IPT);
+  hipLaunchKernelGGL(count_pass<IPT>, dim3(grid), dim3(BS), 0, s, a.kin, a.count_dev, 0u, a.shift, a.nbits,
+                     (uint32_t *)a.C, a.c_stride);
+  hipLaunchKernelGGL(scan_rows<IPT>, dim3(1u << a.nbits), dim3(BS), 0, s, (uint32_t *)a.C, a.c_stride, a.count_dev,
+                     0u, tot, pass);
+  hipLaunchKernelGGL(scatter_pass<IPT>, dim3(grid), dim3(BS), 0, s, a);
+}
+}  // namespace
+
 hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles, int grid_w,
                           int grid_h, int64_t capacity, void *ws, size_t, uint64_t *keys, uint32_t *vals,
                           uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys, int32_t *overflow,
@@ -1046,9 +1067,9 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
     int dc = 0;
     for (int pass = 0; pass < DEPTH_PASSES; ++pass) {
       const uint32_t *kin = pass == 0 ? reinterpret_cast<const uint32_t *>(depth) : w.dk[dc];
-      hipLaunchKernelGGL(count_pass, dim3(ngrid), dim3(BS), 0, s, kin, (const uint32_t *)nullptr, (uint32_t)n,
-                         8 * pass, 8, w.dC, w.dstride);
-      hipLaunchKernelGGL(scan_rows, dim3(RADIX), dim3(BS), 0, s, w.dC, w.dstride, (const uint32_t *)nullptr,
+      hipLaunchKernelGGL(count_pass<SIPT>, dim3(ngrid), dim3(BS), 0, s, kin, (const uint32_t *)nullptr,
+                         (uint32_t)n, 8 * pass, 8, w.dC, w.dstride);
+      hipLaunchKernelGGL(scan_rows<SIPT>, dim3(RADIX), dim3(BS), 0, s, w.dC, w.dstride, (const uint32_t *)nullptr,
                          (uint32_t)n, (const uint32_t *)w.dtot, pass);
       Pass a{};
       a.kin = kin;
@@ -1060,7 +1081,7 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
       a.c_stride = w.dstride;
       a.kout = w.dk[dc ^ 1];
       a.vout = w.dv[dc ^ 1];
-      hipLaunchKernelGGL(scatter_pass, dim3(ngrid), dim3(BS), 0, s, a);
+      hipLaunchKernelGGL(scatter_pass<SIPT>, dim3(ngrid), dim3(BS), 0, s, a);
       dc ^= 1;
     }
     perm = w.dv[dc];
@@ -1094,16 +1115,11 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
   if (err != hipSuccess) return err;
 
   if (capacity > 0 && n > 0) {
-    // 2. stable passes over the tile digits
-    const unsigned kgrid = ceil_div(capacity, SPART);
+    // 2. stable passes over the tile digits (larger partitions for the long
+    // lists' route, so each digit leaves a partition in longer runs)
     const uint32_t *count_dev = w.ctr + CTR_KEYS;
     int cur = 0;
     for (int pass = 0; pass < tp.passes; ++pass) {
-      uint32_t *Cp = w.tC + pass * tpass;
-      hipLaunchKernelGGL(count_pass, dim3(kgrid), dim3(BS), 0, s, (const uint32_t *)w.tk[cur], count_dev, 0u,
-                         tp.bits * pass, tp.bits, Cp, w.tstride);
-      hipLaunchKernelGGL(scan_rows, dim3(1u << tp.bits), dim3(BS), 0, s, Cp, w.tstride, count_dev, 0u,
-                         (const uint32_t *)w.ttot, pass);
       Pass a{};
       a.kin = w.tk[cur];
       a.vin = w.tv[cur];
@@ -1111,7 +1127,7 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
       a.count_dev = count_dev;
       a.shift = tp.bits * pass;
       a.nbits = tp.bits;
-      a.C = Cp;
+      a.C = w.tC + pass * tpass;
       a.c_stride = w.tstride;
       a.kout = w.tk[cur ^ 1];
       a.vout = w.tv[cur ^ 1];
@@ -1120,7 +1136,10 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
         a.keys_final = keys;
         a.vals_final = vals;
       }
-      hipLaunchKernelGGL(scatter_pass, dim3(kgrid), dim3(BS), 0, s, a);
+      if (presort)
+        radix_pass<LONG_SIPT>(a, capacity, w.ttot, pass, s);
+      else
+        radix_pass<SIPT>(a, capacity, w.ttot, pass, s);
       cur ^= 1;
     }
     // 3. per-tile ranges, longest-first order, then (in index order) each tile's list by depth

@@ -30,7 +30,7 @@ RECT_SQUARE, RECT_ELLIPSE_BOX = 0, 1
 RADIUS_SIGMA3, RADIUS_POLY_UNIVERSAL, RADIUS_POLY_OPACITY, RADIUS_EXP_OPACITY = 0, 1, 2, 3
 
 SPLAT_EDGE_NEAR, SPLAT_CULL_NEAR = 1, 2
-PIX_ALPHA_NEAR, PIX_T_NEAR, PIX_EDGE_NEAR = 1, 2, 4
+PIX_ALPHA_NEAR, PIX_T_NEAR, PIX_EDGE_NEAR, PIX_CULL_NEAR = 1, 2, 4, 8
 
 
 class _Cfg(ctypes.Structure):
@@ -38,7 +38,8 @@ class _Cfg(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("c", ctypes.c_double * 4), ("eps", ctypes.c_double),
                 ("alpha_max", ctypes.c_double), ("t_min", ctypes.c_double), ("aa_v", ctypes.c_double),
                 ("near_z", ctypes.c_double), ("radius_pad", ctypes.c_double), ("bg", ctypes.c_double * 3),
-                ("alpha_band", ctypes.c_double), ("t_band_rel", ctypes.c_double), ("rect_mode", ctypes.c_int32)]
+                ("alpha_band", ctypes.c_double), ("t_band_rel", ctypes.c_double), ("rect_mode", ctypes.c_int32),
+                ("tile_cull", ctypes.c_int32)]
 
 
 class _Cam(ctypes.Structure):
@@ -74,6 +75,9 @@ class Cfg:
     # tile rectangle: 0 = bounding square of radius r (Sec. 2.1), 1 = the
     # ellipse Q = k^2's axis-aligned bounding box
     rect_mode: int = 0
+    # 1: a splat is in a tile's list only when the tile passes the per-tile
+    # test of the renderer's culled binning (orc_tile_keep)
+    tile_cull: int = 0
 
     def float_params(self) -> "Cfg":
         """A copy whose scalar parameters (eps, alpha_max, t_min, aa_v, near_z,
@@ -96,6 +100,7 @@ class Cfg:
         for i in range(3):
             c.bg[i] = float(self.bg[i])
         c.alpha_band, c.t_band_rel, c.rect_mode = self.alpha_band, self.t_band_rel, self.rect_mode
+        c.tile_cull = int(self.tile_cull)
         return c
 
 
@@ -141,6 +146,20 @@ def lib():
         L.orc_render_pixels.restype = None
         L.orc_render_pixels.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_int64] + [P] * 7
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_cull_cut.restype = ctypes.c_double
+        L.orc_cull_cut.argtypes = [P] + [ctypes.c_double] * 4
+        L.orc_rect_min_q.restype = ctypes.c_double
+        L.orc_rect_min_q.argtypes = [ctypes.c_double] * 7
+        L.orc_tile_keep.restype = ctypes.c_int
+        L.orc_tile_keep.argtypes = [ctypes.c_double] * 6 + [ctypes.c_int] * 3 + [P]
+        L.orc_cull_cuts.restype = None
+        L.orc_cull_cuts.argtypes = [P, ctypes.c_int64, P, P, P]
+        L.orc_cull_histogram.restype = None
+        L.orc_cull_histogram.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_int, ctypes.c_int, P, P]
+        L.orc_cull_tile_members.restype = None
+        L.orc_cull_copy_mask.restype = ctypes.c_int64
+        L.orc_cull_copy_mask.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P]
+        L.orc_cull_tile_members.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_int, ctypes.c_int, P, P]
         _lib = L
     return _lib
 
@@ -262,6 +281,66 @@ def render_pixels(proj: dict, cfg: Cfg, pixels: np.ndarray, order: np.ndarray = 
                         m, _p(px), _p(out["color"]), _p(out["T"]), _p(out["n_contrib"]), _p(out["n_eval"]),
                         _p(out["last_contrib"]), _p(out["flags"]))
     return out
+
+
+def rect_min_q(a, b, c, x0, x1, y0, y1) -> float:
+    """Least a dx^2 + 2 b dx dy + c dy^2 over [x0, x1] x [y0, y1] (orc_rect_min_q)."""
+    return float(lib().orc_rect_min_q(a, b, c, x0, x1, y0, y1))
+
+
+def cull_cut(cfg: Cfg, o, a, b, c) -> float:
+    """The per-tile test's bound on Q for one record (orc_cull_cut)."""
+    return float(lib().orc_cull_cut(ctypes.byref(cfg._c()), o, a, b, c))
+
+
+def tile_keep(cfg: Cfg, u, v, a, b, c, cut, tx, ty):
+    """(keep, near) of the per-tile test for one splat and tile (orc_tile_keep)."""
+    near = ctypes.c_int(0)
+    k = lib().orc_tile_keep(u, v, a, b, c, cut, int(tx), int(ty), int(cfg.tile), ctypes.byref(near))
+    return bool(k), bool(near.value)
+
+
+def _cull_inputs(proj: dict, cfg: Cfg):
+    c = lambda a, dt: np.ascontiguousarray(a, dtype=dt)
+    m2, co, op = c(proj["means2d"], np.float64), c(proj["conic"], np.float64), c(proj["opac"], np.float64)
+    n = int(op.shape[0])
+    cut = np.zeros(n, np.float64)
+    lib().orc_cull_cuts(ctypes.byref(cfg._c()), n, _p(co), _p(op), _p(cut))
+    return n, m2, co, cut, c(proj["rect"], np.int32)
+
+
+def cull_histogram(proj: dict, cfg: Cfg, grid_w: int, grid_h: int):
+    """Kept copies per tile and near decisions per tile (int64 [grid_h * grid_w]
+    each) with per-tile culling, over the records of ``proj``."""
+    n, m2, co, cut, rect = _cull_inputs(proj, cfg)
+    hist, near = np.zeros(grid_w * grid_h, np.int64), np.zeros(grid_w * grid_h, np.int64)
+    lib().orc_cull_histogram(ctypes.byref(cfg._c()), n, _p(m2), _p(co), _p(cut), _p(rect), int(grid_w), int(grid_h),
+                             _p(hist), _p(near))
+    return hist, near
+
+
+def cull_copy_mask(proj: dict, cfg: Cfg):
+    """The test for every rectangle copy, in the order binning.bin_and_sort_fast
+    lists copies before sorting (bool [sum of areas]), and the number of near
+    decisions."""
+    n, m2, co, cut, rect = _cull_inputs(proj, cfg)
+    r = rect.astype(np.int64)
+    cnt = np.maximum(r[:, 2] - r[:, 0] + 1, 0) * np.maximum(r[:, 3] - r[:, 1] + 1, 0)
+    start = np.ascontiguousarray(np.cumsum(cnt) - cnt, np.int64)
+    keep = np.zeros(int(cnt.sum()), np.uint8)
+    nnear = lib().orc_cull_copy_mask(ctypes.byref(cfg._c()), n, _p(m2), _p(co), _p(cut), _p(rect), _p(start),
+                                     _p(keep))
+    return keep.astype(bool), int(nnear)
+
+
+def cull_tile_members(proj: dict, cfg: Cfg, tx: int, ty: int):
+    """Per splat: in tile (tx, ty)'s culled list (bool [n]), and whether that
+    decision is near (bool [n])."""
+    n, m2, co, cut, rect = _cull_inputs(proj, cfg)
+    keep, near = np.zeros(n, np.uint8), np.zeros(n, np.uint8)
+    lib().orc_cull_tile_members(ctypes.byref(cfg._c()), n, _p(m2), _p(co), _p(cut), _p(rect), int(tx), int(ty),
+                                _p(keep), _p(near))
+    return keep.astype(bool), near.astype(bool)
 
 
 def render_image(scene, cam, cfg: Cfg, round_to=np.float32) -> dict:

@@ -24,8 +24,9 @@
  *
  * Every pixel is tested against every splat in depth order; no tile list is
  * built. The tile rectangle enters only as the membership predicate "the
- * pixel's tile lies in the splat's rectangle", since that rectangle is what
- * decides which splats a tile-based rasterizer ever evaluates for a pixel.
+ * pixel's tile lies in the splat's rectangle" (with tile culling on, "and
+ * the tile passes the tile test"), since that is what decides which splats
+ * a tile-based rasterizer ever evaluates for a pixel.
  *
  * Roots are found by a plain scan plus bisection, never by the closed forms,
  * so the closed forms of Eq. 3-5 and App. B can be checked against it.
@@ -47,7 +48,7 @@ enum {
 /* per-splat flag bits */
 enum { ORC_SPLAT_EDGE_NEAR = 1, ORC_SPLAT_CULL_NEAR = 2 };
 /* per-pixel flag bits */
-enum { ORC_PIX_ALPHA_NEAR = 1, ORC_PIX_T_NEAR = 2, ORC_PIX_EDGE_NEAR = 4 };
+enum { ORC_PIX_ALPHA_NEAR = 1, ORC_PIX_T_NEAR = 2, ORC_PIX_EDGE_NEAR = 4, ORC_PIX_CULL_NEAR = 8 };
 
 typedef struct {
   int32_t kind;        /* ORC_KERNEL_* */
@@ -65,6 +66,7 @@ typedef struct {
   double alpha_band;   /* |alpha - eps| below this flags a pixel */
   double t_band_rel;   /* |T' - t_min| below t_min * this flags a pixel */
   int32_t rect_mode;   /* ORC_RECT_*: bounding square of radius r, or the ellipse's own box */
+  int32_t tile_cull;   /* 1: a splat is in a tile's list only if the tile passes the tile test */
 } orc_cfg;
 
 typedef struct {
@@ -529,6 +531,170 @@ void orc_depth_order(int64_t n, const float *depth32, int64_t *order_out) {
  * one), 1 + list position of the last blended splat (0 if none), and flags
  * for decisions that sit too close to a threshold to be reproduced by a
  * single-precision evaluation. splat_flags may be NULL. */
+/* ------------------------------------------------------------------ */
+/* per-tile culling (the tile test of StopThePop, Sec. 2.1 and Sec. 4)   */
+/* ------------------------------------------------------------------ */
+/*
+ * A splat enters a tile's list only when the point of the tile where it
+ * contributes most can pass alpha >= eps. The kernels decrease in Q, so that
+ * point minimises Q over the rectangle holding the tile's pixel centres, and
+ * the test is: that minimum <= cut. cut is not the exact threshold but a
+ * bound that makes the test safe for a float renderer: the threshold of
+ * alpha >= eps on Q for the kernel with float coefficients, in double, plus
+ * (1) 2^-16 (|thr| + 16), giving T, and (2) the widening
+ * cut = (sqrt(T) (1 + 2^-18) + D)^2 (1 + 2^-30) with
+ * D = 2^-19 (4 sqrt(T) + 16 sqrt(det/c) + 8 |b| sqrt(T/det) + 16 |b|/sqrt(c)
+ * + 32 sqrt(c)), det = a c - b^2 of the conic (a, b, c). These terms bound
+ * the rounding of a float evaluation of the quadric at tile-local pixel
+ * offsets with a wide margin; the oracle takes them as part of the
+ * definition (a renderer that culls with the same formula keeps the same
+ * copies). Below, every operation is a plain IEEE double operation in the
+ * order written (the library is built without contraction), so a renderer
+ * computing the same formula in double takes the same decision unless Q's
+ * minimum lies within a few ulps of cut; such decisions are reported near.
+ */
+
+/* threshold on Q of o k(Q) >= eps for the kernel with float coefficients
+ * (the renderer's), negative when no Q passes */
+static double cull_threshold(const orc_cfg *cfg, double o) {
+  const double eps = (double)(float)cfg->eps;
+  if (cfg->kind == ORC_KERNEL_EXP) return 2.0 * log(o / eps); /* o exp(-Q/2) = eps */
+  double cf[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i <= cfg->order; ++i) cf[i] = (double)(float)cfg->c[i];
+  if (cfg->order == 1) return (eps / o - cf[0]) / cf[1]; /* o (c_0 + c_1 Q) = eps */
+  return orc_first_root(cf, cfg->order, eps / o);        /* -1 when o c_0 < eps */
+}
+
+/* the cut above for a record (opacity o, conic a, b, c); -1 when no pixel
+ * can pass (o <= 0, conic not positive definite, T < 0) */
+double orc_cull_cut(const orc_cfg *cfg, double o, double a, double b, double c) {
+  if (!(o > 0.0) || !(a > 0.0) || !(c > 0.0)) return -1.0;
+  const double det = a * c - b * b;
+  if (!(det > 0.0)) return -1.0;
+  const double thr = cull_threshold(cfg, o);
+  const double T = thr + 0x1p-16 * (fabs(thr) + 16.0);
+  if (!(T >= 0.0)) return -1.0;
+  const double sT = sqrt(T), ab = fabs(b);
+  const double D = 0x1p-19 * (4.0 * sT + 16.0 * sqrt(det / c) + 8.0 * ab * sqrt(T / det) + 16.0 * ab / sqrt(c) +
+                              32.0 * sqrt(c));
+  const double r = sT * (1.0 + 0x1p-18) + D;
+  return r * r * (1.0 + 0x1p-30);
+}
+
+/* least Q = a dx^2 + 2 b dx dy + c dy^2 over the rectangle [x0, x1] x [y0, y1]
+ * of offsets from the mean, for a positive-definite conic: 0 when the mean is
+ * inside; otherwise the minimum lies on an edge. Along an edge of fixed dy
+ * completing the square gives Q = a (dx + b dy / a)^2 + (det / a) dy^2, least
+ * at dx = -b dy / a clamped to the edge; likewise along an edge of fixed dx
+ * with the roles of a and c exchanged. */
+double orc_rect_min_q(double a, double b, double c, double x0, double x1, double y0, double y1) {
+  if (x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0) return 0.0;
+  const double det = a * c - b * b;
+  double best = INFINITY;
+  const double ys[2] = {y0, y1}, xs[2] = {x0, x1};
+  for (int e = 0; e < 2; ++e) {
+    double y = ys[e], xv = -(b * y) / a;
+    double dx = fmin(fmax(xv, x0), x1) - xv;
+    double q = a * (dx * dx) + (det / a) * (y * y);
+    if (q < best) best = q;
+    double x = xs[e], yv = -(b * x) / c;
+    double dy = fmin(fmax(yv, y0), y1) - yv;
+    q = c * (dy * dy) + (det / c) * (x * x);
+    if (q < best) best = q;
+  }
+  return best;
+}
+
+/* the tile test for splat (mean u, v; conic a, b, c; cut) and tile (tx, ty):
+ * 1 keep, 0 drop; *near = 1 when the minimum is within 2^-40 of cut
+ * (relative), where a double evaluation in another order may decide the
+ * other way */
+int orc_tile_keep(double u, double v, double a, double b, double c, double cut, int tx, int ty, int T, int *near) {
+  *near = 0;
+  if (!(cut >= 0.0)) return 0;
+  const double x0 = ((double)(tx * T) + 0.5) - u, x1 = ((double)(tx * T + T) - 0.5) - u;
+  const double y0 = ((double)(ty * T) + 0.5) - v, y1 = ((double)(ty * T + T) - 0.5) - v;
+  const double q = orc_rect_min_q(a, b, c, x0, x1, y0, y1);
+  if (fabs(q - cut) <= 0x1p-40 * cut) *near = 1;
+  return q <= cut;
+}
+
+/* cut for every splat of a projection (records as doubles) */
+void orc_cull_cuts(const orc_cfg *cfg, int64_t n, const double *conic, const double *opac, double *cut) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    cut[i] = orc_cull_cut(cfg, opac[i], conic[3 * i], conic[3 * i + 1], conic[3 * i + 2]);
+}
+
+/* kept copies per tile (hist [gw * gh]) and near decisions per tile
+ * (near [gw * gh]) over every tile of every splat's rectangle */
+void orc_cull_histogram(const orc_cfg *cfg, int64_t n, const double *means2d, const double *conic,
+                        const double *cut, const int32_t *rect, int gw, int gh, int64_t *hist, int64_t *near) {
+  const int64_t nt = (int64_t)gw * gh;
+  memset(hist, 0, sizeof(int64_t) * nt);
+  memset(near, 0, sizeof(int64_t) * nt);
+#pragma omp parallel
+  {
+    int64_t *h = calloc((size_t)(2 * nt), sizeof(int64_t));
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t *r = rect + 4 * i;
+      for (int ty = r[1]; ty <= r[3]; ++ty)
+        for (int tx = r[0]; tx <= r[2]; ++tx) {
+          int nr;
+          int k = orc_tile_keep(means2d[2 * i], means2d[2 * i + 1], conic[3 * i], conic[3 * i + 1],
+                                conic[3 * i + 2], cut[i], tx, ty, cfg->tile, &nr);
+          h[(int64_t)ty * gw + tx] += k;
+          h[nt + (int64_t)ty * gw + tx] += nr;
+        }
+    }
+#pragma omp critical
+    for (int64_t t = 0; t < nt; ++t) {
+      hist[t] += h[t];
+      near[t] += h[nt + t];
+    }
+    free(h);
+  }
+}
+
+/* the test for every copy of every rectangle, in the order the copies are
+ * listed before sorting (splats in index order, each rectangle's tiles
+ * row-major): keep [sum of rectangle areas], starting at start[i] for splat i;
+ * returns the number of near decisions */
+int64_t orc_cull_copy_mask(const orc_cfg *cfg, int64_t n, const double *means2d, const double *conic,
+                           const double *cut, const int32_t *rect, const int64_t *start, uint8_t *keep) {
+  int64_t nnear = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : nnear)
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t *r = rect + 4 * i;
+    int64_t k = start[i];
+    for (int ty = r[1]; ty <= r[3]; ++ty)
+      for (int tx = r[0]; tx <= r[2]; ++tx) {
+        int nr;
+        keep[k++] = (uint8_t)orc_tile_keep(means2d[2 * i], means2d[2 * i + 1], conic[3 * i], conic[3 * i + 1],
+                                           conic[3 * i + 2], cut[i], tx, ty, cfg->tile, &nr);
+        nnear += nr;
+      }
+  }
+  return nnear;
+}
+
+/* per splat: whether tile (tx, ty) is in its rectangle and passes the test
+ * (keep [n]) and whether that decision is near (near [n]) */
+void orc_cull_tile_members(const orc_cfg *cfg, int64_t n, const double *means2d, const double *conic,
+                           const double *cut, const int32_t *rect, int tx, int ty, uint8_t *keep, uint8_t *near) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t *r = rect + 4 * i;
+    keep[i] = near[i] = 0;
+    if (tx < r[0] || tx > r[2] || ty < r[1] || ty > r[3]) continue;
+    int nr;
+    keep[i] = (uint8_t)orc_tile_keep(means2d[2 * i], means2d[2 * i + 1], conic[3 * i], conic[3 * i + 1],
+                                     conic[3 * i + 2], cut[i], tx, ty, cfg->tile, &nr);
+    near[i] = (uint8_t)nr;
+  }
+}
+
 void orc_render_pixels(const orc_cfg *cfg, int64_t n, const int64_t *order,
                        const double *means2d, const double *conic, const double *opac,
                        const double *rgb, const int32_t *rect, const uint8_t *splat_flags,
@@ -537,6 +703,11 @@ void orc_render_pixels(const orc_cfg *cfg, int64_t n, const int64_t *order,
                        uint8_t *pix_flags) {
   const int T = cfg->tile;
   const double x0 = (cfg->kind == ORC_KERNEL_POLY) ? orc_first_root(cfg->c, cfg->order, 0.0) : 0.0;
+  double *cut = NULL;
+  if (cfg->tile_cull) {
+    cut = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    orc_cull_cuts(cfg, n, conic, opac, cut);
+  }
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t j = 0; j < npix; ++j) {
     int x = px[2 * j], y = px[2 * j + 1];
@@ -555,6 +726,13 @@ void orc_render_pixels(const orc_cfg *cfg, int64_t n, const int64_t *order,
           fl |= ORC_PIX_EDGE_NEAR;
       }
       if (!(tx >= rc[0] && tx <= rc[2] && ty >= rc[1] && ty <= rc[3])) continue;
+      if (cut) { /* tile culling: the list holds the splat only if the tile passes */
+        int nr;
+        int keep = orc_tile_keep(means2d[2 * i], means2d[2 * i + 1], conic[3 * i], conic[3 * i + 1],
+                                 conic[3 * i + 2], cut[i], tx, ty, T, &nr);
+        if (nr) fl |= ORC_PIX_CULL_NEAR;
+        if (!keep) continue;
+      }
       ++nev;
       double dx = cx - means2d[2 * i], dy = cy - means2d[2 * i + 1];
       double A = conic[3 * i], B = conic[3 * i + 1], Cc = conic[3 * i + 2];
@@ -578,6 +756,7 @@ void orc_render_pixels(const orc_cfg *cfg, int64_t n, const int64_t *order,
     last_contrib[j] = last;
     pix_flags[j] = fl;
   }
+  free(cut);
 }
 
 /* number of threads OpenMP will use */

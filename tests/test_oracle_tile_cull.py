@@ -1,0 +1,216 @@
+"""Pins of the reference's per-tile culling (the StopThePop tile test the
+paper adds to every renderer it evaluates, Sec. 2.1 and Sec. 4).
+
+A splat stays in a tile's list when the least Q over the tile's pixel-centre
+rectangle is at most cut, a bound just above the threshold of alpha >= eps.
+Pinned here, independently of the formulas in the oracle:
+  - the rectangle minimum against brute force on a fine grid, for round and
+    extremely thin conics, means inside, beside and far from the rectangle;
+  - the threshold: the kernel at cut's base threshold equals eps / o, and cut
+    lies above it by a small margin only;
+  - safety for a float renderer: a float32 evaluation of the completed-square
+    quadric at tile-local pixel offsets (the form a tile renderer uses) never
+    includes a pixel whose tile the test drops, for thin footprints too;
+  - on scenes: no dropped (splat, tile) pair has a pixel with alpha >= eps in
+    FP64, images are unchanged, lists shrink, and the histogram agrees with
+    the per-tile membership.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import binning, core
+from paper_2603_18707_amd import scenes
+from tests import helpers as H
+
+T = 16
+
+
+def _random_conic(rng, thin):
+    """A positive-definite conic (a, b, c) as float values: the inverse of a
+    rotated covariance with axis scales s1, s2 (thin: ratios up to 1e4)."""
+    s1 = math.exp(rng.uniform(-1.0, 4.0))
+    s2 = s1 * (math.exp(-rng.uniform(4.0, 9.0)) if thin else math.exp(rng.uniform(-1.0, 1.0)))
+    th = rng.uniform(0.0, math.pi)
+    R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    cov = R @ np.diag([s1 * s1, s2 * s2]) @ R.T
+    inv = np.linalg.inv(cov)
+    a, b, c = (float(np.float32(x)) for x in (inv[0, 0], inv[0, 1], inv[1, 1]))
+    if not (a > 0 and c > 0 and a * c - b * b > 0):
+        return _random_conic(rng, thin)
+    return a, b, c
+
+
+@pytest.mark.parametrize("thin", [False, True])
+def test_rect_min_matches_a_fine_grid(thin):
+    rng = np.random.default_rng(5 + thin)
+    g = np.linspace(0.0, 1.0, 801)
+    for _ in range(60):
+        a, b, c = _random_conic(rng, thin)
+        x0, y0 = rng.uniform(-60, 60, size=2)
+        x1, y1 = x0 + rng.uniform(0, 15), y0 + rng.uniform(0, 15)
+        q = core.rect_min_q(a, b, c, x0, x1, y0, y1)
+        X, Y = np.meshgrid(x0 + (x1 - x0) * g, y0 + (y1 - y0) * g)
+        Qg = a * X * X + 2 * b * X * Y + c * Y * Y
+        gm = float(Qg.min())
+        assert q >= 0.0
+        # no grid point lies below the minimum (up to the grid's own rounding)
+        assert gm >= q - 1e-9 * (1.0 + abs(Qg).max())
+        # and the grid gets close to it: Q moves by at most |grad| * half a cell
+        step = max(x1 - x0, y1 - y0) / 800.0
+        grad = 2.0 * (abs(a) + abs(b) + abs(c)) * (abs(X).max() + abs(Y).max())
+        assert gm - q <= grad * step + 1e-9 * (1.0 + abs(Qg).max())
+    # a rectangle around the mean has minimum 0; a point rectangle is Q itself
+    assert core.rect_min_q(1.0, 0.3, 2.0, -1.0, 1.0, -2.0, 0.5) == 0.0
+    assert core.rect_min_q(1.0, 0.3, 2.0, 2.0, 2.0, -1.0, -1.0) == pytest.approx(4.0 - 1.2 + 2.0, rel=1e-15)
+
+
+@pytest.mark.parametrize("kind,order", [("poly", 1), ("poly", 2), ("poly", 3), ("exp", 1)])
+def test_cut_sits_just_above_the_threshold(kind, order):
+    cfg = H.oracle_cfg(kind, order, "opacity" if kind == "poly" else "sigma3")
+    cf = [float(np.float32(x)) for x in cfg.coeffs]
+    for o in (0.02, 0.1, 0.5, 0.99):
+        cut = core.cull_cut(cfg, o, 1.0, 0.0, 1.0)
+        # the kernel with the renderer's float coefficients reaches eps / o at the threshold
+        if kind == "exp":
+            thr = 2.0 * math.log(o / cfg.eps)
+            assert o * math.exp(-0.5 * thr) == pytest.approx(cfg.eps, rel=1e-12)
+        else:
+            thr = core.first_root(cf, order, cfg.eps / o)
+            assert o * core.poly(cf, order, thr) == pytest.approx(cfg.eps, abs=1e-12)
+        assert thr < cut < thr * (1 + 2e-4) + 2e-3, (o, thr, cut)
+    # below the cut-off opacity, or a conic that is not positive definite: no tile
+    assert core.cull_cut(cfg, cfg.eps * 0.5, 1.0, 0.0, 1.0) < 0.0
+    assert core.cull_cut(cfg, 0.5, 1.0, 1.0, 1.0) < 0.0
+    assert core.cull_cut(cfg, 0.5, -1.0, 0.0, 1.0) < 0.0
+
+
+def _float_t(xe, u, v, a, b, c, tx, ty):
+    """t = x_e - Q at the 256 pixel centres of tile (tx, ty), in float32, as a
+    tile renderer computes it: offsets from the tile corner, the quadric
+    completed in dy (g = (ac - b^2)/c, h = b/c), every step rounded to float."""
+    f = np.float32
+    ox, oy = f(tx * T), f(ty * T)
+    mx, my = f(f(u) - ox), f(f(v) - oy)
+    det = a * c - b * b  # exact in double for float inputs
+    g, h = f(det / c), f(f(b) / f(c))
+    px = (np.arange(T, dtype=np.float32) + f(0.5))[None, :]
+    py = (np.arange(T, dtype=np.float32) + f(0.5))[:, None]
+    dx = (px - mx).astype(np.float32)
+    R0 = (f(xe) - (g * dx).astype(np.float32) * dx).astype(np.float32)
+    e = (py + (h * dx - my).astype(np.float32)).astype(np.float32)
+    return (R0 - (f(c) * e).astype(np.float32) * e).astype(np.float32)
+
+
+@pytest.mark.parametrize("thin", [False, True])
+def test_float_inclusion_never_lands_in_a_dropped_tile(thin):
+    # splats placed so that their threshold ellipse's edge crosses tiles near
+    # the dropped ones; any float-included pixel must lie in a kept tile
+    cfg = H.oracle_cfg("poly", 1, "opacity")
+    rng = np.random.default_rng(11 + thin)
+    included, dropped_near = 0, 0
+    for _ in range(300):
+        a, b, c = _random_conic(rng, thin)
+        o = float(np.float32(rng.uniform(0.02, 1.0)))
+        cut = core.cull_cut(cfg, o, a, b, c)
+        thr_f = float(np.float32((np.float32(cfg.eps) / np.float32(o) - np.float32(cfg.coeffs[0])) /
+                                 np.float32(cfg.coeffs[1])))
+        u = float(np.float32(rng.uniform(100, 900)))
+        v = float(np.float32(rng.uniform(100, 900)))
+        ex = math.sqrt(max(cut, 0) * c / (a * c - b * b))
+        ey = math.sqrt(max(cut, 0) * a / (a * c - b * b))
+        for tx in range(int((u - ex) // T) - 1, int((u + ex) // T) + 2):
+            for ty in range(int((v - ey) // T) - 1, int((v + ey) // T) + 2):
+                keep, _ = core.tile_keep(cfg, u, v, a, b, c, cut, tx, ty)
+                t = _float_t(thr_f, u, v, a, b, c, tx, ty)
+                if keep:
+                    included += int((t >= 0).sum())
+                else:
+                    assert not (t >= 0).any(), (a, b, c, o, u, v, tx, ty)
+                    dropped_near += 1
+            if ex > 200:  # keep the walk short for huge splats
+                break
+    assert included > 1000 and dropped_near > 100
+
+
+def _scene_pairs(kind, order, radius, rect_mode, n=3000, W=256, H_=192):
+    scene, _ = scenes.workload_heavy(n=n)
+    cam = scenes.orbit_camera(W, H_, 0.7)
+    cfg = H.oracle_cfg(kind, order, radius, rect_mode=rect_mode)
+    rec = core.round_records(core.project(scene, cam, cfg))
+    return cfg, rec, cam
+
+
+@pytest.mark.parametrize("kind,order,radius,rect_mode", [("poly", 1, "opacity", 1), ("exp", 1, "sigma3", 0),
+                                                         ("poly", 2, "universal", 1), ("poly", 3, "opacity", 0)])
+def test_dropped_tiles_hold_no_visible_pixel_and_images_match(kind, order, radius, rect_mode):
+    cfg, rec, cam = _scene_pairs(kind, order, radius, rect_mode)
+    W, Hh = cam.width, cam.height
+    gw, gh = (W + T - 1) // T, (Hh + T - 1) // T
+    culled = core.Cfg(**{**cfg.__dict__, "tile_cull": 1})
+    hist, near = core.cull_histogram(rec, culled, gw, gh)
+    box = binning.tile_histogram(rec["rect"], gw, gh)
+    assert near.sum() == 0
+    assert np.all(hist <= box) and hist.sum() < box.sum()
+    # brute force: every dropped pair, every pixel of the tile: alpha < eps in FP64
+    x0 = core.first_root(cfg.coeffs, order, 0.0) if kind == "poly" else 0.0
+    dropped = 0
+    for t in range(gw * gh):
+        tx, ty = t % gw, t // gw
+        keep, nr = core.cull_tile_members(rec, culled, tx, ty)
+        r = rec["rect"]
+        cover = (r[:, 0] <= tx) & (tx <= r[:, 2]) & (r[:, 1] <= ty) & (ty <= r[:, 3])
+        assert keep.sum() == hist[t] and not nr.any()
+        assert np.all(cover[keep])
+        idx = np.nonzero(cover & ~keep)[0]
+        dropped += idx.size
+        if idx.size == 0:
+            continue
+        px, py = np.meshgrid(np.arange(T) + tx * T + 0.5, np.arange(T) + ty * T + 0.5)
+        dx = px.ravel()[None, :] - rec["means2d"][idx, 0:1]
+        dy = py.ravel()[None, :] - rec["means2d"][idx, 1:2]
+        a, b, c = (rec["conic"][idx, k:k + 1] for k in range(3))
+        Q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+        alpha = rec["opac"][idx, None] * core.kernel_value(cfg, Q.ravel()).reshape(Q.shape)
+        assert np.all(alpha < cfg.eps), f"tile {t}"
+    assert dropped > 0.1 * box.sum()
+    # images, transmittance and blended counts unchanged; lists only shrink
+    pix = core.all_pixels(W, Hh)
+    a0 = core.render_pixels(rec, cfg, pix)
+    a1 = core.render_pixels(rec, culled, pix)
+    assert np.array_equal(a0["color"], a1["color"]) and np.array_equal(a0["T"], a1["T"])
+    assert np.array_equal(a0["n_contrib"], a1["n_contrib"])
+    assert np.all(a1["n_eval"] <= a0["n_eval"]) and a1["n_eval"].sum() < a0["n_eval"].sum()
+    assert not (a1["flags"] & core.PIX_CULL_NEAR).any()
+
+
+def test_tile_list_with_membership():
+    cfg, rec, cam = _scene_pairs("poly", 1, "opacity", 1, n=2000, W=128, H_=128)
+    culled = core.Cfg(**{**cfg.__dict__, "tile_cull": 1})
+    gw = gh = 8
+    keys, vals, ranges = binning.bin_and_sort(rec["rect"], rec["depth32"], gw, gh)
+    for t in (0, 9, 27, 36, 63):
+        keep, _ = core.cull_tile_members(rec, culled, t % gw, t // gw)
+        kb, v = binning.tile_list(rec["rect"], rec["depth32"], t % gw, t // gw, keep=keep)
+        lo, hi = ranges[t]
+        full = vals[lo:hi]
+        # the culled list is the full list with the dropped splats taken out, order kept
+        assert np.array_equal(v, full[keep[full]])
+
+
+def test_copy_mask_binning_agrees_with_tile_lists():
+    cfg, rec, cam = _scene_pairs("exp", 1, "sigma3", 1, n=2000, W=128, H_=128)
+    culled = core.Cfg(**{**cfg.__dict__, "tile_cull": 1})
+    gw = gh = 8
+    mask, nnear = core.cull_copy_mask(rec, culled)
+    assert nnear == 0 and 0 < mask.sum() < mask.size
+    keys, vals, ranges = binning.bin_and_sort_fast(rec["rect"], rec["depth32"], gw, gh, copy_mask=mask)
+    hist, _ = core.cull_histogram(rec, culled, gw, gh)
+    assert keys.shape[0] == mask.sum() == hist.sum()
+    assert np.array_equal((ranges[:, 1] - ranges[:, 0]).astype(np.int64), hist)
+    for t in range(gw * gh):
+        keep, _ = core.cull_tile_members(rec, culled, t % gw, t // gw)
+        kb, v = binning.tile_list(rec["rect"], rec["depth32"], t % gw, t // gw, keep=keep)
+        lo, hi = ranges[t]
+        assert np.array_equal(vals[lo:hi], v) and np.array_equal((keys[lo:hi] & 0xFFFFFFFF).astype(np.uint32), kb)

@@ -195,8 +195,8 @@ gs_status gs_bin_sort_workspace(int64_t n, int64_t key_capacity, int32_t num_til
  *      *num_keys entries valid), ranges [grid_w * grid_h, 2] uint32,
  *      num_keys (device int64) = K, the total number of copies,
  *      overflow (device int32) = 1 when K > key_capacity, else 0. On overflow
- *      no key is written and every range is (0, 0); the caller reads
- *      *num_keys and calls again with a larger capacity.
+ *      keys and vals hold no valid entries and every range is (0, 0); the
+ *      caller reads *num_keys and calls again with a larger capacity.
  *      tile_order [grid_w * grid_h] uint32 (may be NULL) = every tile id once,
  *      longest lists first (lists bucketed by length); passed to the blend
  *      entry points it makes the workgroups with the most work start first.
@@ -206,6 +206,36 @@ gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const 
                       int32_t grid_w, int32_t grid_h, int64_t key_capacity, void *workspace,
                       size_t workspace_bytes, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
                       uint32_t *tile_order, int64_t *num_keys, int32_t *overflow, void *stream);
+
+/* Tile binning with per-tile culling (the tile test of StopThePop that the
+ * paper adds to every renderer it evaluates, Sec. 2.1 and Sec. 4; App. A
+ * looks at the tile bound it gives): as gs_bin_sort, but a splat's copy for
+ * a tile of its rect is emitted only when the point of the tile's
+ * pixel-centre rectangle [16 tx + 0.5, 16 tx + 15.5] x [16 ty + 0.5,
+ * 16 ty + 15.5] where the splat contributes most, the minimum of
+ * Q = d^T conic d over that rectangle (d = point - mean2d), has
+ * Q <= cut(o, conic). cut is the largest Q at which gs_rasterize_fwd can
+ * include a pixel of the splat: the double threshold of alpha >= eps for the
+ * kernel, widened by bounds on the blend's float rounding (relative 2^-16 on
+ * the threshold plus 16 px, then 2^-19 times the rounding terms of its
+ * tile-local evaluation; the formula is in the implementation). Splats whose
+ * conic is not positive definite, or whose opacity reaches eps nowhere, get
+ * no copy. Every pixel the blend includes lies in a kept tile, so images,
+ * final_T, n_contrib and the blended set are those of gs_bin_sort's lists;
+ * the lists hold fewer entries (n_eval and last_contrib count list
+ * positions and shrink with them). K counts kept copies, so a key_capacity
+ * below the sum of tiles_touched may suffice.
+ *
+ * in : as gs_bin_sort, plus kernel and params (kernel, eps, tile) and the
+ *      projected records means2d [n,2] (8-byte aligned) and conic_opacity
+ *      [n,4] (16-byte aligned); grid_w * grid_h < 2^22.
+ * out, workspace: as gs_bin_sort (the same workspace size). */
+gs_status gs_bin_sort_culled(const gs_kernel *kernel, const gs_params *params, int64_t n, const float *depth,
+                             const int32_t *rect, const uint32_t *tiles_touched, const float *means2d,
+                             const float *conic_opacity, int32_t grid_w, int32_t grid_h, int64_t key_capacity,
+                             void *workspace, size_t workspace_bytes, uint64_t *keys, uint32_t *vals,
+                             uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys, int32_t *overflow,
+                             void *stream);
 
 /* Front-to-back blending per pixel (Sec. 2, Eq. 1 and the alpha compositing
  * it feeds; the kernel of Sec. 3 Eq. 2 / Eq. 6 or exp). For each pixel, over

@@ -56,7 +56,7 @@ class GsError(RuntimeError):
 _lib = None
 
 EXPORTS = ("gs_version", "gs_last_error", "gs_kernel_default", "gs_kernel_root", "gs_params_default",
-           "gs_preprocess", "gs_bin_sort_workspace", "gs_bin_sort", "gs_rasterize_fwd", "gs_rasterize_fwd_count",
+           "gs_preprocess", "gs_bin_sort_workspace", "gs_bin_sort", "gs_bin_sort_culled", "gs_rasterize_fwd", "gs_rasterize_fwd_count",
            "gs_rasterize_bwd", "gs_preprocess_bwd", "gs_batch_layout", "gs_render_batched")
 
 
@@ -77,6 +77,7 @@ def lib():
         L.gs_preprocess.argtypes = [P, P, P, I64] + [P] * 5 + [I32] + [P] * 6 + [P]
         L.gs_bin_sort_workspace.argtypes = [I64, I64, I32, P]
         L.gs_bin_sort.argtypes = [I64, P, P, P, I32, I32, I64, P, ctypes.c_size_t] + [P] * 6 + [P]
+        L.gs_bin_sort_culled.argtypes = [P, P, I64, P, P, P, P, P, I32, I32, I64, P, ctypes.c_size_t] + [P] * 6 + [P]
         L.gs_rasterize_fwd.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 5 + [P]
         L.gs_rasterize_fwd_count.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 6 + [P]
         L.gs_rasterize_bwd.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 3 + [P] * 3 + [P]
@@ -182,6 +183,15 @@ def gs_bin_sort(n, depth, rect, tiles_touched, grid_w, grid_h, key_capacity, wor
     _check(lib().gs_bin_sort(int(n), _ptr(depth), _ptr(rect), _ptr(tiles_touched), int(grid_w), int(grid_h),
                              int(key_capacity), _ptr(workspace), int(workspace_bytes), _ptr(keys), _ptr(vals),
                              _ptr(ranges), _ptr(tile_order), _ptr(num_keys), _ptr(overflow), _stream(stream)))
+
+
+def gs_bin_sort_culled(kernel, params, n, depth, rect, tiles_touched, means2d, conic_opacity, grid_w, grid_h,
+                       key_capacity, workspace, workspace_bytes, keys, vals, ranges, tile_order, num_keys, overflow,
+                       stream=None):
+    _check(lib().gs_bin_sort_culled(ctypes.byref(kernel), ctypes.byref(params), int(n), _ptr(depth), _ptr(rect),
+                                    _ptr(tiles_touched), _ptr(means2d), _ptr(conic_opacity), int(grid_w), int(grid_h),
+                                    int(key_capacity), _ptr(workspace), int(workspace_bytes), _ptr(keys), _ptr(vals),
+                                    _ptr(ranges), _ptr(tile_order), _ptr(num_keys), _ptr(overflow), _stream(stream)))
 
 
 def gs_rasterize_fwd(cam, kernel, params, n, means2d, conic_opacity, rgb, vals, ranges, tile_order, image, final_T,

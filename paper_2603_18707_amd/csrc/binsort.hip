@@ -32,6 +32,7 @@
 // Every kernel sized by the key count reads it from device memory and grids
 // are sized by the key capacity, so the stage runs without a host round trip
 // (and can be captured in a graph).
+#include "blend_common.h"
 #include "gs_internal.h"
 
 namespace gs {
@@ -436,6 +437,185 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
     a.tval[pos] = ssp[lo];
     a.tbits[pos] = sbits[lo];
     for (int p = 0; p < a.tile_passes; ++p) atomicAdd(&th[p * RADIX + ((tile >> (p * a.tile_bits)) & dmask)], 1u);
+  }
+  __syncthreads();
+  const int stripe = blockIdx.x % STRIPES;
+  for (int j = threadIdx.x; j < a.tile_passes * RADIX; j += BS) {
+    const uint32_t v = th[j];
+    if (v) atomicAdd(total_at(a.tot, stripe, j / RADIX, j % RADIX), v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tile culling: copies only for the tiles a splat can reach
+// ---------------------------------------------------------------------------
+struct Cull {
+  const float *means2d, *conic_opacity;  // the projected records
+  BlendParams p;                         // kernel and eps, for cull_cut
+  int tile;                              // tile edge in pixels
+};
+
+// Whether some point of the pixel-centre rectangle of tile (tx, ty) has
+// Q <= cut (the record's cull_cut), with Q in double from the float record.
+// Zero when the mean is inside; otherwise the least value over the four
+// edges, where Q restricted to an edge is a quadratic minimised at its vertex
+// clamped to the edge, written as a completed square (two non-negative
+// terms, no cancellation). The rectangle holds every pixel centre of the
+// tile, so a tile any pixel of which the blend includes is kept.
+__device__ inline bool tile_reached(float u, float v, float a, float b, float c, double cut, int tx, int ty, int T) {
+#pragma clang fp contract(off)
+  if (!(cut >= 0.0)) return false;
+  const double A = a, B = b, C = c;
+  const double x0 = ((double)(tx * T) + 0.5) - (double)u, x1 = ((double)(tx * T + T) - 0.5) - (double)u;
+  const double y0 = ((double)(ty * T) + 0.5) - (double)v, y1 = ((double)(ty * T + T) - 0.5) - (double)v;
+  if (x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0) return true;
+  const double det = A * C - B * B;
+  double q = cut + 1.0;
+  const double ya[2] = {y0, y1}, xa[2] = {x0, x1};
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    // along y = ya[e]: Q = A (dx - xs)^2 + (det / A) y^2 with xs = -B y / A
+    const double y = ya[e], xs = -(B * y) / A;
+    const double dx = fmin(fmax(xs, x0), x1) - xs;
+    q = fmin(q, A * (dx * dx) + (det / A) * (y * y));
+    // along x = xa[e]: Q = C (dy - ys)^2 + (det / C) x^2 with ys = -B x / C
+    const double x = xa[e], ys = -(B * x) / C;
+    const double dy = fmin(fmax(ys, y0), y1) - ys;
+    q = fmin(q, C * (dy * dy) + (det / C) * (x * x));
+  }
+  return q <= cut;
+}
+
+// Per-partition state of the culled emission: the splats' rectangle copies
+// (box offsets), their records and thresholds. The partition's box copies
+// are walked BS at a time in emission order; copy k belongs to the splat j
+// with loff[j] <= k < loff[j + 1].
+struct CullLds {
+  uint32_t loff[EPART + 1];
+  int32_t sx[EPART], sy[EPART], sw[EPART], sh[EPART];
+  double cut[EPART];
+  float su[EPART], sv[EPART], sa[EPART], sb[EPART], sc[EPART];
+  uint32_t ssp[EPART], sbits[EPART];
+};
+
+// Loads the partition's splats (emission positions s0..s0+EIPT-1 of this
+// thread) into the LDS tables; returns the partition's box copies.
+__device__ inline uint32_t cull_stage(uint32_t n, const uint32_t *perm, const uint32_t *tiles, const int32_t *rect,
+                                      const float *depth, const Cull &cu, CullLds &L) {
+  const uint32_t part = blockIdx.x;
+  const uint64_t s0 = (uint64_t)part * EPART + (uint64_t)threadIdx.x * EIPT;
+  uint32_t c[EIPT], sp[EIPT];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < EIPT; ++j) {
+    sp[j] = s0 + j < n ? (perm ? perm[s0 + j] : (uint32_t)(s0 + j)) : 0u;
+    c[j] = s0 + j < n ? tiles[sp[j]] : 0u;
+    sum += c[j];
+  }
+  uint32_t total;
+  uint32_t off = block_exclusive<uint32_t>(sum, total);
+#pragma unroll
+  for (int j = 0; j < EIPT; ++j) {
+    const int ls = threadIdx.x * EIPT + j;
+    L.loff[ls] = off;
+    off += c[j];
+    L.sw[ls] = 0;
+    if (c[j]) {
+      const int4 r = reinterpret_cast<const int4 *>(rect)[sp[j]];
+      const float2 m = reinterpret_cast<const float2 *>(cu.means2d)[sp[j]];
+      const float4 co = reinterpret_cast<const float4 *>(cu.conic_opacity)[sp[j]];
+      L.sx[ls] = r.x;
+      L.sy[ls] = r.y;
+      L.sw[ls] = r.z - r.x + 1;
+      L.sh[ls] = r.w - r.y + 1;
+      L.su[ls] = m.x;
+      L.sv[ls] = m.y;
+      L.sa[ls] = co.x;
+      L.sb[ls] = co.y;
+      L.sc[ls] = co.z;
+      L.cut[ls] = cull_cut(cu.p, co.w, co.x, co.y, co.z);
+      L.ssp[ls] = sp[j];
+      L.sbits[ls] = depth ? __float_as_uint(depth[sp[j]]) : 0u;
+    }
+  }
+  if (threadIdx.x == BS - 1) L.loff[EPART] = off;
+  __syncthreads();
+  return total;
+}
+
+// Box copy k of the partition: whether its tile is kept, and the tile
+__device__ inline bool cull_copy(uint32_t k, const CullLds &L, int grid_w, int T, uint32_t &tile, uint32_t &lo_out) {
+  uint32_t lo = 0, hi = EPART;  // loff[lo] <= k < loff[hi]
+#pragma unroll
+  for (int it = 0; it < 10; ++it) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (L.loff[mid] <= k) lo = mid; else hi = mid;
+  }
+  lo_out = lo;
+  const int32_t wdt = L.sw[lo];
+  if (wdt <= 0) return false;  // counts that disagree with the rectangle
+  const uint32_t r = k - L.loff[lo];
+  const uint32_t q = r / (uint32_t)wdt;
+  if ((int64_t)q >= (int64_t)L.sh[lo]) return false;  // a count larger than the rectangle: no copy outside it
+  const int tx = L.sx[lo] + (int)(r - q * (uint32_t)wdt), ty = L.sy[lo] + (int)q;
+  tile = (uint32_t)ty * (uint32_t)grid_w + (uint32_t)tx;
+  return tile_reached(L.su[lo], L.sv[lo], L.sa[lo], L.sb[lo], L.sc[lo], L.cut[lo], tx, ty, T);
+}
+
+// kept copies per emission partition (the culled emit_sums)
+__global__ __launch_bounds__(BS) void emit_sums_culled(uint32_t n, const uint32_t *__restrict__ tiles,
+                                                       const uint32_t *__restrict__ perm, const int32_t *__restrict__ rect,
+                                                       Cull cu, int grid_w, uint64_t *__restrict__ esum) {
+  __shared__ CullLds L;
+  const uint32_t T = cull_stage(n, perm, tiles, rect, nullptr, cu, L);
+  uint64_t kept = 0;
+  for (uint32_t k = threadIdx.x; k < T; k += BS) {
+    uint32_t tile, lo;
+    kept += cull_copy(k, L, grid_w, cu.tile, tile, lo) ? 1u : 0u;
+  }
+  uint64_t total;
+  block_exclusive<uint64_t>(kept, total);
+  if (threadIdx.x == 0) esum[blockIdx.x] = total;
+}
+
+// the kept copies of a partition, in emission order (box copies walked BS at
+// a time, the kept ones compacted by a workgroup scan), counting the tile
+// digits as they are written; as emit_copies otherwise
+__global__ __launch_bounds__(BS) void emit_copies_culled(Emit a, Cull cu) {
+  __shared__ CullLds L;
+  __shared__ uint32_t th[MAX_TILE_PASSES * RADIX];
+  const uint32_t nparts = (uint32_t)(((uint64_t)a.n + EPART - 1) / EPART);
+  const uint32_t part = blockIdx.x;
+  for (int j = threadIdx.x; j < MAX_TILE_PASSES * RADIX; j += BS) th[j] = 0u;
+  uint64_t part_sum = 0, pre;
+  for (uint32_t q = threadIdx.x; q < part; q += BS) part_sum += a.esum[q];
+  block_exclusive<uint64_t>(part_sum, pre);
+  const uint64_t mine = a.esum[part];
+  if (threadIdx.x == 0 && part == nparts - 1) {
+    const uint64_t K = pre + mine;
+    const bool over = K > a.capacity;
+    *a.num_keys = (int64_t)K;
+    *a.overflow = over ? 1 : 0;
+    a.ctr[CTR_KEYS] = over ? 0u : (uint32_t)K;
+  }
+  const uint32_t T = cull_stage(a.n, a.perm, a.tiles, a.rect, a.depth, cu, L);
+  if (pre + mine > a.capacity || mine == 0) return;  // an overflowing call writes no key
+  const uint32_t dmask = (1u << a.tile_bits) - 1u;
+  uint64_t carry = pre;
+  for (uint32_t base = 0; base < T; base += BS) {  // uniform trip count
+    const uint32_t k = base + threadIdx.x;
+    uint32_t tile = 0, lo = 0;
+    const bool keep = k < T && cull_copy(k, L, a.grid_w, cu.tile, tile, lo);
+    uint32_t chunk;
+    const uint32_t at = block_exclusive<uint32_t>(keep ? 1u : 0u, chunk);
+    if (keep && carry + at < pre + mine) {  // both kernels take the same decisions; the bound only guards the writes
+      const uint64_t pos = carry + at;
+      a.tkey[pos] = tile;
+      a.tval[pos] = L.ssp[lo];
+      a.tbits[pos] = L.sbits[lo];
+      for (int p = 0; p < a.tile_passes; ++p) atomicAdd(&th[p * RADIX + ((tile >> (p * a.tile_bits)) & dmask)], 1u);
+    }
+    carry += chunk;
   }
   __syncthreads();
   const int stripe = blockIdx.x % STRIPES;
@@ -1033,10 +1213,10 @@ void radix_pass(const Pass &a, int64_t capacity, const uint32_t *tot, int pass, 
 }
 }  // namespace
 
-hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles, int grid_w,
-                          int grid_h, int64_t capacity, void *ws, size_t, uint64_t *keys, uint32_t *vals,
-                          uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys, int32_t *overflow,
-                          hipStream_t s) {
+namespace {
+hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles, int grid_w, int grid_h,
+                   int64_t capacity, void *ws, uint64_t *keys, uint32_t *vals, uint32_t *ranges, uint32_t *tile_order,
+                   int64_t *num_keys, int32_t *overflow, const Cull *cu, hipStream_t s) {
   const int64_t ntiles = (int64_t)grid_w * grid_h;
   Workspace w;
   carve(ws, n, capacity, ntiles, &w);
@@ -1052,7 +1232,7 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
 
   // 0. zero totals, counters and ranges; num_keys = overflow = 0 (with step 1 when n > 0)
   const size_t nz16 = w.zero_bytes / 16, nr = 2 * (size_t)ntiles;
-  if (n == 0 || presort) {
+  if (n == 0 || presort || cu) {
     const size_t m = nz16 > nr ? nz16 : nr;
     const unsigned grid = (unsigned)(m / BS + 1 < 2048 ? m / BS + 1 : 2048);
     hipLaunchKernelGGL(clear_state, dim3(grid), dim3(BS), 0, s, (uint4 *)w.zero_begin, nz16, ranges, nr, num_keys,
@@ -1089,8 +1269,12 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
   if (n > 0) {
     // 1. copies (in splat-index or depth order) with their depth bits, the tile digit totals, K
     const unsigned egrid = ceil_div(n, EPART);
-    hipLaunchKernelGGL(emit_sums, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, tiles, perm, w.esum,
-                       presort ? (uint4 *)nullptr : (uint4 *)w.zero_begin, nz16, ranges, nr, num_keys, overflow);
+    if (cu)
+      hipLaunchKernelGGL(emit_sums_culled, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, tiles, perm, rect, *cu, grid_w,
+                         w.esum);
+    else
+      hipLaunchKernelGGL(emit_sums, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, tiles, perm, w.esum,
+                         presort ? (uint4 *)nullptr : (uint4 *)w.zero_begin, nz16, ranges, nr, num_keys, overflow);
     Emit e{};
     e.n = (uint32_t)n;
     e.perm = perm;
@@ -1109,7 +1293,10 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
     e.tile_bits = tp.bits;
     e.num_keys = num_keys;
     e.overflow = overflow;
-    hipLaunchKernelGGL(emit_copies, dim3(egrid), dim3(BS), 0, s, e);
+    if (cu)
+      hipLaunchKernelGGL(emit_copies_culled, dim3(egrid), dim3(BS), 0, s, e, *cu);
+    else
+      hipLaunchKernelGGL(emit_copies, dim3(egrid), dim3(BS), 0, s, e);
   }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
@@ -1172,6 +1359,25 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
   if (tile_order)
     hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order, (uint32_t *)nullptr);
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles, int grid_w,
+                          int grid_h, int64_t capacity, void *ws, size_t, uint64_t *keys, uint32_t *vals,
+                          uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys, int32_t *overflow,
+                          hipStream_t s) {
+  return binsort(n, depth, rect, tiles, grid_w, grid_h, capacity, ws, keys, vals, ranges, tile_order, num_keys,
+                 overflow, nullptr, s);
+}
+
+hipError_t launch_binsort_culled(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles,
+                                 const float *means2d, const float *conic_opacity, const BlendParams &bp, int tile,
+                                 int grid_w, int grid_h, int64_t capacity, void *ws, size_t, uint64_t *keys,
+                                 uint32_t *vals, uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys,
+                                 int32_t *overflow, hipStream_t s) {
+  const Cull cu{means2d, conic_opacity, bp, tile};
+  return binsort(n, depth, rect, tiles, grid_w, grid_h, capacity, ws, keys, vals, ranges, tile_order, num_keys,
+                 overflow, &cu, s);
 }
 
 }  // namespace gs

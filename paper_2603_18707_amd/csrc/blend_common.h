@@ -18,15 +18,15 @@ constexpr int PIX = 4;  // pixels per lane
 
 // first root of o p(x) = eps for orders 2 and 3, in double (App. B closed
 // forms, Newton-polished); -1 when p(0) < eps / o
-__device__ inline float opacity_threshold64(const BlendParams &p, int order, float o) {
-  if (!(o > 0.0f)) return -1.0f;
+__device__ inline double opacity_root_d(const BlendParams &p, int order, float o) {
+  if (!(o > 0.0f)) return -1.0;
   double c[4] = {p.c[0], p.c[1], p.c[2], p.c[3]};
   const double cc = c[0] - (double)p.eps / (double)o;
-  if (cc < 0.0) return -1.0f;
+  if (cc < 0.0) return -1.0;
   double x;
   if (order == 2) {
     const double disc = c[1] * c[1] - 4.0 * cc * c[2];
-    if (disc < 0.0) return -1.0f;
+    if (disc < 0.0) return -1.0;
     x = 2.0 * cc / (-c[1] + sqrt(disc));
   } else {
     const double d0 = c[2] * c[2] - 3.0 * c[3] * c[1];
@@ -45,7 +45,10 @@ __device__ inline float opacity_threshold64(const BlendParams &p, int order, flo
     }
     if (fp != 0.0) x -= f / fp;
   }
-  return (float)x;
+  return x;
+}
+__device__ inline float opacity_threshold64(const BlendParams &p, int order, float o) {
+  return (float)opacity_root_d(p, order, o);
 }
 
 // Staged record, positions relative to the tile's corner (x0, y0):
@@ -61,19 +64,60 @@ __device__ inline float opacity_threshold64(const BlendParams &p, int order, flo
 // positions keep the pixel offsets free of the rounding of absolute image
 // coordinates. A conic that is not positive definite gets x_e = -1 and a zero
 // quadric: it never passes.
+// The quadric value up to which alpha = o' k(Q) >= eps: the threshold of
+// the inclusion test t = x_e - Q >= 0 (-1 when no pixel can pass).
+template <int KIND>
+__device__ inline float alpha_threshold(const BlendParams &p, float o) {
+  if (KIND == BLEND_POLY1) return (o * p.c[0] >= p.eps) ? (p.eps / o - p.c[0]) / p.c[1] : -1.0f;
+  if (KIND == BLEND_EXP) return (o >= p.eps) ? 1.38629436111989061f * (log2f(o) - p.log2_eps) : -1.0f;  // 2 ln(o/eps)
+  return opacity_threshold64(p, KIND == BLEND_POLY2 ? 2 : 3, o);
+}
+
+// Tile culling bound: the largest Q at which the blend can include any pixel
+// of a record with opacity o and conic (a, b, c); negative when it includes
+// none (opacity below the cut-off, or a conic that is not positive
+// definite). Starting from the threshold thr of alpha >= eps in double, it
+// adds (1) 2^-16 (|thr| + 16) for the float rounding of x_e (a few ulps of
+// thr, or of the root scale when eps / o nearly equals c_0, and the log2
+// approximation of the exponential), giving T, and (2) for the float
+// evaluation of t = x_e - Q at a tile-local pixel: with u = 2^-24 the float
+// inclusion t' >= 0 implies sqrt(Q) <= sqrt(T)(1 + 9u) + D', where
+// D' <= u (4 sqrt(T) + 16 sqrt(g) + 7 |b| sqrt(T / det) + 16 |b| / sqrt(c)
+// + 32 sqrt(c)) sums the rounding of the tile-local offsets (at most 16 px
+// from the tile's corner plus the offset), of g and h (the reciprocal is
+// within 1 ulp) and of the products forming e = dy + h dx and t. The bound
+// takes 32 times D'. Rounding of the double evaluation itself is covered by
+// a final factor 1 + 2^-30. Everything is rounded as written (no fused
+// multiply-adds), so any double implementation of the same formula takes
+// the same decisions.
+__device__ inline double cull_cut(const BlendParams &p, float o, float a, float b, float c) {
+#pragma clang fp contract(off)
+  if (!(o > 0.0f) || !(a > 0.0f) || !(c > 0.0f)) return -1.0;
+  const double A = a, B = b, C = c;
+  const double det = A * C - B * B;
+  if (!(det > 0.0)) return -1.0;
+  double thr;
+  switch (p.blend) {
+    case BLEND_POLY1: thr = ((double)p.eps / (double)o - (double)p.c[0]) / (double)p.c[1]; break;
+    case BLEND_EXP: thr = 2.0 * log((double)o / (double)p.eps); break;
+    case BLEND_POLY2: thr = opacity_root_d(p, 2, o); break;
+    default: thr = opacity_root_d(p, 3, o); break;
+  }
+  const double T = thr + 0x1p-16 * (fabs(thr) + 16.0);
+  if (!(T >= 0.0)) return -1.0;
+  const double sT = sqrt(T), aB = fabs(B);
+  const double D = 0x1p-19 * (4.0 * sT + 16.0 * sqrt(det / C) + 8.0 * aB * sqrt(T / det) + 16.0 * aB / sqrt(C) +
+                              32.0 * sqrt(C));
+  const double r = sT * (1.0 + 0x1p-18) + D;
+  return r * r * (1.0 + 0x1p-30);
+}
+
 template <int KIND>
 __device__ inline void fold(float2 m, float4 co, float3 c, float x0, float y0, const BlendParams &p, float4 &s0,
                             float4 &s1, float4 &s2) {
   const float o = co.w;
-  float xe, S = 0.0f;
-  if (KIND == BLEND_POLY1) {
-    xe = (o * p.c[0] >= p.eps) ? (p.eps / o - p.c[0]) / p.c[1] : -1.0f;
-    S = -o * p.c[1];
-  } else if (KIND == BLEND_EXP) {
-    xe = (o >= p.eps) ? 1.38629436111989061f * (log2f(o) - p.log2_eps) : -1.0f;  // 2 ln(o / eps)
-  } else {
-    xe = opacity_threshold64(p, KIND == BLEND_POLY2 ? 2 : 3, o);
-  }
+  float xe = alpha_threshold<KIND>(p, o), S = 0.0f;
+  if (KIND == BLEND_POLY1) S = -o * p.c[1];
   // a c - b^2 in double: both products of floats are exact there
   const double det = fma((double)co.x, (double)co.z, -((double)co.y * (double)co.y));
   const bool pd = co.x > 0.0f && co.z > 0.0f && det > 0.0;

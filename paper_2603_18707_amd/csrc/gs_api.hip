@@ -258,17 +258,13 @@ gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const 
                    "gs_bin_sort launch");
 }
 
-static gs_status make_blend(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params,
-                            BlendParams *b) {
+// the kernel part of the blend parameters (no image size)
+static gs_status make_kernel_params(const gs_kernel *kernel, const gs_params *params, BlendParams *b) {
   gs_status st;
-  if ((st = check_camera(cam)) != GS_OK || (st = check_params(params)) != GS_OK) return st;
+  if ((st = check_params(params)) != GS_OK) return st;
   Resolved r;
   if ((st = resolve_kernel(kernel, &r)) != GS_OK) return st;
   std::memset(b, 0, sizeof(*b));
-  b->W = cam->width;
-  b->H = cam->height;
-  b->gx = (cam->width + params->tile - 1) / params->tile;
-  b->gy = (cam->height + params->tile - 1) / params->tile;
   b->blend = blend_kind(r);
   for (int i = 0; i < 4; ++i) b->c[i] = (float)r.c[i];
   b->x0 = (float)r.x0;
@@ -279,6 +275,46 @@ static gs_status make_blend(const gs_camera *cam, const gs_kernel *kernel, const
   for (int i = 0; i < 3; ++i) b->bg[i] = params->bg[i];
   b->threads = params->blend_threads ? params->blend_threads : 256;
   return GS_OK;
+}
+
+static gs_status make_blend(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params,
+                            BlendParams *b) {
+  gs_status st;
+  if ((st = check_camera(cam)) != GS_OK || (st = make_kernel_params(kernel, params, b)) != GS_OK) return st;
+  b->W = cam->width;
+  b->H = cam->height;
+  b->gx = (cam->width + params->tile - 1) / params->tile;
+  b->gy = (cam->height + params->tile - 1) / params->tile;
+  return GS_OK;
+}
+
+gs_status gs_bin_sort_culled(const gs_kernel *kernel, const gs_params *params, int64_t n, const float *depth,
+                             const int32_t *rect, const uint32_t *tiles_touched, const float *means2d,
+                             const float *conic_opacity, int32_t grid_w, int32_t grid_h, int64_t key_capacity,
+                             void *workspace, size_t workspace_bytes, uint64_t *keys, uint32_t *vals,
+                             uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys, int32_t *overflow,
+                             void *stream) {
+  BlendParams b;
+  gs_status st = make_kernel_params(kernel, params, &b);
+  if (st != GS_OK) return st;
+  if (grid_w < 1 || grid_h < 1 || (int64_t)grid_w * grid_h >= (1ll << 22))
+    return fail(GS_EINVAL, "tile grid %dx%d invalid for culled binning (needs fewer than 2^22 tiles)", grid_w, grid_h);
+  size_t need = 0;
+  if ((st = gs_bin_sort_workspace(n, key_capacity, grid_w * grid_h, &need)) != GS_OK) return st;
+  if (!workspace || workspace_bytes < need)
+    return fail(GS_EINVAL, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes, need);
+  if (!ranges || !num_keys || !overflow) return fail(GS_EINVAL, "NULL output argument");
+  if (key_capacity > 0 && (!keys || !vals)) return fail(GS_EINVAL, "NULL keys or vals");
+  if (n > 0 && (!depth || !rect || !tiles_touched || !means2d || !conic_opacity))
+    return fail(GS_EINVAL, "NULL input argument");
+  if (!aligned(workspace, 256) || (rect && !aligned(rect, 16)) || (keys && !aligned(keys, 8)) ||
+      (means2d && !aligned(means2d, 8)) || (conic_opacity && !aligned(conic_opacity, 16)))
+    return fail(GS_EINVAL,
+                "workspace needs 256-byte, rect and conic_opacity 16-byte, keys and means2d 8-byte alignment");
+  return check_hip(launch_binsort_culled(n, depth, rect, tiles_touched, means2d, conic_opacity, b, params->tile, grid_w,
+                                         grid_h, key_capacity, workspace, workspace_bytes, keys, vals, ranges,
+                                         tile_order, num_keys, overflow, (hipStream_t)stream),
+                   "gs_bin_sort_culled launch");
 }
 
 gs_status gs_rasterize_fwd(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,

@@ -103,6 +103,17 @@ struct BlendParams {
   float bg[3];
 };
 
+// launch_binsort with tile culling: a splat's copy for a tile of its
+// rectangle is emitted only when some pixel centre of the tile may pass the
+// blend's inclusion test (bp supplies the kernel, eps and the blend kind;
+// means2d and conic_opacity are the projected records). Needs
+// grid_w * grid_h < 2^22.
+hipError_t launch_binsort_culled(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles,
+                                 const float *means2d, const float *conic_opacity, const BlendParams &bp, int tile,
+                                 int grid_w, int grid_h, int64_t capacity, void *ws, size_t ws_bytes, uint64_t *keys,
+                                 uint32_t *vals, uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys,
+                                 int32_t *overflow, hipStream_t s);
+
 struct BlendOut {
   float *image, *final_T;
   uint32_t *n_contrib, *last_contrib, *n_eval;

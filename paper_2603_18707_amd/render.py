@@ -51,8 +51,9 @@ class Rasterizer:
     key capacity between frames (the capacity grows when a frame overflows)."""
 
     def __init__(self, kernel: L.GsKernel, params: L.GsParams = None, device="cuda", capacity: int = 0,
-                 reuse_buffers: bool = True):
+                 reuse_buffers: bool = True, tile_cull: bool = False):
         self.kernel = kernel
+        self.tile_cull = bool(tile_cull)  # bin with gs_bin_sort_culled: copies only for reachable tiles
         self.params = params if params is not None else L.gs_params_default()
         self.device = torch.device(device)
         self.capacity = int(capacity)
@@ -97,8 +98,13 @@ class Rasterizer:
                    tile_order=self._buf("tile_order", (gw * gh,), torch.int32),
                    num_keys=self._buf("num_keys", (1,), torch.int64),
                    overflow=self._buf("overflow", (1,), torch.int32))
-        L.gs_bin_sort(n, proj["depth"], proj["rect"], proj["tiles"], gw, gh, cap, ws, ws.numel(), out["keys"],
-                      out["vals"], out["ranges"], out["tile_order"], out["num_keys"], out["overflow"], stream)
+        if self.tile_cull:
+            L.gs_bin_sort_culled(self.kernel, self.params, n, proj["depth"], proj["rect"], proj["tiles"],
+                                 proj["means2d"], proj["conic_opacity"], gw, gh, cap, ws, ws.numel(), out["keys"],
+                                 out["vals"], out["ranges"], out["tile_order"], out["num_keys"], out["overflow"], stream)
+        else:
+            L.gs_bin_sort(n, proj["depth"], proj["rect"], proj["tiles"], gw, gh, cap, ws, ws.numel(), out["keys"],
+                          out["vals"], out["ranges"], out["tile_order"], out["num_keys"], out["overflow"], stream)
         out["capacity"] = cap
         return out
 

@@ -80,11 +80,12 @@ RECT_MODES = {"square": 0, "box": 1}
 RECT_NAMES = {"square": "bounding-square tile rectangles", "box": "ellipse-box tile rectangles"}
 
 
-def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, threads=0, rect="box"):
+def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, threads=0, rect="box", cull=False):
     """Times `steps` frames; per-stage HIP events inside the same timed loop.
-    threads = 0 lets the autotuner pick the blend launch shape during warm-up."""
+    threads = 0 lets the autotuner pick the blend launch shape during warm-up;
+    cull bins with per-tile culling (gs_bin_sort_culled)."""
     from paper_2603_18707_amd import autotune
-    r = render.Rasterizer(render.kernel_spec(kind, order, radius))
+    r = render.Rasterizer(render.kernel_spec(kind, order, radius), tile_cull=cull)
     r.params.rect_mode = RECT_MODES[rect]
     stream = torch.cuda.current_stream()
     # warm-up frames also size the key capacity (host readback happens here only)
@@ -210,19 +211,21 @@ def time_heavy(torch, render, scenes, steps, rect):
     dev = render.to_device(sc)
     out = {"workload": "4M splats (Student-t log-scales, SH3), orbit views 0 (1920x1080) and 1 (3840x2160)"}
     other = "square" if rect == "box" else "box"
-    for label, (w, h, view), modes in (("1080p", (1920, 1080, 0), (rect,)), ("4k", (3840, 2160, 1), (rect, other))):
+    for label, (w, h, view), modes in (("1080p", (1920, 1080, 0), ((rect, False), (rect, True))),
+                                       ("4k", (3840, 2160, 1), ((rect, False), (other, False), (rect, True)))):
         cam = scenes.orbit_camera(w, h, 2.0 * math.pi * view / 8)
-        for mode in modes:
+        for mode, cull in modes:
             row = {}
             for name, kind, order, radius in (("poly1", "poly", 1, "opacity"), ("exp", "exp", 1, "sigma3")):
-                t = time_config(torch, render, dev, cam, kind, order, radius, steps, 2, 0, mode)
+                t = time_config(torch, render, dev, cam, kind, order, radius, steps, 2, 0, mode, cull)
                 row[name] = {"ms_per_step": round(t["ms"], 3), "Mpix_per_s": round(w * h / (t["ms"] * 1e-3) / 1e6, 1),
                              "keys": t["K"], "stage_ms": [round(x, 3) for x in t["stage_ms"]]}
-                print(f"[bench] heavy {label} {mode} {name}: {t['ms']:.3f} ms K={t['K']}", file=sys.stderr, flush=True)
+                print(f"[bench] heavy {label} {mode}{' tile-culled' if cull else ''} {name}: {t['ms']:.3f} ms "
+                      f"K={t['K']} stages={[round(x, 3) for x in t['stage_ms']]}", file=sys.stderr, flush=True)
                 del t
                 torch.cuda.empty_cache()
             row["speedup_poly1_vs_exp"] = round(row["exp"]["ms_per_step"] / row["poly1"]["ms_per_step"], 4)
-            out[f"{label}_{'ellipse_box' if mode == 'box' else 'square'}"] = row
+            out[f"{label}_{'ellipse_box' if mode == 'box' else 'square'}{'_tile_culled' if cull else ''}"] = row
     return out
 
 
@@ -393,6 +396,21 @@ def main():
         if "exp" in alt and "poly1" in alt:
             alt["speedup_poly1_vs_exp"] = round(alt["exp"]["ms_per_step"] / alt["poly1"]["ms_per_step"], 4)
         out["other_rect"] = alt
+        # the same frames binned with per-tile culling (identical images, shorter lists)
+        tc = {"rect": RECT_NAMES[a.rect], "binning": "gs_bin_sort_culled"}
+        for name, kind, order, radius in configs:
+            t = time_config(torch, render, scene, cam, kind, order, radius, a.steps, a.warmup, a.blend_threads, a.rect,
+                            cull=True)
+            print(f"[bench] {name} ({a.rect}, tile-culled): {t['ms']:.3f} ms/frame (pre {t['stage_ms'][0]:.3f}, sort "
+                  f"{t['stage_ms'][1]:.3f}, blend {t['stage_ms'][2]:.3f}) K={t['K']} E={t['E']}", file=sys.stderr,
+                  flush=True)
+            tc[name] = {"ms_per_step": round(t["ms"], 4), "Mpix_per_s": round(W * H / (t["ms"] * 1e-3) / 1e6, 2),
+                        "keys": t["K"], "evals": t["E"],
+                        "stage_ms": {"preprocess": round(t["stage_ms"][0], 4), "bin_sort": round(t["stage_ms"][1], 4),
+                                     "blend": round(t["stage_ms"][2], 4)}}
+        if "exp" in tc and "poly1" in tc:
+            tc["speedup_poly1_vs_exp"] = round(tc["exp"]["ms_per_step"] / tc["poly1"]["ms_per_step"], 4)
+        out["tile_culled"] = tc
     if not a.no_batched and not a.only:
         print("[bench] batched multi-view ...", file=sys.stderr, flush=True)
         out["batched"] = time_batched(torch, render, scenes, max(2, a.steps // 10), a.rect)

@@ -455,164 +455,215 @@ struct Cull {
   int tile;                              // tile edge in pixels
 };
 
-// Whether some point of the pixel-centre rectangle of tile (tx, ty) has
-// Q <= cut (the record's cull_cut), with Q in double from the float record.
-// Zero when the mean is inside; otherwise the least value over the four
-// edges, where Q restricted to an edge is a quadratic minimised at its vertex
-// clamped to the edge, written as a completed square (two non-negative
-// terms, no cancellation). The rectangle holds every pixel centre of the
-// tile, so a tile any pixel of which the blend includes is kept.
-__device__ inline bool tile_reached(float u, float v, float a, float b, float c, double cut, int tx, int ty, int T) {
-#pragma clang fp contract(off)
-  if (!(cut >= 0.0)) return false;
-  const double A = a, B = b, C = c;
-  const double x0 = ((double)(tx * T) + 0.5) - (double)u, x1 = ((double)(tx * T + T) - 0.5) - (double)u;
-  const double y0 = ((double)(ty * T) + 0.5) - (double)v, y1 = ((double)(ty * T + T) - 0.5) - (double)v;
-  if (x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0) return true;
-  const double det = A * C - B * B;
-  double q = cut + 1.0;
-  const double ya[2] = {y0, y1}, xa[2] = {x0, x1};
-#pragma unroll
-  for (int e = 0; e < 2; ++e) {
-    // along y = ya[e]: Q = A (dx - xs)^2 + (det / A) y^2 with xs = -B y / A
-    const double y = ya[e], xs = -(B * y) / A;
-    const double dx = fmin(fmax(xs, x0), x1) - xs;
-    q = fmin(q, A * (dx * dx) + (det / A) * (y * y));
-    // along x = xa[e]: Q = C (dy - ys)^2 + (det / C) x^2 with ys = -B x / C
-    const double x = xa[e], ys = -(B * x) / C;
-    const double dy = fmin(fmax(ys, y0), y1) - ys;
-    q = fmin(q, C * (dy * dy) + (det / C) * (x * x));
-  }
-  return q <= cut;
-}
-
-// Per-partition state of the culled emission: the splats' rectangle copies
-// (box offsets), their records and thresholds. The partition's box copies
-// are walked BS at a time in emission order; copy k belongs to the splat j
-// with loff[j] <= k < loff[j + 1].
+// One workgroup of the culled binning takes BS splats (in emission order)
+// and walks their rectangle rows, BS rows at a time: rows, not tiles, are
+// the unit of work, so a splat covering thousands of tiles costs a few dozen
+// row items and the workgroup's lanes stay evenly loaded. Per splat it keeps
+// what the tile test needs, in double: the conic (a, b, c) with b/a, b/c,
+// det/a, det/c and 1/a precomputed, the cut, and the half extents
+// X = sqrt(cut c / det), Y = sqrt(cut a / det) of the region Q <= cut.
 struct CullLds {
-  uint32_t loff[EPART + 1];
-  int32_t sx[EPART], sy[EPART], sw[EPART], sh[EPART];
-  double cut[EPART];
-  float su[EPART], sv[EPART], sa[EPART], sb[EPART], sc[EPART];
-  uint32_t ssp[EPART], sbits[EPART];
+  uint32_t roff[BS + 1];  // row items of the workgroup's splats before each splat
+  float u[BS], v[BS], A[BS], C[BS];
+  double iA[BS], bA[BS], bC[BS], dA[BS], dC[BS], cut[BS], X[BS], Y[BS];
+  int32_t x0[BS], x1[BS], y0[BS];
+  uint32_t sp[BS], bits[BS];
 };
 
-// Loads the partition's splats (emission positions s0..s0+EIPT-1 of this
-// thread) into the LDS tables; returns the partition's box copies.
+// Stages the workgroup's splats; returns its row items. A splat without
+// tiles, with an empty rectangle or with cut < 0 has no row.
 __device__ inline uint32_t cull_stage(uint32_t n, const uint32_t *perm, const uint32_t *tiles, const int32_t *rect,
                                       const float *depth, const Cull &cu, CullLds &L) {
-  const uint32_t part = blockIdx.x;
-  const uint64_t s0 = (uint64_t)part * EPART + (uint64_t)threadIdx.x * EIPT;
-  uint32_t c[EIPT], sp[EIPT];
-  uint32_t sum = 0;
-#pragma unroll
-  for (int j = 0; j < EIPT; ++j) {
-    sp[j] = s0 + j < n ? (perm ? perm[s0 + j] : (uint32_t)(s0 + j)) : 0u;
-    c[j] = s0 + j < n ? tiles[sp[j]] : 0u;
-    sum += c[j];
-  }
-  uint32_t total;
-  uint32_t off = block_exclusive<uint32_t>(sum, total);
-#pragma unroll
-  for (int j = 0; j < EIPT; ++j) {
-    const int ls = threadIdx.x * EIPT + j;
-    L.loff[ls] = off;
-    off += c[j];
-    L.sw[ls] = 0;
-    if (c[j]) {
-      const int4 r = reinterpret_cast<const int4 *>(rect)[sp[j]];
-      const float2 m = reinterpret_cast<const float2 *>(cu.means2d)[sp[j]];
-      const float4 co = reinterpret_cast<const float4 *>(cu.conic_opacity)[sp[j]];
-      L.sx[ls] = r.x;
-      L.sy[ls] = r.y;
-      L.sw[ls] = r.z - r.x + 1;
-      L.sh[ls] = r.w - r.y + 1;
-      L.su[ls] = m.x;
-      L.sv[ls] = m.y;
-      L.sa[ls] = co.x;
-      L.sb[ls] = co.y;
-      L.sc[ls] = co.z;
-      L.cut[ls] = cull_cut(cu.p, co.w, co.x, co.y, co.z);
-      L.ssp[ls] = sp[j];
-      L.sbits[ls] = depth ? __float_as_uint(depth[sp[j]]) : 0u;
+#pragma clang fp contract(off)
+  const uint64_t pos = (uint64_t)blockIdx.x * BS + threadIdx.x;
+  const int j = threadIdx.x;
+  uint32_t rows = 0;
+  if (pos < n) {
+    const uint32_t s = perm ? perm[pos] : (uint32_t)pos;
+    if (tiles[s] != 0u) {
+      const int4 r = reinterpret_cast<const int4 *>(rect)[s];
+      const float2 m = reinterpret_cast<const float2 *>(cu.means2d)[s];
+      const float4 co = reinterpret_cast<const float4 *>(cu.conic_opacity)[s];
+      const double cut = cull_cut(cu.p, co.w, co.x, co.y, co.z);
+      if (cut >= 0.0 && r.z >= r.x && r.w >= r.y) {
+        const double A = co.x, B = co.y, C = co.z, det = A * C - B * B;
+        rows = (uint32_t)(r.w - r.y + 1);
+        L.u[j] = m.x;
+        L.v[j] = m.y;
+        L.A[j] = co.x;
+        L.C[j] = co.z;
+        L.iA[j] = 1.0 / A;
+        L.bA[j] = B / A;
+        L.bC[j] = B / C;
+        L.dA[j] = det / A;
+        L.dC[j] = det / C;
+        L.cut[j] = cut;
+        L.X[j] = sqrt(cut * C / det);
+        L.Y[j] = sqrt(cut * A / det);
+        L.x0[j] = r.x;
+        L.x1[j] = r.z;
+        L.y0[j] = r.y;
+        L.sp[j] = s;
+        L.bits[j] = depth ? __float_as_uint(depth[s]) : 0u;
+      }
     }
   }
-  if (threadIdx.x == BS - 1) L.loff[EPART] = off;
+  uint32_t total;
+  L.roff[j] = block_exclusive<uint32_t>(rows, total);
+  if (j == BS - 1) L.roff[BS] = total;
   __syncthreads();
   return total;
 }
 
-// Box copy k of the partition: whether its tile is kept, and the tile
-__device__ inline bool cull_copy(uint32_t k, const CullLds &L, int grid_w, int T, uint32_t &tile, uint32_t &lo_out) {
-  uint32_t lo = 0, hi = EPART;  // loff[lo] <= k < loff[hi]
+// row item k of the workgroup: its splat j (roff[j] <= k < roff[j + 1]) and tile row
+__device__ inline void row_item(const CullLds &L, uint32_t k, int &j, int &ty) {
+  uint32_t lo = 0, hi = BS;
 #pragma unroll
-  for (int it = 0; it < 10; ++it) {
+  for (int it = 0; it < 8; ++it) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (L.loff[mid] <= k) lo = mid; else hi = mid;
+    if (L.roff[mid] <= k) lo = mid; else hi = mid;
   }
-  lo_out = lo;
-  const int32_t wdt = L.sw[lo];
-  if (wdt <= 0) return false;  // counts that disagree with the rectangle
-  const uint32_t r = k - L.loff[lo];
-  const uint32_t q = r / (uint32_t)wdt;
-  if ((int64_t)q >= (int64_t)L.sh[lo]) return false;  // a count larger than the rectangle: no copy outside it
-  const int tx = L.sx[lo] + (int)(r - q * (uint32_t)wdt), ty = L.sy[lo] + (int)q;
-  tile = (uint32_t)ty * (uint32_t)grid_w + (uint32_t)tx;
-  return tile_reached(L.su[lo], L.sv[lo], L.sa[lo], L.sb[lo], L.sc[lo], L.cut[lo], tx, ty, T);
+  j = (int)lo;
+  ty = L.y0[lo] + (int)(k - L.roff[lo]);
 }
 
-// kept copies per emission partition (the culled emit_sums)
-__global__ __launch_bounds__(BS) void emit_sums_culled(uint32_t n, const uint32_t *__restrict__ tiles,
-                                                       const uint32_t *__restrict__ perm, const int32_t *__restrict__ rect,
-                                                       Cull cu, int grid_w, uint64_t *__restrict__ esum) {
+// The tile test: whether the least Q over the pixel-centre rectangle of
+// tile (tx, ty) is at most cut. Zero when the mean is inside; otherwise the
+// least value over the four edges, where Q restricted to an edge is a
+// quadratic minimised at its vertex clamped to the edge, written as a
+// completed square (two non-negative terms, no cancellation):
+//   along dy = y: Q = a (dx - xs)^2 + (det / a) y^2, xs = -(b / a) y;
+//   along dx = x: Q = c (dy - ys)^2 + (det / c) x^2, ys = -(b / c) x.
+// Its relative error is a few ulps of double, so only minima within ~1e-15
+// of cut can be decided differently by another double evaluation.
+__device__ inline bool tile_kept(const CullLds &L, int j, int tx, int ty, int T) {
+#pragma clang fp contract(off)
+  const double u = L.u[j], v = L.v[j];
+  const double x0 = ((double)(tx * T) + 0.5) - u, x1 = ((double)(tx * T + T) - 0.5) - u;
+  const double y0 = ((double)(ty * T) + 0.5) - v, y1 = ((double)(ty * T + T) - 0.5) - v;
+  if (x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0) return true;
+  const double A = L.A[j], C = L.C[j], bA = L.bA[j], bC = L.bC[j], dA = L.dA[j], dC = L.dC[j], cut = L.cut[j];
+  double q = cut + 1.0;
+  const double ya[2] = {y0, y1}, xa[2] = {x0, x1};
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const double y = ya[e], xs = -(bA * y);
+    const double dx = fmin(fmax(xs, x0), x1) - xs;
+    q = fmin(q, A * (dx * dx) + dA * (y * y));
+    const double x = xa[e], ys = -(bC * x);
+    const double dy = fmin(fmax(ys, y0), y1) - ys;
+    q = fmin(q, C * (dy * dy) + dC * (x * x));
+  }
+  return q <= cut;
+}
+
+// The kept tiles of row ty of splat j, [a, b] (a > b: none). The region
+// Q <= cut is convex, so its tiles in a row are contiguous: the row's strip
+// of pixel-centre offsets meets the ellipse in an x-interval, found in
+// closed form (the ellipse's right side x_r(y) = -(b/a) y +
+// sqrt((cut - (det/a) y^2) / a) is concave with its apex at y = -(b/c) X, so
+// its largest value over the strip is at that apex clamped to the strip;
+// the left side likewise), widened by 1e-3 px + 1e-6 (X + Y) so that it
+// holds every tile the test can keep. From both ends of that candidate
+// range tiles are put to the test until one is kept; those between are kept
+// untested (they hold points of the ellipse's interior). Only ties within
+// rounding of cut on two or more tiles of one row could make a per-tile
+// evaluation differ.
+__device__ inline void row_span(const CullLds &L, int j, int ty, int T, int &a, int &b) {
+#pragma clang fp contract(off)
+  a = 1;
+  b = 0;
+  const double v = L.v[j], X = L.X[j], Y = L.Y[j], cut = L.cut[j];
+  const double y0 = ((double)(ty * T) + 0.5) - v, y1 = ((double)(ty * T + T) - 0.5) - v;
+  const double m = 1e-3 + 1e-6 * (X + Y);
+  if (y0 > Y + m || y1 < -Y - m) return;
+  double lo = fmax(y0, -Y), hi = fmin(y1, Y);
+  if (lo > hi) lo = hi = (y0 > 0.0 ? Y : -Y);  // the strip passes within m of a tip
+  const double bA = L.bA[j], dA = L.dA[j], iA = L.iA[j];
+  const double yr = -(L.bC[j] * X);           // apex of the right side; the left one's is at -yr
+  const double ya = fmin(fmax(yr, lo), hi), yb = fmin(fmax(-yr, lo), hi);
+  const double ra = cut - dA * (ya * ya), rb = cut - dA * (yb * yb);
+  const double u = L.u[j];
+  const double xmax = -(bA * ya) + (ra > 0.0 ? sqrt(ra * iA) : 0.0) + m;
+  const double xmin = -(bA * yb) - (rb > 0.0 ? sqrt(rb * iA) : 0.0) - m;
+  // tiles whose pixel-centre span [T tx + 0.5 - u, T tx + T - 0.5 - u] meets [xmin, xmax]
+  const double ca = fmax(ceil(((xmin + u) - ((double)T - 0.5)) / (double)T), (double)L.x0[j]);
+  const double cb = fmin(floor(((xmax + u) - 0.5) / (double)T), (double)L.x1[j]);
+  if (!(ca <= cb)) return;
+  int ia = (int)ca, ib = (int)cb;
+  while (ia <= ib && !tile_kept(L, j, ia, ty, T)) ++ia;
+  if (ia > ib) return;
+  while (ib > ia && !tile_kept(L, j, ib, ty, T)) --ib;
+  a = ia;
+  b = ib;
+}
+
+// kept copies per workgroup of BS emission positions (esum)
+__global__ __launch_bounds__(BS) void cull_count(uint32_t n, const uint32_t *__restrict__ perm,
+                                                 const uint32_t *__restrict__ tiles, const int32_t *__restrict__ rect,
+                                                 Cull cu, uint64_t *__restrict__ esum) {
   __shared__ CullLds L;
-  const uint32_t T = cull_stage(n, perm, tiles, rect, nullptr, cu, L);
+  const uint32_t R = cull_stage(n, perm, tiles, rect, nullptr, cu, L);
   uint64_t kept = 0;
-  for (uint32_t k = threadIdx.x; k < T; k += BS) {
-    uint32_t tile, lo;
-    kept += cull_copy(k, L, grid_w, cu.tile, tile, lo) ? 1u : 0u;
+  for (uint32_t k = threadIdx.x; k < R; k += BS) {
+    int j, ty, a, b;
+    row_item(L, k, j, ty);
+    row_span(L, j, ty, cu.tile, a, b);
+    if (a <= b) kept += (uint64_t)(b - a + 1);
   }
   uint64_t total;
   block_exclusive<uint64_t>(kept, total);
   if (threadIdx.x == 0) esum[blockIdx.x] = total;
 }
 
-// the kept copies of a partition, in emission order (box copies walked BS at
-// a time, the kept ones compacted by a workgroup scan), counting the tile
-// digits as they are written; as emit_copies otherwise
-__global__ __launch_bounds__(BS) void emit_copies_culled(Emit a, Cull cu) {
+// esum -> exclusive prefix in place (one workgroup); K, overflow and the key
+// counter from the total
+__global__ __launch_bounds__(BS) void cull_scan(uint64_t *__restrict__ esum, uint32_t parts, uint64_t capacity,
+                                                uint32_t *__restrict__ ctr, int64_t *num_keys, int32_t *overflow) {
+  uint64_t carry = 0;
+  for (uint32_t base = 0; base < parts; base += BS) {
+    const uint32_t i = base + threadIdx.x;
+    const uint64_t v = i < parts ? esum[i] : 0u;
+    uint64_t chunk;
+    const uint64_t off = block_exclusive<uint64_t>(v, chunk);
+    if (i < parts) esum[i] = carry + off;
+    carry += chunk;
+  }
+  if (threadIdx.x == 0) {
+    const bool over = carry > capacity;
+    *num_keys = (int64_t)carry;
+    *overflow = over ? 1 : 0;
+    ctr[CTR_KEYS] = over ? 0u : (uint32_t)carry;
+  }
+}
+
+// The kept copies of the workgroup's splats, in emission order (splats in
+// order, each one's tiles row-major): row items BS at a time, each writing
+// its row's run of tiles at the place a workgroup scan of the runs' lengths
+// gives it; nothing when the call overflows. Counts the tile digits.
+__global__ __launch_bounds__(BS) void cull_emit(Emit a, Cull cu) {
   __shared__ CullLds L;
   __shared__ uint32_t th[MAX_TILE_PASSES * RADIX];
-  const uint32_t nparts = (uint32_t)(((uint64_t)a.n + EPART - 1) / EPART);
-  const uint32_t part = blockIdx.x;
   for (int j = threadIdx.x; j < MAX_TILE_PASSES * RADIX; j += BS) th[j] = 0u;
-  uint64_t part_sum = 0, pre;
-  for (uint32_t q = threadIdx.x; q < part; q += BS) part_sum += a.esum[q];
-  block_exclusive<uint64_t>(part_sum, pre);
-  const uint64_t mine = a.esum[part];
-  if (threadIdx.x == 0 && part == nparts - 1) {
-    const uint64_t K = pre + mine;
-    const bool over = K > a.capacity;
-    *a.num_keys = (int64_t)K;
-    *a.overflow = over ? 1 : 0;
-    a.ctr[CTR_KEYS] = over ? 0u : (uint32_t)K;
-  }
-  const uint32_t T = cull_stage(a.n, a.perm, a.tiles, a.rect, a.depth, cu, L);
-  if (pre + mine > a.capacity || mine == 0) return;  // an overflowing call writes no key
+  const uint32_t R = cull_stage(a.n, a.perm, a.tiles, a.rect, a.depth, cu, L);  // orders th's reset too
+  if (*a.overflow) return;  // uniform: written before this launch
   const uint32_t dmask = (1u << a.tile_bits) - 1u;
-  uint64_t carry = pre;
-  for (uint32_t base = 0; base < T; base += BS) {  // uniform trip count
+  uint64_t carry = a.esum[blockIdx.x];
+  for (uint32_t base = 0; base < R; base += BS) {  // uniform trip count
     const uint32_t k = base + threadIdx.x;
-    uint32_t tile = 0, lo = 0;
-    const bool keep = k < T && cull_copy(k, L, a.grid_w, cu.tile, tile, lo);
+    int j = 0, ty = 0, ta = 1, tb = 0;
+    if (k < R) {
+      row_item(L, k, j, ty);
+      row_span(L, j, ty, cu.tile, ta, tb);
+    }
     uint32_t chunk;
-    const uint32_t at = block_exclusive<uint32_t>(keep ? 1u : 0u, chunk);
-    if (keep && carry + at < pre + mine) {  // both kernels take the same decisions; the bound only guards the writes
-      const uint64_t pos = carry + at;
-      a.tkey[pos] = tile;
-      a.tval[pos] = L.ssp[lo];
-      a.tbits[pos] = L.sbits[lo];
+    uint64_t o = carry + block_exclusive<uint32_t>(ta <= tb ? (uint32_t)(tb - ta + 1) : 0u, chunk);
+    // both kernels take the same decisions; the bound only guards the writes
+    for (int tx = ta; tx <= tb && o < a.capacity; ++tx, ++o) {
+      const uint32_t tile = (uint32_t)ty * (uint32_t)a.grid_w + (uint32_t)tx;
+      a.tkey[o] = tile;
+      a.tval[o] = L.sp[j];
+      a.tbits[o] = L.bits[j];
       for (int p = 0; p < a.tile_passes; ++p) atomicAdd(&th[p * RADIX + ((tile >> (p * a.tile_bits)) & dmask)], 1u);
     }
     carry += chunk;
@@ -1169,7 +1220,7 @@ size_t carve(void *base, int64_t n, int64_t cap, int64_t ntiles, Workspace *w) {
     return r;
   };
   Workspace t;
-  t.esum = (uint64_t *)take(8 * (size_t)ceil_div((int64_t)N, EPART));
+  t.esum = (uint64_t *)take(8 * (size_t)ceil_div((int64_t)N, BS));  // per BS splats (culled route), else per EPART
   for (int b = 0; b < 2; ++b) {
     t.tk[b] = (uint32_t *)take(4 * C);
     t.tv[b] = (uint32_t *)take(4 * C);
@@ -1268,13 +1319,15 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
   }
   if (n > 0) {
     // 1. copies (in splat-index or depth order) with their depth bits, the tile digit totals, K
-    const unsigned egrid = ceil_div(n, EPART);
-    if (cu)
-      hipLaunchKernelGGL(emit_sums_culled, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, tiles, perm, rect, *cu, grid_w,
-                         w.esum);
-    else
+    const unsigned egrid = ceil_div(n, EPART), cgrid = ceil_div(n, BS);
+    if (cu) {
+      hipLaunchKernelGGL(cull_count, dim3(cgrid), dim3(BS), 0, s, (uint32_t)n, perm, tiles, rect, *cu, w.esum);
+      hipLaunchKernelGGL(cull_scan, dim3(1), dim3(BS), 0, s, w.esum, cgrid, (uint64_t)capacity, w.ctr, num_keys,
+                         overflow);
+    } else {
       hipLaunchKernelGGL(emit_sums, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, tiles, perm, w.esum,
                          presort ? (uint4 *)nullptr : (uint4 *)w.zero_begin, nz16, ranges, nr, num_keys, overflow);
+    }
     Emit e{};
     e.n = (uint32_t)n;
     e.perm = perm;
@@ -1294,7 +1347,7 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
     e.num_keys = num_keys;
     e.overflow = overflow;
     if (cu)
-      hipLaunchKernelGGL(emit_copies_culled, dim3(egrid), dim3(BS), 0, s, e, *cu);
+      hipLaunchKernelGGL(cull_emit, dim3(cgrid), dim3(BS), 0, s, e, *cu);
     else
       hipLaunchKernelGGL(emit_copies, dim3(egrid), dim3(BS), 0, s, e);
   }

@@ -451,8 +451,7 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
 // ---------------------------------------------------------------------------
 struct Cull {
   const float *means2d, *conic_opacity;  // the projected records
-  BlendParams p;                         // kernel and eps, for cull_cut
-  int tile;                              // tile edge in pixels
+  BlendParams p;                         // kernel and eps, for cull_cut (tiles are TS pixels wide)
 };
 
 // One workgroup of the culled binning takes BS splats (in emission order)
@@ -487,19 +486,20 @@ __device__ inline uint32_t cull_stage(uint32_t n, const uint32_t *perm, const ui
       const double cut = cull_cut(cu.p, co.w, co.x, co.y, co.z);
       if (cut >= 0.0 && r.z >= r.x && r.w >= r.y) {
         const double A = co.x, B = co.y, C = co.z, det = A * C - B * B;
+        const double iA = 1.0 / A, iC = 1.0 / C, cd = cut / det;
         rows = (uint32_t)(r.w - r.y + 1);
         L.u[j] = m.x;
         L.v[j] = m.y;
         L.A[j] = co.x;
         L.C[j] = co.z;
-        L.iA[j] = 1.0 / A;
-        L.bA[j] = B / A;
-        L.bC[j] = B / C;
-        L.dA[j] = det / A;
-        L.dC[j] = det / C;
+        L.iA[j] = iA;
+        L.bA[j] = B * iA;
+        L.bC[j] = B * iC;
+        L.dA[j] = det * iA;
+        L.dC[j] = det * iC;
         L.cut[j] = cut;
-        L.X[j] = sqrt(cut * C / det);
-        L.Y[j] = sqrt(cut * A / det);
+        L.X[j] = sqrt(cd * C);
+        L.Y[j] = sqrt(cd * A);
         L.x0[j] = r.x;
         L.x1[j] = r.z;
         L.y0[j] = r.y;
@@ -536,8 +536,9 @@ __device__ inline void row_item(const CullLds &L, uint32_t k, int &j, int &ty) {
 //   along dx = x: Q = c (dy - ys)^2 + (det / c) x^2, ys = -(b / c) x.
 // Its relative error is a few ulps of double, so only minima within ~1e-15
 // of cut can be decided differently by another double evaluation.
-__device__ inline bool tile_kept(const CullLds &L, int j, int tx, int ty, int T) {
+__device__ inline bool tile_kept(const CullLds &L, int j, int tx, int ty) {
 #pragma clang fp contract(off)
+  constexpr int T = TS;
   const double u = L.u[j], v = L.v[j];
   const double x0 = ((double)(tx * T) + 0.5) - u, x1 = ((double)(tx * T + T) - 0.5) - u;
   const double y0 = ((double)(ty * T) + 0.5) - v, y1 = ((double)(ty * T + T) - 0.5) - v;
@@ -569,8 +570,9 @@ __device__ inline bool tile_kept(const CullLds &L, int j, int tx, int ty, int T)
 // untested (they hold points of the ellipse's interior). Only ties within
 // rounding of cut on two or more tiles of one row could make a per-tile
 // evaluation differ.
-__device__ inline void row_span(const CullLds &L, int j, int ty, int T, int &a, int &b) {
+__device__ inline void row_span(const CullLds &L, int j, int ty, int &a, int &b) {
 #pragma clang fp contract(off)
+  constexpr int T = TS;
   a = 1;
   b = 0;
   const double v = L.v[j], X = L.X[j], Y = L.Y[j], cut = L.cut[j];
@@ -587,13 +589,13 @@ __device__ inline void row_span(const CullLds &L, int j, int ty, int T, int &a, 
   const double xmax = -(bA * ya) + (ra > 0.0 ? sqrt(ra * iA) : 0.0) + m;
   const double xmin = -(bA * yb) - (rb > 0.0 ? sqrt(rb * iA) : 0.0) - m;
   // tiles whose pixel-centre span [T tx + 0.5 - u, T tx + T - 0.5 - u] meets [xmin, xmax]
-  const double ca = fmax(ceil(((xmin + u) - ((double)T - 0.5)) / (double)T), (double)L.x0[j]);
-  const double cb = fmin(floor(((xmax + u) - 0.5) / (double)T), (double)L.x1[j]);
+  const double ca = fmax(ceil(((xmin + u) - ((double)T - 0.5)) * (1.0 / T)), (double)L.x0[j]);
+  const double cb = fmin(floor(((xmax + u) - 0.5) * (1.0 / T)), (double)L.x1[j]);
   if (!(ca <= cb)) return;
   int ia = (int)ca, ib = (int)cb;
-  while (ia <= ib && !tile_kept(L, j, ia, ty, T)) ++ia;
+  while (ia <= ib && !tile_kept(L, j, ia, ty)) ++ia;
   if (ia > ib) return;
-  while (ib > ia && !tile_kept(L, j, ib, ty, T)) --ib;
+  while (ib > ia && !tile_kept(L, j, ib, ty)) --ib;
   a = ia;
   b = ib;
 }
@@ -608,7 +610,7 @@ __global__ __launch_bounds__(BS) void cull_count(uint32_t n, const uint32_t *__r
   for (uint32_t k = threadIdx.x; k < R; k += BS) {
     int j, ty, a, b;
     row_item(L, k, j, ty);
-    row_span(L, j, ty, cu.tile, a, b);
+    row_span(L, j, ty, a, b);
     if (a <= b) kept += (uint64_t)(b - a + 1);
   }
   uint64_t total;
@@ -616,24 +618,26 @@ __global__ __launch_bounds__(BS) void cull_count(uint32_t n, const uint32_t *__r
   if (threadIdx.x == 0) esum[blockIdx.x] = total;
 }
 
-// esum -> exclusive prefix in place (one workgroup); K, overflow and the key
+// esum -> exclusive prefix in place (one workgroup, each thread a contiguous
+// chunk: its loads are independent and overlap); K, overflow and the key
 // counter from the total
 __global__ __launch_bounds__(BS) void cull_scan(uint64_t *__restrict__ esum, uint32_t parts, uint64_t capacity,
                                                 uint32_t *__restrict__ ctr, int64_t *num_keys, int32_t *overflow) {
-  uint64_t carry = 0;
-  for (uint32_t base = 0; base < parts; base += BS) {
-    const uint32_t i = base + threadIdx.x;
-    const uint64_t v = i < parts ? esum[i] : 0u;
-    uint64_t chunk;
-    const uint64_t off = block_exclusive<uint64_t>(v, chunk);
-    if (i < parts) esum[i] = carry + off;
-    carry += chunk;
+  const uint32_t per = (parts + BS - 1) / BS, b = threadIdx.x * per, e = b + per < parts ? b + per : parts;
+  uint64_t sum = 0;
+  for (uint32_t i = b; i < e; ++i) sum += esum[i];
+  uint64_t total;
+  uint64_t off = block_exclusive<uint64_t>(sum, total);
+  for (uint32_t i = b; i < e; ++i) {
+    const uint64_t v = esum[i];
+    esum[i] = off;
+    off += v;
   }
   if (threadIdx.x == 0) {
-    const bool over = carry > capacity;
-    *num_keys = (int64_t)carry;
+    const bool over = total > capacity;
+    *num_keys = (int64_t)total;
     *overflow = over ? 1 : 0;
-    ctr[CTR_KEYS] = over ? 0u : (uint32_t)carry;
+    ctr[CTR_KEYS] = over ? 0u : (uint32_t)total;
   }
 }
 
@@ -654,7 +658,7 @@ __global__ __launch_bounds__(BS) void cull_emit(Emit a, Cull cu) {
     int j = 0, ty = 0, ta = 1, tb = 0;
     if (k < R) {
       row_item(L, k, j, ty);
-      row_span(L, j, ty, cu.tile, ta, tb);
+      row_span(L, j, ty, ta, tb);
     }
     uint32_t chunk;
     uint64_t o = carry + block_exclusive<uint32_t>(ta <= tb ? (uint32_t)(tb - ta + 1) : 0u, chunk);
@@ -1424,11 +1428,11 @@ hipError_t launch_binsort(int64_t n, const float *depth, const int32_t *rect, co
 }
 
 hipError_t launch_binsort_culled(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles,
-                                 const float *means2d, const float *conic_opacity, const BlendParams &bp, int tile,
+                                 const float *means2d, const float *conic_opacity, const BlendParams &bp,
                                  int grid_w, int grid_h, int64_t capacity, void *ws, size_t, uint64_t *keys,
                                  uint32_t *vals, uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys,
                                  int32_t *overflow, hipStream_t s) {
-  const Cull cu{means2d, conic_opacity, bp, tile};
+  const Cull cu{means2d, conic_opacity, bp};
   return binsort(n, depth, rect, tiles, grid_w, grid_h, capacity, ws, keys, vals, ranges, tile_order, num_keys,
                  overflow, &cu, s);
 }

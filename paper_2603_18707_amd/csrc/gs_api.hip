@@ -311,7 +311,7 @@ gs_status gs_bin_sort_culled(const gs_kernel *kernel, const gs_params *params, i
       (means2d && !aligned(means2d, 8)) || (conic_opacity && !aligned(conic_opacity, 16)))
     return fail(GS_EINVAL,
                 "workspace needs 256-byte, rect and conic_opacity 16-byte, keys and means2d 8-byte alignment");
-  return check_hip(launch_binsort_culled(n, depth, rect, tiles_touched, means2d, conic_opacity, b, params->tile, grid_w,
+  return check_hip(launch_binsort_culled(n, depth, rect, tiles_touched, means2d, conic_opacity, b, grid_w,
                                          grid_h, key_capacity, workspace, workspace_bytes, keys, vals, ranges,
                                          tile_order, num_keys, overflow, (hipStream_t)stream),
                    "gs_bin_sort_culled launch");

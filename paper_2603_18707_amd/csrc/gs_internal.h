@@ -109,7 +109,7 @@ struct BlendParams {
 // means2d and conic_opacity are the projected records). Needs
 // grid_w * grid_h < 2^22.
 hipError_t launch_binsort_culled(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles,
-                                 const float *means2d, const float *conic_opacity, const BlendParams &bp, int tile,
+                                 const float *means2d, const float *conic_opacity, const BlendParams &bp,
                                  int grid_w, int grid_h, int64_t capacity, void *ws, size_t ws_bytes, uint64_t *keys,
                                  uint32_t *vals, uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys,
                                  int32_t *overflow, hipStream_t s);

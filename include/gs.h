@@ -131,6 +131,17 @@ const char *gs_last_error(void);
  * [0, 2 ln 255] (Sec. 3.1 fitting; Sec. 3.3). */
 gs_status gs_kernel_default(int32_t kind, int32_t order, int32_t radius_mode, gs_kernel *out);
 
+/* App. A: the order-2 polynomial kernel fitted (same L1 objective) over
+ * [0, x_max], x_max = (sqrt(2) p_t / s_min + sqrt(-2 ln eps))^2 = 1992.8 for
+ * 16-px tiles and s_min = sqrt(0.3), the smallest scale the 2-D
+ * anti-aliasing leaves: every quadric value a renderer with exact per-tile
+ * culling (gs_bin_sort_culled) can evaluate, for splats culled at their eps
+ * cut-off. The fit stays monotone over that range, the alternative to the cut
+ * at the first root of Eq. 6; on a range this wide it is all but the
+ * order-1 line, as App. A expects for 16-px tiles. Fills `out` (kind POLY,
+ * order 2, the given radius_mode). */
+gs_status gs_kernel_order2_tile_range(int32_t radius_mode, gs_kernel *out);
+
 /* First positive root x_0 of the kernel's polynomial (App. B closed forms:
  * linear, quadratic formula, Cardano), after the checks gs_preprocess makes. */
 gs_status gs_kernel_root(const gs_kernel *kernel, double *x0_out);

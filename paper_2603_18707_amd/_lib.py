@@ -55,7 +55,8 @@ class GsError(RuntimeError):
 
 _lib = None
 
-EXPORTS = ("gs_version", "gs_last_error", "gs_kernel_default", "gs_kernel_root", "gs_params_default",
+EXPORTS = ("gs_version", "gs_last_error", "gs_kernel_default", "gs_kernel_order2_tile_range", "gs_kernel_root",
+           "gs_params_default",
            "gs_preprocess", "gs_bin_sort_workspace", "gs_bin_sort", "gs_bin_sort_culled", "gs_rasterize_fwd", "gs_rasterize_fwd_count",
            "gs_rasterize_bwd", "gs_preprocess_bwd", "gs_batch_layout", "gs_render_batched")
 
@@ -72,6 +73,7 @@ def lib():
         L.gs_version.restype = ctypes.c_char_p
         L.gs_last_error.restype = ctypes.c_char_p
         L.gs_kernel_default.argtypes = [I32, I32, I32, P]
+        L.gs_kernel_order2_tile_range.argtypes = [I32, P]
         L.gs_kernel_root.argtypes = [P, P]
         L.gs_params_default.argtypes = [P]
         L.gs_preprocess.argtypes = [P, P, P, I64] + [P] * 5 + [I32] + [P] * 6 + [P]
@@ -122,6 +124,12 @@ def gs_version() -> str:
 def gs_kernel_default(kind: int, order: int, radius_mode: int) -> GsKernel:
     k = GsKernel()
     _check(lib().gs_kernel_default(kind, order, radius_mode, ctypes.byref(k)))
+    return k
+
+
+def gs_kernel_order2_tile_range(radius_mode: int) -> GsKernel:
+    k = GsKernel()
+    _check(lib().gs_kernel_order2_tile_range(radius_mode, ctypes.byref(k)))
     return k
 
 

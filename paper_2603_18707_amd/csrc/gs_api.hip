@@ -168,6 +168,17 @@ gs_status gs_kernel_default(int32_t kind, int32_t order, int32_t radius_mode, gs
   return resolve_kernel(out, &r);
 }
 
+gs_status gs_kernel_order2_tile_range(int32_t radius_mode, gs_kernel *out) {
+  if (!out) return fail(GS_EINVAL, "out is NULL");
+  std::memset(out, 0, sizeof(*out));
+  out->kind = GS_KERNEL_POLY;
+  out->order = 2;
+  out->radius_mode = radius_mode;
+  for (int i = 0; i < 4; ++i) out->coeffs[i] = GS_FIT_ORDER2_TILE16[i];
+  Resolved r;
+  return resolve_kernel(out, &r);
+}
+
 gs_status gs_kernel_root(const gs_kernel *kernel, double *x0_out) {
   if (!x0_out) return fail(GS_EINVAL, "x0_out is NULL");
   Resolved r;

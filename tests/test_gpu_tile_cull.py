@@ -26,11 +26,11 @@ from tests.test_gpu_forward import _check_pixels, _check_projection, _np
 pytestmark = pytest.mark.gpu
 
 
-def _frames(scene, cam, kind, order, radius, params=None, capacity=None):
+def _frames(scene, cam, kind, order, radius, params=None, capacity=None, kern=None):
     """The same frame binned with and without culling (one projection)."""
     print(f"[gpu] cull n={scene.n} {cam.width}x{cam.height} {kind}{order}/{radius}", flush=True)
     params = params or H.gpu_params()
-    kern = H.gpu_kernel(kind, order, radius)
+    kern = kern or H.gpu_kernel(kind, order, radius)
     ds = render.to_device(scene)
     r0 = render.Rasterizer(kern, params, reuse_buffers=False)
     r1 = render.Rasterizer(kern, params, reuse_buffers=False, tile_cull=True)
@@ -242,3 +242,27 @@ def test_heavy_scene_culled():
     nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, gw, gh))
     print(f"K={K} box={int(cnt.sum())} kept={K / cnt.sum():.3f} flagged={nflag} max_err={err:.3g}")
     assert nflag <= 0.01 * pix.shape[0]
+
+
+@pytest.mark.parametrize("radius", ["opacity", "universal"])
+def test_order2_tile_range_fit(radius):
+    """App. A's order-2 fit over every value a tile-culled renderer evaluates
+    (gs_kernel_order2_tile_range): full frame against the oracle with the same
+    coefficients, culled and unculled images equal."""
+    from paper_2603_18707_amd import _lib
+    rm = {"opacity": _lib.RADIUS_POLY_OPACITY, "universal": _lib.RADIUS_POLY_UNIVERSAL}[radius]
+    kern = _lib.gs_kernel_order2_tile_range(rm)
+    scene, cam = scenes.workload_tiny()
+    scene.scales *= 2.0
+    cfg = replace(H.oracle_cfg("poly", 2, radius, rect_mode=1), coeffs=tuple(kern.coeffs))
+    o = ocore.project(scene, cam, cfg)
+    g, g0 = _frames(scene, cam, "poly", 2, radius, params=H.gpu_params(rect_mode=1), kern=kern)
+    exempt = (o["flags"] & ocore.SPLAT_EDGE_NEAR) != 0
+    rec = _check_projection(g["proj"], o, exempt)
+    if not exempt.any():
+        _check_culled_binning(g, rec, cfg, 8, 8)
+    _same_image(g, g0)
+    pix = ocore.all_pixels(128, 128)
+    ores = ocore.render_pixels(rec, replace(cfg, tile_cull=1), pix)
+    nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, 8, 8))
+    assert nflag <= 0.005 * pix.shape[0]

@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-view measurement")
     ap.add_argument("--no-train", action="store_true", help="skip the forward+backward step measurement")
     ap.add_argument("--no-heavy", action="store_true", help="skip the 4M-splat heavy-tailed scene")
+    ap.add_argument("--heavy-only", default=None, metavar="ROW",
+                    help="time only the heavy-tailed scene, all rows ('all') or one row such as "
+                         "'4k_ellipse_box_tile_culled' (for profiling; prints its own JSON object)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -202,7 +205,7 @@ def time_batched(torch, render, scenes, steps, rect):
                       "candidates_ms": {f"{k[0]}x{k[1]}": round(v, 3) for k, v in tuned.items()}}}
 
 
-def time_heavy(torch, render, scenes, steps, rect):
+def time_heavy(torch, render, scenes, steps, rect, only=None):
     """The 4M-splat heavy-tailed scene (Student-t log-scales), one orbit view at
     1920x1080 and one at 3840x2160: poly-1/opacity against exp/3 sigma, in the
     headline's rectangle mode, and at 4K also in the other one."""
@@ -215,6 +218,9 @@ def time_heavy(torch, render, scenes, steps, rect):
                                        ("4k", (3840, 2160, 1), ((rect, False), (other, False), (rect, True)))):
         cam = scenes.orbit_camera(w, h, 2.0 * math.pi * view / 8)
         for mode, cull in modes:
+            key = f"{label}_{'ellipse_box' if mode == 'box' else 'square'}{'_tile_culled' if cull else ''}"
+            if only not in (None, "all", key):
+                continue
             row = {}
             for name, kind, order, radius in (("poly1", "poly", 1, "opacity"), ("exp", "exp", 1, "sigma3")):
                 t = time_config(torch, render, dev, cam, kind, order, radius, steps, 2, 0, mode, cull)
@@ -225,7 +231,7 @@ def time_heavy(torch, render, scenes, steps, rect):
                 del t
                 torch.cuda.empty_cache()
             row["speedup_poly1_vs_exp"] = round(row["exp"]["ms_per_step"] / row["poly1"]["ms_per_step"], 4)
-            out[f"{label}_{'ellipse_box' if mode == 'box' else 'square'}{'_tile_culled' if cull else ''}"] = row
+            out[key] = row
     return out
 
 
@@ -325,6 +331,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.heavy_only:
+        print(json.dumps({"heavy": time_heavy(torch, render, scenes, a.steps, a.rect, a.heavy_only)}), flush=True)
+        return
     scene_np, cam = scenes.workload_scene()
     scene = render.to_device(scene_np)
     W, H = cam.width, cam.height

@@ -121,6 +121,24 @@ def test_device_calls_reject_bad_arguments_on_host():
     _expect(L.GS_EINVAL, L.gs_bin_sort, 10, 256, 256, 256, 4, 4, 100, 256, 10, 256, 256, 256, None, 256, 256)
     _expect(L.GS_EINVAL, L.gs_bin_sort_workspace, 10, 1 << 33, 16)
     _expect(L.GS_EINVAL, L.gs_bin_sort, 10, 256, 256, 256, 0, 4, 100, 256, 1 << 30, 256, 256, 256, None, 256, 256)
+    # culled bin sort: the same checks, plus the records, the kernel and a grid below 2^22 tiles
+    ws = L.gs_bin_sort_workspace(10, 100, 16)
+    good = dict(depth=256, rect=256, tiles=256, m2=256, co=256)
+    def culled(kern=k, par=p, n=10, gw=4, gh=4, ws_bytes=ws, **kw):
+        a = {**good, **kw}
+        return L.gs_bin_sort_culled(kern, par, n, a["depth"], a["rect"], a["tiles"], a["m2"], a["co"], gw, gh, 100,
+                                    256, ws_bytes, 256, 256, 256, None, 256, 256)
+    assert "NULL" in _expect(L.GS_EINVAL, lambda: culled(m2=None))
+    assert "NULL" in _expect(L.GS_EINVAL, lambda: culled(co=None))
+    assert "alignment" in _expect(L.GS_EINVAL, lambda: culled(co=264))
+    assert "workspace" in _expect(L.GS_EINVAL, lambda: culled(ws_bytes=ws - 1))
+    assert "2^22" in _expect(L.GS_EINVAL, lambda: culled(gw=4096, gh=1024))
+    bad_k = L.gs_kernel_default(L.KERNEL_POLY, 1, L.RADIUS_POLY_OPACITY)
+    bad_k.kind = 7
+    _expect(L.GS_EINVAL, lambda: culled(kern=bad_k))
+    p3 = L.gs_params_default()
+    p3.eps = 0.0
+    _expect(L.GS_EINVAL, lambda: culled(par=p3))
     # rasterize: NULL outputs
     _expect(L.GS_EINVAL, L.gs_rasterize_fwd, cam, k, p, 0, None, None, None, None, None, None, None, None, None, None)
     msg = _expect(L.GS_EINVAL, L.gs_rasterize_bwd, cam, k, p, 5, None, None, None, None, 256, None, 256, 256, 256,

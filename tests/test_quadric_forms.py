@@ -1,0 +1,60 @@
+"""Why the blend evaluates the quadric as a completed square, and not as the
+dot product of a pixel's monomials with a splat's coefficient vector (the
+matrix-product form that would put Q on matrix cores, Sec. 5.1's NPU
+argument): on long, thin footprints the expanded terms exceed Q by orders of
+magnitude, and in float32 the dot product misses the 2e-4 pixel bar.
+
+Both forms are evaluated here in float32 (numpy, every step rounded) at every
+pixel centre of the tiles near each footprint's axis, in coordinates
+relative to the tile corner, against Q in FP64 from the same float record.
+"""
+import numpy as np
+
+from oracle import coeffs
+from paper_2603_18707_amd import scenes
+
+T = 16
+f32 = np.float32
+
+
+def _forms(rec, tx, ty, i):
+    u, v = rec["means2d"][i]
+    a, b, c = rec["conic"][i]
+    mx, my = f32(f32(u) - f32(tx * T)), f32(f32(v) - f32(ty * T))
+    px, py = np.meshgrid(np.arange(T, dtype=np.float32) + f32(0.5), np.arange(T, dtype=np.float32) + f32(0.5))
+    # exact, from the float record
+    dx, dy = px.astype(np.float64) - float(mx), py.astype(np.float64) - float(my)
+    q = a * dx * dx + 2 * b * dx * dy + c * dy * dy
+    # dot product of (x^2, xy, y^2, x, y, 1) with the splat's coefficient vector, float32
+    af, bf, cf = f32(a), f32(b), f32(c)
+    vec = [af, f32(2) * bf, cf, f32(-2) * (af * mx + bf * my), f32(-2) * (bf * mx + cf * my),
+           af * mx * mx + f32(2) * bf * mx * my + cf * my * my]
+    mono = [px * px, px * py, py * py, px, py, np.ones_like(px)]
+    qe = np.zeros_like(px)
+    for m, w in zip(mono, vec):
+        qe = (qe + (m * w).astype(np.float32)).astype(np.float32)
+    # completed square c (dy + h dx)^2 + g dx^2 with h = b/c, g = (ac - b^2)/c, float32
+    h, g = f32(bf / cf), f32((float(a) * float(c) - float(b) * float(b)) / float(c))
+    ddx = (px - mx).astype(np.float32)
+    e = ((py - my).astype(np.float32) + (h * ddx).astype(np.float32)).astype(np.float32)
+    qc = ((cf * e).astype(np.float32) * e + (g * ddx).astype(np.float32) * ddx).astype(np.float32)
+    return q, qe.astype(np.float64), qc.astype(np.float64)
+
+
+def test_expanded_quadric_misses_the_bar_on_thin_footprints():
+    W, H = 320, 256
+    rec = scenes.thin_footprint_records(W, H, n=12, seed=7)
+    slope = abs(coeffs.PAPER_F1[1])  # |d alpha / dQ| of f1 at opacity 1
+    err_e = err_c = 0.0
+    for i in range(rec["opac"].shape[0]):
+        for tx in range(W // T):
+            for ty in range(H // T):
+                q, qe, qc = _forms(rec, tx, ty, i)
+                near = q <= 4.386  # where f1 is non-zero
+                if not near.any():
+                    continue
+                err_e = max(err_e, float(np.abs(qe - q)[near].max()) * slope)
+                err_c = max(err_c, float(np.abs(qc - q)[near].max()) * slope)
+    # the alpha error the float quadric alone causes, o' = 1
+    assert err_e > 2e-4, err_e
+    assert err_c < 1e-5, err_c

@@ -225,10 +225,11 @@ gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const 
  * pixel-centre rectangle [16 tx + 0.5, 16 tx + 15.5] x [16 ty + 0.5,
  * 16 ty + 15.5] where the splat contributes most, the minimum of
  * Q = d^T conic d over that rectangle (d = point - mean2d), has
- * Q <= cut(o, conic). cut is the largest Q at which gs_rasterize_fwd can
+ * Q <= cut(o, conic), evaluated in double (a minimum within double rounding
+ * of cut may be decided either way). cut is the largest Q at which gs_rasterize_fwd can
  * include a pixel of the splat: the double threshold of alpha >= eps for the
- * kernel, widened by bounds on the blend's float rounding (relative 2^-16 on
- * the threshold plus 16 px, then 2^-19 times the rounding terms of its
+ * kernel, widened by bounds on the blend's float rounding (2^-16 (|thr| + 16)
+ * on the threshold thr, then 2^-19 times the rounding terms of its
  * tile-local evaluation; the formula is in the implementation). Splats whose
  * conic is not positive definite, or whose opacity reaches eps nowhere, get
  * no copy. Every pixel the blend includes lies in a kept tile, so images,

@@ -1,7 +1,8 @@
 """Frame-level driver over the C ABI: buffers, key capacity and the three stages.
 
 PyTorch supplies device memory and the stream; every stage is one of libgs's
-HIP entry points (gs_preprocess -> gs_bin_sort -> gs_rasterize_fwd).
+HIP entry points (gs_preprocess -> gs_bin_sort, or gs_bin_sort_culled with
+per-tile culling -> gs_rasterize_fwd).
 """
 from dataclasses import dataclass
 

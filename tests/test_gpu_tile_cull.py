@@ -266,3 +266,28 @@ def test_order2_tile_range_fit(radius):
     ores = ocore.render_pixels(rec, replace(cfg, tile_cull=1), pix)
     nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, 8, 8))
     assert nflag <= 0.005 * pix.shape[0]
+
+
+@pytest.mark.parametrize("size", [(37, 23), (1, 1), (17, 200), (300, 40)])
+def test_ragged_image_sizes_culled(size):
+    """Partial tiles at the right and bottom edges (the test uses the whole
+    tile's pixel-centre rectangle, inside the image or not) and splats far
+    larger than the image."""
+    W, Hh = size
+    cam = scenes.tiny_camera(W, Hh)
+    scene, _ = scenes.workload_tiny()
+    scene.scales *= 4.0
+    cfg = H.oracle_cfg("exp", 1, "sigma3", rect_mode=1)
+    o = ocore.project(scene, cam, cfg)
+    g, g0 = _frames(scene, cam, "exp", 1, "sigma3", params=H.gpu_params(rect_mode=1))
+    exempt = (o["flags"] & ocore.SPLAT_EDGE_NEAR) != 0
+    rec = _check_projection(g["proj"], o, exempt)
+    gx, gy = (W + 15) // 16, (Hh + 15) // 16
+    if not exempt.any():
+        _check_culled_binning(g, rec, cfg, gx, gy)
+    for k in ("image", "final_T", "n_contrib"):
+        assert torch.equal(g[k], g0[k]), k
+    pix = ocore.all_pixels(W, Hh)
+    ores = ocore.render_pixels(rec, replace(cfg, tile_cull=1), pix)
+    nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, gx, gy))
+    assert nflag <= max(2, 0.005 * pix.shape[0])

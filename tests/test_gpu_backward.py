@@ -43,8 +43,11 @@ def _compare(name, g, ref):
     assert not bad.any(), (name, np.nonzero(bad)[0][:5], g[bad][:5], ref[bad][:5])
 
 
-@pytest.mark.parametrize("kind,order,radius,scale_mul", CASES)
-def test_scene_gradients_match_reference(kind, order, radius, scale_mul):
+@pytest.mark.parametrize("kind,order,radius,scale_mul,cull", [c + (False,) for c in CASES] +
+                         [("poly", 1, "opacity", 4.0, True), ("exp", 1, "sigma3", 4.0, True)])
+def test_scene_gradients_match_reference(kind, order, radius, scale_mul, cull):
+    """cull: the frame is binned with per-tile culling (gs_bin_sort_culled);
+    the backward walks the culled lists and must give the same gradients."""
     scene, cam = _scene(scale_mul)
     cfg = H.oracle_cfg(kind, order, radius)
     # pixels holding a decision within single-precision reach of a threshold get zero weight,
@@ -62,8 +65,10 @@ def test_scene_gradients_match_reference(kind, order, radius, scale_mul):
     print(f"[gpu] backward {kind}{order}/{radius} x{scale_mul}", flush=True)
     dev = {k: torch.tensor(np.asarray(getattr(scene, k), np.float32), device="cuda", requires_grad=True)
            for k in ("means3d", "scales", "quats", "opacities", "sh")}
+    kern, params = H.gpu_kernel(kind, order, radius), H.gpu_params()
+    rast = render.Rasterizer(kern, params, reuse_buffers=False, tile_cull=True) if cull else None
     gimg = autograd.render(dev["means3d"], dev["scales"], dev["quats"], dev["opacities"], dev["sh"], scene.sh_degree,
-                           cam, H.gpu_kernel(kind, order, radius), H.gpu_params())
+                           cam, kern, params, rasterizer=rast)
     assert np.abs(gimg.detach().cpu().numpy() - ref["image"]).max() < 2e-4
     (gimg * torch.as_tensor(w, dtype=torch.float32, device="cuda")).sum().backward()
     torch.cuda.synchronize()

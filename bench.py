@@ -375,6 +375,7 @@ def main():
                    "rect": RECT_NAMES[a.rect], "blend_threads": head["threads"]},
         "splat_pixel_evals_per_s": round(evals, 1),
         "keys": head["K"], "evals": head["E"], "list_entries": head["E_list"], "blended": head["B"],
+        "scheduled_pairs_bound": head["K"] * 256,
         "stage_ms": {"preprocess": round(head["stage_ms"][0], 4), "bin_sort": round(head["stage_ms"][1], 4),
                      "blend": round(head["stage_ms"][2], 4)},
         "roofline": {"bound": "alu", "kernel": "blend_fwd<poly1>", "achieved": round(achieved, 3),

@@ -40,7 +40,7 @@ OPS_EVAL = {"poly1": 10, "exp": 11, "poly2": 12, "poly3": 13}
 OPS_BLEND = 7
 # MI355X vector ALU issue peak without packed FP32: 256 CUs x 4 SIMDs x 16
 # lanes x 2.4 GHz = 39.3e12 lane-ops/s (the 157.3 TFLOP/s FP32 figure counts
-# packed FMA as 4 flops; packed FP32 is disabled in this build).
+# packed FMA as 4 flops; the library is compiled with packed FP32 disabled).
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
@@ -315,7 +315,7 @@ def cpu_baseline(scene_np, cam, gpu_image, target_s, rect_mode):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import torch
 
@@ -337,11 +337,11 @@ def main():
     scene_np, cam = scenes.workload_scene()
     scene = render.to_device(scene_np)
     W, H = cam.width, cam.height
-    configs = [("poly1", "poly", 1, "opacity"), ("exp", "exp", 1, "sigma3")]
+    kernels = [("poly1", "poly", 1, "opacity"), ("exp", "exp", 1, "sigma3")]
     if a.only:
-        configs = [c for c in configs if c[0] == a.only]
+        kernels = [c for c in kernels if c[0] == a.only]
     res = {}
-    for name, kind, order, radius in configs:
+    for name, kind, order, radius in kernels:
         res[name] = time_config(torch, render, scene, cam, kind, order, radius, a.steps, a.warmup, a.blend_threads,
                                 a.rect)
         r = res[name]
@@ -349,11 +349,11 @@ def main():
               f" blend {r['stage_ms'][2]:.3f}) K={r['K']} E={r['E']} threads={r['threads']} tuned={r['tuned']}",
               file=sys.stderr, flush=True)
 
-    head = res[configs[0][0]]
+    head = res[kernels[0][0]]
     ms = head["ms"]
     mpix = W * H / (ms * 1e-3) / 1e6
     evals = head["E"] / (ms * 1e-3)
-    hname = configs[0][0]
+    hname = kernels[0][0]
     ops = head["E"] * OPS_EVAL[hname] + head["B"] * OPS_BLEND
     achieved = ops / (head["blend_ms"] * 1e-3) / 1e12
 
@@ -394,7 +394,7 @@ def main():
     if not a.only:
         other = "square" if a.rect == "box" else "box"
         alt = {"rect": RECT_NAMES[other]}
-        for name, kind, order, radius in configs:
+        for name, kind, order, radius in kernels:
             t = time_config(torch, render, scene, cam, kind, order, radius, a.steps, a.warmup, a.blend_threads, other)
             print(f"[bench] {name} ({other}): {t['ms']:.3f} ms/frame (pre {t['stage_ms'][0]:.3f}, sort "
                   f"{t['stage_ms'][1]:.3f}, blend {t['stage_ms'][2]:.3f}) K={t['K']} E={t['E']}", file=sys.stderr,
@@ -408,7 +408,7 @@ def main():
         out["other_rect"] = alt
         # the same frames binned with per-tile culling (identical images, shorter lists)
         tc = {"rect": RECT_NAMES[a.rect], "binning": "gs_bin_sort_culled"}
-        for name, kind, order, radius in configs:
+        for name, kind, order, radius in kernels:
             t = time_config(torch, render, scene, cam, kind, order, radius, a.steps, a.warmup, a.blend_threads, a.rect,
                             cull=True)
             print(f"[bench] {name} ({a.rect}, tile-culled): {t['ms']:.3f} ms/frame (pre {t['stage_ms'][0]:.3f}, sort "

@@ -10,7 +10,7 @@ composite trapezoid quadrature on a fine grid, minimised with Nelder-Mead from
 several starts. (The paper reaches the same optimum by gradient descent on
 samples; an independent implementation of that route lives in the product.)
 
-Readings of the paper (listed in the design doc as well):
+Readings of the paper:
   * Sec. 3.1 prints c_0 ~ -0.176 and c_1 ~ 0.773. Read literally f_1 would grow
     with x and vanish only for x < 0.228, contradicting the same paragraph
     (maximum opacity below one, zero beyond x = 4.386). The labels are taken as

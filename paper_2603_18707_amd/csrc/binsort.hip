@@ -452,7 +452,43 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
 struct Cull {
   const float *means2d, *conic_opacity;  // the projected records
   BlendParams p;                         // kernel and eps, for cull_cut (tiles are TS pixels wide)
+  // each row's kept run [a, b], saved by cull_count for cull_emit: workgroup
+  // g owns rcap slots at seg[g / per_seg] + (g % per_seg) * rcap (buffers the
+  // tile passes use later), 16-bit slots a | b << 8 when the grid is at most
+  // 256 tiles wide, else 32-bit a | b << 16; a workgroup with more rows than
+  // rcap saves none
+  uint32_t *seg[3];
+  uint32_t rcap, per_seg;
+  bool narrow;
 };
+
+struct SpanSlots {
+  void *p;
+  bool narrow;
+  __device__ void put(uint32_t k, int a, int b) const {
+    if (narrow)
+      static_cast<uint16_t *>(p)[k] = (uint16_t)((uint32_t)(a & 0xFF) | ((uint32_t)(b & 0xFF) << 8));
+    else
+      static_cast<uint32_t *>(p)[k] = (uint32_t)a | ((uint32_t)b << 16);
+  }
+  __device__ void get(uint32_t k, int &a, int &b) const {
+    if (narrow) {
+      const uint32_t w = static_cast<const uint16_t *>(p)[k];
+      a = (int)(w & 0xFFu);
+      b = (int)(w >> 8);
+    } else {
+      const uint32_t w = static_cast<const uint32_t *>(p)[k];
+      a = (int)(w & 0xFFFFu);
+      b = (int)(w >> 16);
+    }
+  }
+};
+
+__device__ inline SpanSlots span_slots(const Cull &cu, uint32_t g) {
+  const size_t off = (size_t)(g % cu.per_seg) * cu.rcap;
+  uint32_t *base = cu.seg[g / cu.per_seg];
+  return SpanSlots{cu.narrow ? (void *)(reinterpret_cast<uint16_t *>(base) + off) : (void *)(base + off), cu.narrow};
+}
 
 // One workgroup of the culled binning takes BS splats (in emission order)
 // and walks their rectangle rows, BS rows at a time: rows, not tiles, are
@@ -471,23 +507,32 @@ struct CullLds {
 
 // Stages the workgroup's splats; returns its row items. A splat without
 // tiles, with an empty rectangle or with cut < 0 has no row.
+// Rows are counted from the rectangle alone (a splat with cut < 0 keeps its
+// rows, all empty), so `full` = false stages only what writing saved runs
+// needs (splat, depth bits, first row) and gives the same row items.
 __device__ inline uint32_t cull_stage(uint32_t n, const uint32_t *perm, const uint32_t *tiles, const int32_t *rect,
-                                      const float *depth, const Cull &cu, CullLds &L) {
+                                      const float *depth, const Cull &cu, CullLds &L, bool full = true) {
 #pragma clang fp contract(off)
   const uint64_t pos = (uint64_t)blockIdx.x * BS + threadIdx.x;
   const int j = threadIdx.x;
   uint32_t rows = 0;
   if (pos < n) {
     const uint32_t s = perm ? perm[pos] : (uint32_t)pos;
-    if (tiles[s] != 0u) {
-      const int4 r = reinterpret_cast<const int4 *>(rect)[s];
+    const int4 r = tiles[s] != 0u ? reinterpret_cast<const int4 *>(rect)[s] : make_int4(0, 0, -1, -1);
+    if (r.z >= r.x && r.w >= r.y) {
+      rows = (uint32_t)(r.w - r.y + 1);
+      L.y0[j] = r.y;
+      L.sp[j] = s;
+      L.bits[j] = depth ? __float_as_uint(depth[s]) : 0u;
+      L.cut[j] = -1.0;
+    }
+    if (full && rows) {
       const float2 m = reinterpret_cast<const float2 *>(cu.means2d)[s];
       const float4 co = reinterpret_cast<const float4 *>(cu.conic_opacity)[s];
       const double cut = cull_cut(cu.p, co.w, co.x, co.y, co.z);
-      if (cut >= 0.0 && r.z >= r.x && r.w >= r.y) {
+      if (cut >= 0.0) {
         const double A = co.x, B = co.y, C = co.z, det = A * C - B * B;
         const double iA = 1.0 / A, iC = 1.0 / C, cd = cut / det;
-        rows = (uint32_t)(r.w - r.y + 1);
         L.u[j] = m.x;
         L.v[j] = m.y;
         L.A[j] = co.x;
@@ -502,9 +547,6 @@ __device__ inline uint32_t cull_stage(uint32_t n, const uint32_t *perm, const ui
         L.Y[j] = sqrt(cd * A);
         L.x0[j] = r.x;
         L.x1[j] = r.z;
-        L.y0[j] = r.y;
-        L.sp[j] = s;
-        L.bits[j] = depth ? __float_as_uint(depth[s]) : 0u;
       }
     }
   }
@@ -575,7 +617,9 @@ __device__ inline void row_span(const CullLds &L, int j, int ty, int &a, int &b)
   constexpr int T = TS;
   a = 1;
   b = 0;
-  const double v = L.v[j], X = L.X[j], Y = L.Y[j], cut = L.cut[j];
+  const double cut = L.cut[j];
+  if (!(cut >= 0.0)) return;  // no pixel passes
+  const double v = L.v[j], X = L.X[j], Y = L.Y[j];
   const double y0 = ((double)(ty * T) + 0.5) - v, y1 = ((double)(ty * T + T) - 0.5) - v;
   const double m = 1e-3 + 1e-6 * (X + Y);
   if (y0 > Y + m || y1 < -Y - m) return;
@@ -606,12 +650,20 @@ __global__ __launch_bounds__(BS) void cull_count(uint32_t n, const uint32_t *__r
                                                  Cull cu, uint64_t *__restrict__ esum) {
   __shared__ CullLds L;
   const uint32_t R = cull_stage(n, perm, tiles, rect, nullptr, cu, L);
+  const bool save = R <= cu.rcap;
+  const SpanSlots saved = span_slots(cu, blockIdx.x);
   uint64_t kept = 0;
   for (uint32_t k = threadIdx.x; k < R; k += BS) {
     int j, ty, a, b;
     row_item(L, k, j, ty);
     row_span(L, j, ty, a, b);
-    if (a <= b) kept += (uint64_t)(b - a + 1);
+    if (a <= b) {
+      kept += (uint64_t)(b - a + 1);
+    } else {
+      a = 1;  // one encoding for every empty run
+      b = 0;
+    }
+    if (save) saved.put(k, a, b);  // tile columns < 2^15 (< 2^8 for narrow slots)
   }
   uint64_t total;
   block_exclusive<uint64_t>(kept, total);
@@ -649,8 +701,12 @@ __global__ __launch_bounds__(BS) void cull_emit(Emit a, Cull cu) {
   __shared__ CullLds L;
   __shared__ uint32_t th[MAX_TILE_PASSES * RADIX];
   for (int j = threadIdx.x; j < MAX_TILE_PASSES * RADIX; j += BS) th[j] = 0u;
-  const uint32_t R = cull_stage(a.n, a.perm, a.tiles, a.rect, a.depth, cu, L);  // orders th's reset too
+  // the row items of the rectangles alone first: whether cull_count saved the runs
+  uint32_t R = cull_stage(a.n, a.perm, a.tiles, a.rect, a.depth, cu, L, false);  // orders th's reset too
   if (*a.overflow) return;  // uniform: written before this launch
+  const bool save = R <= cu.rcap;
+  const SpanSlots saved = span_slots(cu, blockIdx.x);
+  if (!save) R = cull_stage(a.n, a.perm, a.tiles, a.rect, a.depth, cu, L);  // recompute the runs
   const uint32_t dmask = (1u << a.tile_bits) - 1u;
   uint64_t carry = a.esum[blockIdx.x];
   for (uint32_t base = 0; base < R; base += BS) {  // uniform trip count
@@ -658,7 +714,11 @@ __global__ __launch_bounds__(BS) void cull_emit(Emit a, Cull cu) {
     int j = 0, ty = 0, ta = 1, tb = 0;
     if (k < R) {
       row_item(L, k, j, ty);
-      row_span(L, j, ty, ta, tb);
+      if (save) {
+        saved.get(k, ta, tb);
+      } else {
+        row_span(L, j, ty, ta, tb);
+      }
     }
     uint32_t chunk;
     uint64_t o = carry + block_exclusive<uint32_t>(ta <= tb ? (uint32_t)(tb - ta + 1) : 0u, chunk);
@@ -1432,7 +1492,21 @@ hipError_t launch_binsort_culled(int64_t n, const float *depth, const int32_t *r
                                  int grid_w, int grid_h, int64_t capacity, void *ws, size_t, uint64_t *keys,
                                  uint32_t *vals, uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys,
                                  int32_t *overflow, hipStream_t s) {
-  const Cull cu{means2d, conic_opacity, bp};
+  Cull cu{means2d, conic_opacity, bp, {nullptr, nullptr, nullptr}, 0u, 1u, grid_w <= 256};
+  {
+    // the second ping-pong buffers of the tile passes are free until the
+    // first pass: three arrays of `capacity` words for the saved runs
+    Workspace w;
+    carve(ws, n, capacity, (int64_t)grid_w * grid_h, &w);
+    const uint64_t groups = n > 0 ? (uint64_t)ceil_div(n, BS) : 1u;
+    const uint64_t per_seg = (groups + 2) / 3;
+    const uint64_t rcap = capacity > 0 ? (uint64_t)capacity * (cu.narrow ? 2u : 1u) / per_seg : 0u;
+    cu.seg[0] = w.tk[1];
+    cu.seg[1] = w.tv[1];
+    cu.seg[2] = w.tb[1];
+    cu.per_seg = (uint32_t)per_seg;
+    cu.rcap = (uint32_t)(rcap < 0xFFFFFFFFull ? rcap : 0xFFFFFFFFull);
+  }
   return binsort(n, depth, rect, tiles, grid_w, grid_h, capacity, ws, keys, vals, ranges, tile_order, num_keys,
                  overflow, &cu, s);
 }

@@ -291,3 +291,30 @@ def test_ragged_image_sizes_culled(size):
     ores = ocore.render_pixels(rec, replace(cfg, tile_cull=1), pix)
     nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, gx, gy))
     assert nflag <= max(2, 0.005 * pix.shape[0])
+
+
+def test_saved_runs_fallback():
+    """Workgroups whose rectangles hold more rows than their share of the
+    space for saved runs recompute the runs in the emission kernel: faint
+    splats (no pixel reaches eps) with whole-grid rectangles add 64 empty rows
+    each beside small visible splats, so the kept copies, and with them the
+    key capacity, stay small."""
+    W = Hh = 1024
+    cam = scenes.tiny_camera(W, Hh)
+    rng = np.random.default_rng(17)
+    n = 4096
+    faint = np.arange(n) % 2 == 1
+    m2 = rng.uniform(8, W - 8, size=(n, 2))
+    tx, ty = (m2[:, 0] // 16).astype(np.int32), (m2[:, 1] // 16).astype(np.int32)
+    rect = np.stack([tx, ty, tx, ty], 1).astype(np.int32)
+    rect[faint] = (0, 0, 63, 63)
+    rec = dict(means2d=m2, conic=np.tile([0.25, 0.0, 0.25], (n, 1)), opac=np.where(faint, 1e-3, 0.5),
+               rgb=rng.uniform(0, 1, (n, 3)), depth32=rng.permutation(np.arange(1, n + 1)).astype(np.float32),
+               rect=rect, flags=np.zeros(n, np.uint8))
+    for k in ("means2d", "conic", "opac", "rgb"):
+        rec[k] = rec[k].astype(np.float32).astype(np.float64)
+    g, g0 = _records_frames(rec, cam, "exp", 1, "sigma3")
+    K, Kbox = _check_culled_binning(g, rec, H.oracle_cfg("exp", 1, "sigma3"), 64, 64)
+    assert 0 < K <= n // 2 and Kbox > 64 * K
+    for k in ("image", "final_T", "n_contrib"):
+        assert torch.equal(g[k], g0[k]), k

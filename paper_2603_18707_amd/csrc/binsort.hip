@@ -506,9 +506,9 @@ struct CullLds {
 };
 
 // Stages the workgroup's splats; returns its row items. A splat without
-// tiles, with an empty rectangle or with cut < 0 has no row.
-// Rows are counted from the rectangle alone (a splat with cut < 0 keeps its
-// rows, all empty), so `full` = false stages only what writing saved runs
+// tiles or with an empty rectangle has no row; otherwise its rows are those
+// of its rectangle (with cut < 0 all of them empty), counted from the
+// rectangle alone, so `full` = false stages only what writing saved runs
 // needs (splat, depth bits, first row) and gives the same row items.
 __device__ inline uint32_t cull_stage(uint32_t n, const uint32_t *perm, const uint32_t *tiles, const int32_t *rect,
                                       const float *depth, const Cull &cu, CullLds &L, bool full = true) {

@@ -214,3 +214,42 @@ def test_copy_mask_binning_agrees_with_tile_lists():
         kb, v = binning.tile_list(rec["rect"], rec["depth32"], t % gw, t // gw, keep=keep)
         lo, hi = ranges[t]
         assert np.array_equal(vals[lo:hi], v) and np.array_equal((keys[lo:hi] & 0xFFFFFFFF).astype(np.uint32), kb)
+
+
+@pytest.mark.parametrize("thin", [False, True])
+def test_kept_tiles_of_a_row_form_one_run_inside_the_strip_extent(thin):
+    """What a row-wise culled binning relies on: in each tile row the kept
+    tiles are contiguous, and they lie in the tiles that meet the ellipse
+    Q <= cut's horizontal extent over the row's strip of pixel centres,
+    widened by 1e-3 px + 1e-6 (X + Y). The extent is taken here from the
+    ellipse's chord at every height of a fine grid over the strip (x =
+    (-b y +- sqrt(b^2 y^2 - a (c y^2 - cut))) / a), not from a closed form."""
+    cfg = H.oracle_cfg("poly", 1, "opacity")
+    rng = np.random.default_rng(23 + thin)
+    rows = 0
+    for _ in range(200):
+        a, b, c = _random_conic(rng, thin)
+        o = float(np.float32(rng.uniform(0.02, 1.0)))
+        cut = core.cull_cut(cfg, o, a, b, c)
+        if cut < 0:
+            continue
+        det = a * c - b * b
+        X, Y = math.sqrt(cut * c / det), math.sqrt(cut * a / det)
+        m = 1e-3 + 1e-6 * (X + Y)
+        u, v = float(np.float32(rng.uniform(0, 800))), float(np.float32(rng.uniform(0, 800)))
+        for ty in range(int((v - Y) // T) - 1, int((v + Y) // T) + 2):
+            tx_lo, tx_hi = int((u - X) // T) - 2, int((u + X) // T) + 2
+            kept = [tx for tx in range(tx_lo, tx_hi + 1) if core.tile_keep(cfg, u, v, a, b, c, cut, tx, ty)[0]]
+            if not kept:
+                continue
+            rows += 1
+            assert kept == list(range(kept[0], kept[-1] + 1)), "kept tiles of a row are one run"
+            y = np.linspace(ty * T + 0.5 - v, ty * T + T - 0.5 - v, 4001)
+            disc = b * b * y * y - a * (c * y * y - cut)
+            y, disc = y[disc >= 0], disc[disc >= 0]
+            assert y.size, "a kept tile's strip meets the ellipse"
+            xl = float(((-b * y - np.sqrt(disc)) / a).min()) - m
+            xr = float(((-b * y + np.sqrt(disc)) / a).max()) + m
+            for tx in kept:  # every kept tile's pixel-centre span meets [xl, xr]
+                assert tx * T + T - 0.5 - u >= xl and tx * T + 0.5 - u <= xr
+    assert rows > 300

@@ -55,7 +55,7 @@ constexpr int DEPTH_PASSES = 4;         // 8-bit digits of a float's bits
 // Average list length from which the splats are sorted by depth before the
 // emission (no per-tile sort): lists this long are sorted by the per-tile
 // kernel in chunks through global memory, at a fraction of the HBM rate.
-constexpr int64_t PRESORT_MIN_AVG = 1024;
+constexpr int64_t PRESORT_MIN_AVG = 2048;
 static_assert(DEPTH_PASSES <= MAX_TILE_PASSES, "the depth totals share the tile totals' layout");
 
 enum : int { CTR_KEYS = 0, CTR_SPLIT = 1, CTR_SLOTS = 16 };

@@ -122,16 +122,16 @@ def test_bin_sort_without_tile_order():
                                               (60_000, 3, 2, 12, 0.0), (5000, 120, 68, 3, 0.003)])
 def test_depth_first_and_per_tile_sorts_agree(n, gw, gh, seed, big):
     """Both routes to the sorted keys, forced by the capacity (a capacity of
-    1024 copies per tile or more sorts the splats by depth before emitting
+    2048 copies per tile or more sorts the splats by depth before emitting
     their copies; a smaller one sorts each tile's list), give the oracle's
     keys, values and ranges."""
     depth, rect, tiles = scenes.binning_inputs(n, gw, gh, seed, big=big)
     keys, vals, ranges = binning.bin_and_sort_fast(rect, depth, gw, gh)
     K = keys.shape[0]
-    small, large = K, max(K, 1024 * gw * gh)
+    small, large = K, max(K, 2048 * gw * gh)
     print(f"[gpu] bin_sort routes n={n} grid={gw}x{gh} K={K} capacities {small} {large}", flush=True)
     outs = []
-    for cap in ((small, large) if K < 1024 * gw * gh else (large,)):
+    for cap in ((small, large) if K < 2048 * gw * gh else (large,)):
         g = _run(depth, rect, tiles, gw, gh, cap)
         assert g["overflow"] == 0 and g["K"] == K
         assert np.array_equal(g["keys"], keys) and np.array_equal(g["vals"], vals)

@@ -146,7 +146,7 @@ def test_scene_scale_culled(kind, order, radius, rect_mode):
 
 
 def test_presort_route_and_overflow_culled():
-    """A capacity of 1024 copies per tile or more takes the depth-first route;
+    """A capacity of 2048 copies per tile or more takes the depth-first route;
     it must give the same lists. A capacity below the kept copies overflows
     with num_keys = the kept count."""
     scene, cam = scenes.workload_tiny()
@@ -156,7 +156,7 @@ def test_presort_route_and_overflow_culled():
     proj = r.preprocess(render.to_device(scene), cam)
     a = r.bin_sort_fit(proj, cam)
     K = int(a["num_keys"].item())
-    big = r.bin_sort(proj, cam, capacity=1024 * 64 + 5)
+    big = r.bin_sort(proj, cam, capacity=2048 * 64 + 5)
     torch.cuda.synchronize()
     assert int(big["overflow"].item()) == 0 and int(big["num_keys"].item()) == K
     assert torch.equal(big["keys"][:K], a["keys"][:K]) and torch.equal(big["vals"][:K], a["vals"][:K])

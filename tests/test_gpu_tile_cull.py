@@ -318,3 +318,23 @@ def test_saved_runs_fallback():
     assert 0 < K <= n // 2 and Kbox > 64 * K
     for k in ("image", "final_T", "n_contrib"):
         assert torch.equal(g[k], g0[k]), k
+
+
+def test_conic_not_positive_definite_gets_no_copy():
+    """Records whose conic is indefinite, singular or NaN, which the blend
+    never includes, get no copy at all from the culled binning; the image is
+    the unculled one."""
+    W, Hh = 320, 256
+    cam = scenes.tiny_camera(W, Hh)
+    rec = scenes.thin_footprint_records(W, Hh)
+    rec["conic"] = rec["conic"].copy()
+    rec["conic"][2] = (1.0, 2.0, 1.0)        # indefinite
+    rec["conic"][5] = (0.5, 0.0, 0.0)        # c = 0
+    rec["conic"][8] = (np.nan, 0.0, 1.0)
+    g, g0 = _records_frames(rec, cam, "poly", 1, "opacity")
+    K, Kbox = _check_culled_binning(g, rec, H.oracle_cfg("poly", 1, "opacity"), 20, 16)
+    b = g["binned"]
+    vals = _np(b["vals"])[:K].view(np.uint32)
+    assert not np.isin(vals, [2, 5, 8]).any()
+    for k in ("image", "final_T", "n_contrib"):
+        assert torch.equal(g[k], g0[k]), k

@@ -338,3 +338,28 @@ def test_conic_not_positive_definite_gets_no_copy():
     assert not np.isin(vals, [2, 5, 8]).any()
     for k in ("image", "final_T", "n_contrib"):
         assert torch.equal(g[k], g0[k]), k
+
+
+@pytest.mark.parametrize("scale", [1.0, 8.0])
+def test_auto_culling_choice(scale):
+    """tile_cull="auto" culls when the rectangles hold at least
+    AUTO_CULL_TILES_PER_SPLAT tiles per visible splat; either way the frame is
+    the unculled one."""
+    scene, cam = scenes.workload_tiny()
+    scene.scales *= scale
+    kern, params = H.gpu_kernel("poly", 1, "opacity"), H.gpu_params()
+    ds = render.to_device(scene)
+    ra = render.Rasterizer(kern, params, reuse_buffers=False, tile_cull="auto")
+    r0 = render.Rasterizer(kern, params, reuse_buffers=False)
+    fa, f0 = ra.render(ds, cam), r0.render(ds, cam)
+    torch.cuda.synchronize()
+    tiles = _np(fa["proj"]["tiles"]).astype(np.int64)
+    want = tiles.sum() >= render.AUTO_CULL_TILES_PER_SPLAT * (tiles > 0).sum()
+    print(f"scale {scale}: {tiles.sum() / max(1, (tiles > 0).sum()):.2f} tiles per splat, culling {ra.culling}")
+    assert ra.culling == want and ra.culling == (scale > 1.0)
+    for k in ("image", "final_T", "n_contrib"):
+        assert torch.equal(fa[k], f0[k]), k
+    Ka, K0 = int(fa["binned"]["num_keys"].item()), int(f0["binned"]["num_keys"].item())
+    assert (Ka < K0) == ra.culling
+    with pytest.raises(ValueError):
+        render.Rasterizer(kern, params, tile_cull="always")

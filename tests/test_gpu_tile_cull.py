@@ -68,7 +68,8 @@ def _check_culled_binning(g, rec, cfg, gx, gy):
 
 @pytest.mark.parametrize("kind,order,radius,rect_mode", [
     ("exp", 1, "sigma3", 0), ("exp", 1, "exp_opacity", 1), ("poly", 1, "opacity", 0), ("poly", 1, "opacity", 1),
-    ("poly", 2, "universal", 1), ("poly", 3, "opacity", 0)])
+    ("poly", 2, "universal", 1), ("poly", 3, "opacity", 0), ("exp", 1, "sigma3", 1), ("exp", 1, "exp_opacity", 0),
+    ("poly", 1, "sigma3", 1), ("poly", 1, "universal", 0), ("poly", 2, "opacity", 0), ("poly", 3, "universal", 1)])
 def test_tiny_culled_full_frame(kind, order, radius, rect_mode):
     scene, cam = scenes.workload_tiny()
     scene.scales *= 2.0  # larger footprints: more tiles to drop

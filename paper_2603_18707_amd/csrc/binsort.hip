@@ -51,6 +51,11 @@ static_assert(BS == RADIX, "per-digit steps give one digit to each thread");
 constexpr int MAX_TILE_PASSES = 4;      // tile ids < 2^30 need at most four digits of <= 8 bits
 constexpr int STRIPES = 8;              // copies of the digit totals
 constexpr int SEG_IPT = 4;              // copies per thread of a workgroup's list sort (1024 in LDS)
+constexpr int LONG_SEG_IPT = 8;         // the same for long lists (2048 in LDS)
+// Average list length (capacity per tile) from which the per-tile sort keeps
+// up to 2048 copies in LDS: fewer lists take the chunked path through global
+// memory, at some cost in registers for the shorter lists
+constexpr int64_t LONG_SEG_MIN_AVG = 512;
 constexpr int DEPTH_PASSES = 4;         // 8-bit digits of a float's bits
 // Average list length from which the splats are sorted by depth before the
 // emission (no per-tile sort): lists this long are sorted by the per-tile
@@ -1196,9 +1201,10 @@ __device__ inline void sort_list_wave(const Seg &a, uint32_t t, uint32_t start, 
 // order every workgroup takes one tile. Either way a list is sorted by the
 // whole workgroup when it is longer than WAVE_MAX, else by one wave; the
 // grid has one workgroup per tile and the spare ones exit.
+template <int IPT>
 __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
   __shared__ union {
-    SortLds<SEG_IPT> sl;
+    SortLds<IPT> sl;
     WaveLds wl[BS / 64];
   } lds;
   constexpr int NQ = BS / 64;
@@ -1232,7 +1238,7 @@ __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
 #pragma unroll
   for (int j = 0; j < NQ; ++j) {  // uniform over the workgroup
     if (nn[j] > WAVE_MAX) {
-      sort_list<SEG_IPT>(a, tt[j], st[j], nn[j], lds.sl);
+      sort_list<IPT>(a, tt[j], st[j], nn[j], lds.sl);
       __syncthreads();  // the LDS is reused
     }
   }
@@ -1469,7 +1475,10 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
     g.keys = keys;
     g.vout = vals;
     g.split = tile_order ? w.ctr + CTR_SPLIT : nullptr;
-    hipLaunchKernelGGL(segment_sort, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
+    if (capacity >= LONG_SEG_MIN_AVG * ntiles)
+      hipLaunchKernelGGL(segment_sort<LONG_SEG_IPT>, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
+    else
+      hipLaunchKernelGGL(segment_sort<SEG_IPT>, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
     return hipGetLastError();
   }
   // nothing emitted (or no room): ranges stay zero

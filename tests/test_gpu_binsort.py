@@ -119,22 +119,52 @@ def test_bin_sort_without_tile_order():
 
 
 @pytest.mark.parametrize("n,gw,gh,seed,big", [(20_000, 4, 4, 11, 0.0), (300_000, 120, 68, 4, 0.003),
-                                              (60_000, 3, 2, 12, 0.0), (5000, 120, 68, 3, 0.003)])
+                                              (60_000, 3, 2, 12, 0.0), (5000, 120, 68, 3, 0.003),
+                                              (20_000, 200, 1, 5, 0.003)])
 def test_depth_first_and_per_tile_sorts_agree(n, gw, gh, seed, big):
     """Both routes to the sorted keys, forced by the capacity (a capacity of
     2048 copies per tile or more sorts the splats by depth before emitting
-    their copies; a smaller one sorts each tile's list), give the oracle's
+    their copies; a smaller one sorts each tile's list, keeping up to 2048
+    copies in LDS from 512 copies per tile, else 1024), give the oracle's
     keys, values and ranges."""
     depth, rect, tiles = scenes.binning_inputs(n, gw, gh, seed, big=big)
     keys, vals, ranges = binning.bin_and_sort_fast(rect, depth, gw, gh)
     K = keys.shape[0]
-    small, large = K, max(K, 2048 * gw * gh)
-    print(f"[gpu] bin_sort routes n={n} grid={gw}x{gh} K={K} capacities {small} {large}", flush=True)
+    T = gw * gh
+    small, mid, large = K, max(K, 512 * T), max(K, 2048 * T)
+    caps = [c for c in (small, mid) if c < 2048 * T] + [large]
+    longest = int((ranges[:, 1] - ranges[:, 0]).max())
+    print(f"[gpu] bin_sort routes n={n} grid={gw}x{gh} K={K} longest list {longest} capacities {caps}", flush=True)
     outs = []
-    for cap in ((small, large) if K < 2048 * gw * gh else (large,)):
+    for cap in dict.fromkeys(caps):
         g = _run(depth, rect, tiles, gw, gh, cap)
         assert g["overflow"] == 0 and g["K"] == K
         assert np.array_equal(g["keys"], keys) and np.array_equal(g["vals"], vals)
         assert np.array_equal(g["ranges"], ranges)
         _check_order(g["order"], ranges)
         outs.append(g)
+
+
+def test_hot_tiles_on_the_per_tile_route():
+    """A few very long lists beside short ones, at an average below the
+    depth-first route's threshold: lists sorted in LDS up to 2048 copies and
+    in 2048-copy chunks beyond (a capacity of 512+ copies per tile), and in
+    1024-copy pieces (a smaller capacity), ties included, give the oracle's
+    keys, values and ranges."""
+    gw, gh, n = 16, 1, 8000
+    rng = np.random.default_rng(8)
+    tx = rng.integers(0, gw, size=n)
+    tx[:5200] = 0                      # a hot tile: 5200+ copies
+    tx[5200:6700] = 1                  # 1500+ copies: in LDS only with 2048 slots
+    rect = np.stack([tx, np.zeros(n, np.int64), tx, np.zeros(n, np.int64)], 1).astype(np.int32)
+    depth = rng.choice(np.linspace(1.0, 50.0, 3000), size=n).astype(np.float32)  # many ties
+    tiles = np.ones(n, np.uint32)
+    keys, vals, ranges = binning.bin_and_sort_fast(rect, depth, gw, gh)
+    K = keys.shape[0]
+    for cap in (K, 512 * gw * gh + 7):
+        assert cap < 2048 * gw * gh  # the per-tile route
+        print(f"[gpu] bin_sort hot tiles K={K} capacity {cap}", flush=True)
+        g = _run(depth, rect, tiles, gw, gh, cap)
+        assert g["overflow"] == 0 and g["K"] == K
+        assert np.array_equal(g["keys"], keys) and np.array_equal(g["vals"], vals)
+        assert np.array_equal(g["ranges"], ranges)

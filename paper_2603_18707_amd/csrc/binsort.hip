@@ -1446,7 +1446,7 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
         a.keys_final = keys;
         a.vals_final = vals;
       }
-      if (presort)
+      if (presort || capacity >= LONG_SEG_MIN_AVG * ntiles)
         radix_pass<LONG_SIPT>(a, capacity, w.ttot, pass, s);
       else
         radix_pass<SIPT>(a, capacity, w.ttot, pass, s);

@@ -364,3 +364,31 @@ def test_auto_culling_choice(scale):
     assert (Ka < K0) == ra.culling
     with pytest.raises(ValueError):
         render.Rasterizer(kern, params, tile_cull="always")
+
+
+def test_culled_without_tile_order():
+    """tile_order = NULL (row-major dispatch of the per-tile sort): the same
+    keys, values and ranges."""
+    from paper_2603_18707_amd import _lib as L
+    scene, cam = scenes.workload_tiny()
+    scene.scales *= 2.0
+    kern, params = H.gpu_kernel("exp", 1, "sigma3"), H.gpu_params(rect_mode=1)
+    r = render.Rasterizer(kern, params, reuse_buffers=False, tile_cull=True)
+    proj = r.preprocess(render.to_device(scene), cam)
+    a = r.bin_sort_fit(proj, cam)
+    K, cap = int(a["num_keys"].item()), a["capacity"]
+    dev = a["keys"].device
+    gw, gh = render.grid_of(cam)
+    ws_bytes = L.gs_bin_sort_workspace(proj["n"], cap, gw * gh)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    keys = torch.full((cap,), -1, dtype=torch.int64, device=dev)
+    vals = torch.full((cap,), -1, dtype=torch.int32, device=dev)
+    ranges = torch.full((gw * gh, 2), -1, dtype=torch.int32, device=dev)
+    nk = torch.zeros(1, dtype=torch.int64, device=dev)
+    ov = torch.zeros(1, dtype=torch.int32, device=dev)
+    L.gs_bin_sort_culled(kern, params, proj["n"], proj["depth"], proj["rect"], proj["tiles"], proj["means2d"],
+                         proj["conic_opacity"], gw, gh, cap, ws, ws_bytes, keys, vals, ranges, None, nk, ov)
+    torch.cuda.synchronize()
+    assert int(ov.item()) == 0 and int(nk.item()) == K
+    assert torch.equal(keys[:K], a["keys"][:K]) and torch.equal(vals[:K], a["vals"][:K])
+    assert torch.equal(ranges, a["ranges"])

@@ -8,11 +8,17 @@
 //     stable LSD radix sort on the ceil(log2 tiles) tile bits only (two 7-bit
 //     passes at 1080p), so inside a tile they stay in index order;
 //  2. each tile's list is sorted stably by depth bits: by one wave when it
-//     holds at most 254 copies, by a workgroup in LDS up to 1024 copies and
-//     in 1024-copy chunks through global memory beyond that, all in one
-//     kernel (longest lists dispatched first, so they overlap the rest).
-//     Keys are offset by the tile's smallest depth, so only the bits that
-//     vary inside the tile are sorted (usually 3 of 4 bytes).
+//     holds at most 254 copies, by a workgroup in LDS up to 1024 copies (2048
+//     when the capacity holds 512 or more per tile) and in chunks of that
+//     size through global memory beyond, all in one kernel (longest lists
+//     dispatched first, so they overlap the rest). Keys are offset by the
+//     tile's smallest depth, so only the bits that vary inside the tile are
+//     sorted (usually 3 of 4 bytes).
+// With a capacity of 2048 or more copies per tile, the splats are instead
+// sorted by depth first and their copies emitted in that order, so the tile
+// passes alone give the final order. With per-tile culling, the copies come
+// from the culling kernels (cull_count, cull_scan, cull_emit) and then take
+// the same route.
 // A radix pass of step 1 is three kernels and no workgroup ever waits on
 // another (a hand-off between workgroups costs ~0.5 us through memory, and
 // device atomics on scattered addresses cost more than the pass itself):

@@ -144,7 +144,7 @@ def lib():
         L.orc_depth_order.restype = None
         L.orc_depth_order.argtypes = [ctypes.c_int64, P, P]
         L.orc_render_pixels.restype = None
-        L.orc_render_pixels.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_int64] + [P] * 7
+        L.orc_render_pixels.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_int64] + [P] * 8
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_cull_cut.restype = ctypes.c_double
         L.orc_cull_cut.argtypes = [P] + [ctypes.c_double] * 4
@@ -262,7 +262,10 @@ def all_pixels(width: int, height: int) -> np.ndarray:
 
 def render_pixels(proj: dict, cfg: Cfg, pixels: np.ndarray, order: np.ndarray = None) -> dict:
     """Composites the given pixels ([m,2] integer x, y) front to back against
-    every splat of ``proj`` in depth order. FP64 arithmetic throughout."""
+    every splat of ``proj`` in depth order. FP64 arithmetic throughout.
+    Besides colour, T and the counts it returns the pixel flags and, for
+    flagged pixels, ``reach`` [m, 2]: bounds on how far the colour and T can
+    move when the flagged decisions go the other way (0 elsewhere)."""
     L = lib()
     n = int(proj["opac"].shape[0])
     if order is None:
@@ -275,11 +278,12 @@ def render_pixels(proj: dict, cfg: Cfg, pixels: np.ndarray, order: np.ndarray = 
     px = c(pixels, np.int32)
     m = int(px.shape[0])
     out = dict(color=np.zeros((m, 3)), T=np.zeros(m), n_contrib=np.zeros(m, np.int32),
-               n_eval=np.zeros(m, np.int32), last_contrib=np.zeros(m, np.int32), flags=np.zeros(m, np.uint8))
+               n_eval=np.zeros(m, np.int32), last_contrib=np.zeros(m, np.int32), flags=np.zeros(m, np.uint8),
+               reach=np.zeros((m, 2), np.float64))
     cc = cfg._c()
     L.orc_render_pixels(ctypes.byref(cc), n, _p(order), _p(m2), _p(co), _p(op), _p(rgb), _p(rect), _p(fl),
                         m, _p(px), _p(out["color"]), _p(out["T"]), _p(out["n_contrib"]), _p(out["n_eval"]),
-                        _p(out["last_contrib"]), _p(out["flags"]))
+                        _p(out["last_contrib"]), _p(out["flags"]), _p(out["reach"]))
     return out
 
 

@@ -695,18 +695,45 @@ void orc_cull_tile_members(const orc_cfg *cfg, int64_t n, const double *means2d,
   }
 }
 
+/* Brute-force compositing of the requested pixels (see the file header).
+ *
+ * reach (may be NULL, else [npix, 2]): per pixel, bounds on how far the
+ * colour (any channel) and the final T can move
+ * when the decisions the pixel's flags mark are taken the other way (reading
+ * G13). Every colour is non-negative, so what a pixel still gathers from
+ * transmittance T on lies in [0, T (R + B)], R the largest rgb entry of any
+ * splat and B the largest background entry. Hence
+ *   - a pair whose inclusion is uncertain (alpha within the band of eps, a
+ *     rectangle edge or a tile-culling test within rounding) and that can
+ *     have alpha a there changes the colour by at most a T (rgb_i + R + B):
+ *     its own term, and the factor (1 - a) on everything behind it; it
+ *     also leaves T uncertain by the relative amount a;
+ *   - a stop decision within its band, widened by that accumulated
+ *     uncertainty of T, changes it by at most T (R + B), the whole remainder,
+ *     which also covers every later decision.
+ * reach is the sum of these terms (0 for unflagged pixels); the bound on T
+ * takes the same terms without the colour factors (a T, and T). */
 void orc_render_pixels(const orc_cfg *cfg, int64_t n, const int64_t *order,
                        const double *means2d, const double *conic, const double *opac,
                        const double *rgb, const int32_t *rect, const uint8_t *splat_flags,
                        int64_t npix, const int32_t *px, double *color, double *final_T,
                        int32_t *n_contrib, int32_t *n_eval, int32_t *last_contrib,
-                       uint8_t *pix_flags) {
+                       uint8_t *pix_flags, double *reach) {
   const int T = cfg->tile;
   const double x0 = (cfg->kind == ORC_KERNEL_POLY) ? orc_first_root(cfg->c, cfg->order, 0.0) : 0.0;
   double *cut = NULL;
   if (cfg->tile_cull) {
     cut = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     orc_cull_cuts(cfg, n, conic, opac, cut);
+  }
+  double crange = 0.0; /* R + B of the reach bound */
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (rgb[i] > crange) crange = rgb[i];
+  {
+    double bmax = 0.0;
+    for (int ch = 0; ch < 3; ++ch)
+      if (fabs(cfg->bg[ch]) > bmax) bmax = fabs(cfg->bg[ch]);
+    crange += bmax;
   }
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t j = 0; j < npix; ++j) {
@@ -716,33 +743,60 @@ void orc_render_pixels(const orc_cfg *cfg, int64_t n, const int64_t *order,
     double Tr = 1.0, C[3] = {0.0, 0.0, 0.0};
     int32_t ncon = 0, nev = 0, last = 0;
     uint8_t fl = 0;
+    double rch = 0.0, rchT = 0.0, unc = 0.0; /* reach of colour and of T so far; relative uncertainty of Tr */
+    int capped = 0;              /* a stop decision was uncertain: rch covers the rest */
     for (int64_t s = 0; s < n; ++s) {
       int64_t i = order[s];
       const int32_t *rc = rect + 4 * i;
+      int uncertain = 0; /* membership of this pair in the pixel's list may differ */
       if (splat_flags && (splat_flags[i] & ORC_SPLAT_EDGE_NEAR)) {
         /* a rectangle edge this close to a tile boundary may land on either side */
         if (tx >= rc[0] - 1 && tx <= rc[2] + 1 && ty >= rc[1] - 1 && ty <= rc[3] + 1 &&
-            (tx <= rc[0] || tx >= rc[2] || ty <= rc[1] || ty >= rc[3]))
+            (tx <= rc[0] || tx >= rc[2] || ty <= rc[1] || ty >= rc[3])) {
           fl |= ORC_PIX_EDGE_NEAR;
+          uncertain = 1;
+        }
       }
-      if (!(tx >= rc[0] && tx <= rc[2] && ty >= rc[1] && ty <= rc[3])) continue;
-      if (cut) { /* tile culling: the list holds the splat only if the tile passes */
+      int member = tx >= rc[0] && tx <= rc[2] && ty >= rc[1] && ty <= rc[3];
+      if (member && cut) { /* tile culling: the list holds the splat only if the tile passes */
         int nr;
         int keep = orc_tile_keep(means2d[2 * i], means2d[2 * i + 1], conic[3 * i], conic[3 * i + 1],
                                  conic[3 * i + 2], cut[i], tx, ty, T, &nr);
-        if (nr) fl |= ORC_PIX_CULL_NEAR;
-        if (!keep) continue;
+        if (nr) {
+          fl |= ORC_PIX_CULL_NEAR;
+          uncertain = 1;
+        }
+        member = keep;
       }
-      ++nev;
+      if (!member && !uncertain) continue;
       double dx = cx - means2d[2 * i], dy = cy - means2d[2 * i + 1];
       double A = conic[3 * i], B = conic[3 * i + 1], Cc = conic[3 * i + 2];
       double Q = A * dx * dx + 2.0 * B * dx * dy + Cc * dy * dy;
       double a = opac[i] * orc_kernel(cfg, x0, Q);
       if (a > cfg->alpha_max) a = cfg->alpha_max;
-      if (fabs(a - cfg->eps) <= cfg->alpha_band) fl |= ORC_PIX_ALPHA_NEAR;
+      const double rgbi = fmax(rgb[3 * i], fmax(rgb[3 * i + 1], rgb[3 * i + 2]));
+      const int anear = member && fabs(a - cfg->eps) <= cfg->alpha_band;
+      if (anear) fl |= ORC_PIX_ALPHA_NEAR;
+      if (!capped && ((uncertain && a >= cfg->eps - cfg->alpha_band) || anear)) {
+        /* this pair may be blended or not: its own term and the factor on what lies behind */
+        const double ah = a > cfg->eps + cfg->alpha_band ? a : cfg->eps + cfg->alpha_band;
+        rch += ah * Tr * (rgbi + crange);
+        rchT += ah * Tr;
+        unc += ah;
+      }
+      if (!member) continue;
+      ++nev;
       if (a < cfg->eps) continue;
       double Tn = Tr * (1.0 - a);
-      if (fabs(Tn - cfg->t_min) <= cfg->t_band_rel * cfg->t_min) fl |= ORC_PIX_T_NEAR;
+      const int tnear = fabs(Tn - cfg->t_min) <= cfg->t_band_rel * cfg->t_min;
+      if (tnear) fl |= ORC_PIX_T_NEAR;
+      if (!capped && (tnear || (unc > 0.0 && fabs(Tn - cfg->t_min) <= (cfg->t_band_rel + unc) * fmax(Tn, cfg->t_min)))) {
+        /* the stop may fall here or not: everything from here on is uncertain */
+        fl |= ORC_PIX_T_NEAR;
+        rch += Tr * crange;
+        rchT += Tr;
+        capped = 1;
+      }
       if (Tn < cfg->t_min) break;
       for (int ch = 0; ch < 3; ++ch) C[ch] += rgb[3 * i + ch] * a * Tr;
       Tr = Tn;
@@ -755,6 +809,10 @@ void orc_render_pixels(const orc_cfg *cfg, int64_t n, const int64_t *order,
     n_eval[j] = nev;
     last_contrib[j] = last;
     pix_flags[j] = fl;
+    if (reach) {
+      reach[2 * j] = fl ? rch : 0.0;
+      reach[2 * j + 1] = fl ? rchT : 0.0;
+    }
   }
   free(cut);
 }

@@ -7,6 +7,7 @@ termination stops before the splat that would push T below T_min. A plain
 Python per-pixel loop on a tiny scene must agree with the C reference.
 """
 import math
+from dataclasses import replace
 
 import numpy as np
 import pytest
@@ -170,3 +171,38 @@ def test_tiny_scene_matches_python_loop(golden_coeffs, kind, order):
     assert np.allclose(full["image"].transpose(1, 2, 0), ref, atol=1e-13)
     assert np.allclose(full["T"], Tref, atol=1e-13)
     assert full["image"].max() > 0.05  # the scene is not empty
+
+
+@pytest.mark.parametrize("kind,order", [(core.KERNEL_EXP, 1), (core.KERNEL_POLY, 1), (core.KERNEL_POLY, 3)])
+def test_reach_bounds_the_flagged_decisions(golden_coeffs, kind, order):
+    """``reach`` bounds what the flagged decisions can change: moving eps
+    and t_min anywhere inside their bands (which flips exactly decisions the
+    flags mark, and no others) leaves unflagged pixels bit-identical and
+    moves flagged ones by at most reach (colour and T). Wide bands make
+    thousands of pixels flagged, with stops and skips flipped together."""
+    scene = scenes.tiny_scene(1500, seed=41)
+    scene.scales *= 2.0
+    scene.opacities[:] = np.clip(scene.opacities * 1.6, 0.0, 0.99).astype(np.float32)
+    cam = scenes.tiny_camera(64, 64)
+    c = tuple(golden_coeffs["paper1"]["c"]) if order == 1 else tuple(golden_coeffs[f"fit{order}"]["c"])
+    base = core.Cfg(kind=kind, order=order, radius_mode=core.RADIUS_SIGMA3, coeffs=c,
+                    alpha_band=2e-3, t_band_rel=0.05)
+    proj = core.round_records(core.project(scene, cam, base))
+    pix = core.all_pixels(64, 64)
+    ref = core.render_pixels(proj, base, pix)
+    fl = ref["flags"] != 0
+    assert fl.sum() > 300 and (~fl).sum() > 300
+    assert ((ref["flags"] & core.PIX_T_NEAR) != 0).sum() > 20
+    worst = 0.0
+    for de in (-0.99, -0.5, 0.5, 0.99):
+        for dt in (-0.99, 0.0, 0.99):
+            cfg = replace(base, eps=base.eps + de * base.alpha_band, t_min=base.t_min * (1.0 + dt * base.t_band_rel))
+            r = core.render_pixels(proj, cfg, pix)
+            dc = np.abs(r["color"] - ref["color"]).max(axis=1)
+            dT = np.abs(r["T"] - ref["T"])
+            assert np.all(dc[~fl] == 0.0) and np.all(dT[~fl] == 0.0), (de, dt)
+            assert np.all(dc[fl] <= ref["reach"][fl, 0] * (1 + 1e-12) + 1e-15), (de, dt, (dc - ref["reach"][:, 0]).max())
+            assert np.all(dT[fl] <= ref["reach"][fl, 1] * (1 + 1e-12) + 1e-15), (de, dt)
+            worst = max(worst, float((dc[fl] / np.maximum(ref["reach"][fl, 0], 1e-30)).max()))
+    assert worst > 0.25  # the bound is reached to within a small factor somewhere
+    assert np.all(ref["reach"][~fl] == 0.0)

@@ -240,7 +240,7 @@ gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const 
  *
  * in : as gs_bin_sort, plus kernel and params (kernel, eps, tile) and the
  *      projected records means2d [n,2] (8-byte aligned) and conic_opacity
- *      [n,4] (16-byte aligned); grid_w * grid_h < 2^22.
+ *      [n,4] (16-byte aligned); grid_w * grid_h < 2^22 and grid_w <= 32767.
  * out, workspace: as gs_bin_sort (the same workspace size). */
 gs_status gs_bin_sort_culled(const gs_kernel *kernel, const gs_params *params, int64_t n, const float *depth,
                              const int32_t *rect, const uint32_t *tiles_touched, const float *means2d,
@@ -369,13 +369,16 @@ gs_status gs_batch_layout(const gs_scene *scenes, int32_t num_scenes, const gs_v
  * gs_rasterize_fwd's for each view bit for bit. workgroups: persistent blend
  * workgroups (0 = library default). images_len / planes_len: lengths (in
  * elements) of the output buffers, checked against every view's range.
- * num_keys / overflow as in gs_bin_sort (on overflow nothing is blended). */
+ * num_keys / overflow as in gs_bin_sort (on overflow nothing is blended).
+ * view_keys (device int64 [num_views], may be NULL): the keys of each view,
+ * i.e. the copies its splats made in its own tile grid (0 for every view on
+ * overflow); they sum to *num_keys. */
 gs_status gs_render_batched(const gs_kernel *kernel, const gs_params *params, const gs_scene *scenes,
                             int32_t num_scenes, const gs_view *views, const gs_view *views_device,
                             int32_t num_views, int64_t key_capacity, int32_t workgroups, void *workspace,
                             size_t workspace_bytes, float *images, int64_t images_len, float *final_T,
                             uint32_t *n_contrib, uint32_t *last_contrib, int64_t planes_len, int64_t *num_keys,
-                            int32_t *overflow, void *stream);
+                            int32_t *overflow, int64_t *view_keys, void *stream);
 
 #ifdef __cplusplus
 }

@@ -86,7 +86,7 @@ def lib():
         L.gs_preprocess_bwd.argtypes = [P, P, P, I64] + [P] * 5 + [I32] + [P] * 4 + [P] * 5 + [P]
         L.gs_batch_layout.argtypes = [P, I32, P, I32, I64, P, P, P, P]
         L.gs_render_batched.argtypes = [P, P, P, I32, P, P, I32, I64, I32, P, ctypes.c_size_t, P, I64, P, P, P, I64,
-                                        P, P, P]
+                                        P, P, P, P]
         for name in EXPORTS[2:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -246,9 +246,9 @@ def gs_batch_layout(scenes, views, key_capacity):
 
 def gs_render_batched(kernel, params, scenes, views, views_device, key_capacity, workgroups, workspace,
                       workspace_bytes, images, images_len, final_T, n_contrib, last_contrib, planes_len, num_keys,
-                      overflow, stream=None):
+                      overflow, stream=None, view_keys=None):
     _check(lib().gs_render_batched(ctypes.byref(kernel), ctypes.byref(params), scenes, len(scenes), views,
                                    _ptr(views_device), len(views), int(key_capacity), int(workgroups),
                                    _ptr(workspace), int(workspace_bytes), _ptr(images), int(images_len),
                                    _ptr(final_T), _ptr(n_contrib), _ptr(last_contrib), int(planes_len),
-                                   _ptr(num_keys), _ptr(overflow), _stream(stream)))
+                                   _ptr(num_keys), _ptr(overflow), _ptr(view_keys), _stream(stream)))

@@ -51,6 +51,7 @@ class BatchRenderer:
         self.last_contrib = torch.zeros(pix_off, dtype=torch.int32, device=self.device)
         self.num_keys = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.overflow = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.view_keys = torch.zeros(len(views), dtype=torch.int64, device=self.device)  # keys of each view
         self.capacity = 0
         self.workgroups = 0
         self.ws = None
@@ -67,7 +68,7 @@ class BatchRenderer:
         L.gs_render_batched(self.kernel, self.params, self.c_scenes, self.c_views, self.views_dev, self.capacity,
                             self.workgroups, self.ws, self.ws_bytes, self.images, self.images.numel(), self.final_T,
                             self.n_contrib, self.last_contrib, self.final_T.numel(), self.num_keys, self.overflow,
-                            stream)
+                            stream, view_keys=self.view_keys)
 
     def render_fit(self):
         """Eager render that grows the key capacity until nothing overflows."""

@@ -168,6 +168,27 @@ __global__ __launch_bounds__(NT) void batch_blend(BlendParams base, const ViewIn
   }
 }
 
+// Keys of each view: the copies in the view's block of virtual tiles (rows
+// row_base .. row_base + gy - 1, columns 0 .. gx - 1), summed from the tile
+// ranges. One workgroup per view.
+__global__ __launch_bounds__(256) void batch_view_keys(const ViewInfo *__restrict__ info, int grid_w,
+                                                       const uint32_t *__restrict__ ranges,
+                                                       int64_t *__restrict__ view_keys) {
+  __shared__ uint64_t part[256 / 64];
+  const ViewInfo in = info[blockIdx.x];
+  const int64_t ntile = (int64_t)in.gx * in.gy;
+  uint64_t sum = 0;
+  for (int64_t i = threadIdx.x; i < ntile; i += blockDim.x) {
+    const size_t t = (size_t)(in.row_base + i / in.gx) * (size_t)grid_w + (size_t)(i % in.gx);
+    sum += ranges[2 * t + 1] - ranges[2 * t];
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) view_keys[blockIdx.x] = (int64_t)(part[0] + part[1] + part[2] + part[3]);
+}
+
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BatchWs {
@@ -238,7 +259,7 @@ hipError_t launch_batch(const PreParams &pre, const BlendParams &blend, const gs
                         const gs_view *views_dev, int nviews, int64_t pairs, int gw, int gh, int64_t capacity,
                         int workgroups, void *ws, float *images, int64_t images_len, float *final_T,
                         uint32_t *n_contrib, uint32_t *last_contrib, int64_t planes_len, int64_t *num_keys,
-                        int32_t *overflow, hipStream_t s) {
+                        int32_t *overflow, int64_t *view_keys, hipStream_t s) {
   BatchWs w;
   carve_batch(ws, nviews, pairs, gw, gh, capacity, &w);
   SceneTable st;
@@ -276,6 +297,8 @@ hipError_t launch_batch(const PreParams &pre, const BlendParams &blend, const gs
   e = launch_binsort(pairs, w.depth, w.rect, w.tiles, gw, gh, capacity, w.sort_ws, w.sort_bytes, w.keys, w.vals,
                      w.ranges, w.order, num_keys, overflow, s);
   if (e != hipSuccess) return e;
+  if (view_keys && nviews > 0)
+    hipLaunchKernelGGL(batch_view_keys, dim3(nviews), dim3(256), 0, s, w.info, gw, w.ranges, view_keys);
   const uint32_t nitems = (uint32_t)((int64_t)gw * gh);
   const unsigned wgs = (unsigned)(workgroups > 0 ? workgroups : 2048);
   switch (blend.blend) {

@@ -310,6 +310,8 @@ gs_status gs_bin_sort_culled(const gs_kernel *kernel, const gs_params *params, i
   if (st != GS_OK) return st;
   if (grid_w < 1 || grid_h < 1 || (int64_t)grid_w * grid_h >= (1ll << 22))
     return fail(GS_EINVAL, "tile grid %dx%d invalid for culled binning (needs fewer than 2^22 tiles)", grid_w, grid_h);
+  // the saved per-row runs hold a tile column in 16 bits
+  if (grid_w > 32767) return fail(GS_EINVAL, "tile grid %d columns wide: culled binning takes at most 32767", grid_w);
   size_t need = 0;
   if ((st = gs_bin_sort_workspace(n, key_capacity, grid_w * grid_h, &need)) != GS_OK) return st;
   if (!workspace || workspace_bytes < need)
@@ -483,7 +485,7 @@ gs_status gs_render_batched(const gs_kernel *kernel, const gs_params *params, co
                             int32_t num_views, int64_t key_capacity, int32_t workgroups, void *workspace,
                             size_t workspace_bytes, float *images, int64_t images_len, float *final_T,
                             uint32_t *n_contrib, uint32_t *last_contrib, int64_t planes_len, int64_t *num_keys,
-                            int32_t *overflow, void *stream) {
+                            int32_t *overflow, int64_t *view_keys, void *stream) {
   gs_status st;
   if ((st = check_params(params)) != GS_OK) return st;
   Resolved r;
@@ -531,7 +533,7 @@ gs_status gs_render_batched(const gs_kernel *kernel, const gs_params *params, co
   b.threads = params->blend_threads ? params->blend_threads : 256;
   return check_hip(launch_batch(p, b, scenes, num_scenes, views_device, num_views, pairs, gw, gh, key_capacity,
                                 workgroups, workspace, images, images_len, final_T, n_contrib, last_contrib,
-                                planes_len, num_keys, overflow, (hipStream_t)stream),
+                                planes_len, num_keys, overflow, view_keys, (hipStream_t)stream),
                    "gs_render_batched launch");
 }
 

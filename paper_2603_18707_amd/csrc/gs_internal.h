@@ -107,7 +107,7 @@ struct BlendParams {
 // rectangle is emitted only when some pixel centre of the tile may pass the
 // blend's inclusion test (bp supplies the kernel, eps and the blend kind;
 // means2d and conic_opacity are the projected records). Needs
-// grid_w * grid_h < 2^22.
+// grid_w * grid_h < 2^22 and grid_w <= 32767.
 hipError_t launch_binsort_culled(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles,
                                  const float *means2d, const float *conic_opacity, const BlendParams &bp,
                                  int grid_w, int grid_h, int64_t capacity, void *ws, size_t ws_bytes, uint64_t *keys,
@@ -143,7 +143,7 @@ hipError_t launch_batch(const PreParams &pre, const BlendParams &blend, const gs
                         const gs_view *views_dev, int nviews, int64_t pairs, int gw, int gh, int64_t capacity,
                         int workgroups, void *ws, float *images, int64_t images_len, float *final_T,
                         uint32_t *n_contrib, uint32_t *last_contrib, int64_t planes_len, int64_t *num_keys,
-                        int32_t *overflow, hipStream_t s);
+                        int32_t *overflow, int64_t *view_keys, hipStream_t s);
 
 inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 

@@ -133,6 +133,7 @@ def test_device_calls_reject_bad_arguments_on_host():
     assert "alignment" in _expect(L.GS_EINVAL, lambda: culled(co=264))
     assert "workspace" in _expect(L.GS_EINVAL, lambda: culled(ws_bytes=ws - 1))
     assert "2^22" in _expect(L.GS_EINVAL, lambda: culled(gw=4096, gh=1024))
+    assert "32767" in _expect(L.GS_EINVAL, lambda: culled(gw=70000, gh=1))
     bad_k = L.gs_kernel_default(L.KERNEL_POLY, 1, L.RADIUS_POLY_OPACITY)
     bad_k.kind = 7
     _expect(L.GS_EINVAL, lambda: culled(kern=bad_k))

@@ -129,3 +129,102 @@ def test_backward_with_background_and_termination():
     assert (ref["T"] < 1.5e-4).sum() > 50  # many pixels end near t_min
     for k in leaves:
         _compare(k, dev[k].grad.cpu().numpy(), leaves[k].grad.numpy())
+
+
+# --- long lists: the adjoint's walk over many 64-record stages ---------------
+
+def _multistage_scene(opacity_logit_mean, n=1500, size=64, seed=77):
+    """1,500 tiny-generator splats (SH degree 3) with doubled scales on a
+    64x64 camera: the central tiles' lists hold 500-800 copies, so blend_bwd
+    walks 8-13 stages of 64 records back to front. Opacity logits
+    N(mean, 1): at mean -4 no pixel terminates and the transmittance and the
+    colour behind are carried across every stage; at mean -1 several hundred
+    pixels stop at list positions beyond the first stage."""
+    scene = scenes.tiny_scene(n, seed=seed, sh_degree=3)
+    scene.scales *= 2.0
+    logit = np.random.default_rng(seed).normal(opacity_logit_mean, 1.0, n)
+    scene.opacities[:] = (1.0 / (1.0 + np.exp(-logit))).astype(np.float32)
+    return scene, scenes.tiny_camera(size, size)
+
+
+def _list_lengths(proj, size, tile=16):
+    """Unculled copies per tile, from the oracle's rectangles."""
+    g = size // tile
+    L = np.zeros((g, g), np.int64)
+    for x0, y0, x1, y1 in proj["rect"]:
+        if x1 >= x0 and y1 >= y0:
+            L[y0:y1 + 1, x0:x1 + 1] += 1
+    return np.kron(L, np.ones((tile, tile), np.int64))  # per pixel
+
+
+MULTISTAGE = [("poly", 1, "opacity", -4.0, False), ("poly", 1, "opacity", -4.0, True),
+              ("exp", 1, "sigma3", -4.0, False), ("exp", 1, "sigma3", -4.0, True),
+              ("poly", 1, "opacity", -1.0, False), ("exp", 1, "sigma3", -1.0, False),
+              ("poly", 1, "opacity", -1.0, True), ("poly", 2, "opacity", -1.0, False),
+              ("poly", 3, "opacity", -1.0, False)]
+
+
+@pytest.mark.parametrize("kind,order,radius,logit_mean,cull", MULTISTAGE)
+def test_multistage_gradients_match_reference(kind, order, radius, logit_mean, cull):
+    """Scene-parameter gradients through tiles whose lists span many 64-record
+    stages, against the FP64 reverse-mode reference, at the bar above."""
+    scene, cam = _multistage_scene(logit_mean)
+    cfg = H.oracle_cfg(kind, order, radius)
+    ref = ocore.render_image(scene, cam, cfg, round_to=None)
+    L = _list_lengths(ref["proj"], cam.width)
+    # the walk really crosses stage boundaries, with contributions on both sides
+    assert L.max() >= 500 and (ref["last_contrib"] > 3 * 64).sum() >= 500, (L.max(), ref["last_contrib"].max())
+    stopped = ref["n_eval"] < L
+    if logit_mean > -2.0:
+        assert (stopped & (ref["n_eval"] > 64)).sum() >= 150, int((stopped & (ref["n_eval"] > 64)).sum())
+    else:
+        assert not stopped.any()
+    w = np.random.default_rng(34).normal(size=(3, cam.height, cam.width)) * (ref["flags"] == 0)
+
+    leaves = {k: torch.tensor(np.asarray(getattr(scene, k), np.float64), requires_grad=True)
+              for k in ("means3d", "scales", "quats", "opacities", "sh")}
+    img, _ = ograd.render(*[leaves[k] for k in ("means3d", "scales", "quats", "opacities", "sh")], scene.sh_degree,
+                          cam, cfg)
+    (img * torch.as_tensor(w)).sum().backward()
+
+    print(f"[gpu] multi-stage backward {kind}{order}/{radius} logit {logit_mean} cull {cull}", flush=True)
+    dev = {k: torch.tensor(np.asarray(getattr(scene, k), np.float32), device="cuda", requires_grad=True)
+           for k in ("means3d", "scales", "quats", "opacities", "sh")}
+    kern, params = H.gpu_kernel(kind, order, radius), H.gpu_params()
+    rast = render.Rasterizer(kern, params, reuse_buffers=False, tile_cull=cull)
+    gimg = autograd.render(*[dev[k] for k in ("means3d", "scales", "quats", "opacities", "sh")], scene.sh_degree,
+                           cam, kern, params, rasterizer=rast)
+    good = ref["flags"] == 0
+    assert np.abs(gimg.detach().cpu().numpy() - ref["image"]).max(axis=0)[good].max() < 2e-4
+    (gimg * torch.as_tensor(w, dtype=torch.float32, device="cuda")).sum().backward()
+    torch.cuda.synchronize()
+    for k in leaves:
+        _compare(k, dev[k].grad.cpu().numpy(), leaves[k].grad.numpy())
+
+
+@pytest.mark.parametrize("kind,order,radius,logit_mean", [("poly", 1, "opacity", -4.0), ("exp", 1, "sigma3", -4.0),
+                                                          ("poly", 1, "opacity", -1.0), ("exp", 1, "sigma3", -1.0)])
+def test_multistage_record_gradients_match_reference(kind, order, radius, logit_mean):
+    """gs_rasterize_bwd's 2D record gradients on the long lists."""
+    scene, cam = _multistage_scene(logit_mean)
+    cfg = H.oracle_cfg(kind, order, radius)
+    t64 = {k: torch.tensor(np.asarray(getattr(scene, k), np.float64)) for k in
+           ("means3d", "scales", "quats", "opacities", "sh")}
+    proj = ograd.project(t64["means3d"], t64["scales"], t64["quats"], t64["opacities"], t64["sh"], scene.sh_degree,
+                         cam, cfg)
+    leaf = {k: proj[k].detach().clone().requires_grad_(True) for k in ("u", "v", "a", "b", "c", "opac", "rgb")}
+    img, _ = ograd.render(None, None, None, None, None, scene.sh_degree, cam, cfg, proj=dict(proj, **leaf))
+    ref = ocore.render_image(scene, cam, cfg, round_to=None)
+    w = np.random.default_rng(35).normal(size=(3, cam.height, cam.width)) * (ref["flags"] == 0)
+    (img * torch.as_tensor(w)).sum().backward()
+
+    print(f"[gpu] multi-stage record backward {kind}{order}/{radius} logit {logit_mean}", flush=True)
+    r = render.Rasterizer(H.gpu_kernel(kind, order, radius), H.gpu_params(), reuse_buffers=False)
+    frame = r.render(render.to_device(scene), cam)
+    g2d = autograd.rasterize_backward(r, frame, cam, torch.as_tensor(w, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    gm, gc = g2d["means2d"].cpu().numpy(), g2d["conic_opacity"].cpu().numpy()
+    for name, g, k in (("u", gm[:, 0], "u"), ("v", gm[:, 1], "v"), ("a", gc[:, 0], "a"), ("b", gc[:, 1], "b"),
+                       ("c", gc[:, 2], "c"), ("opacity", gc[:, 3], "opac")):
+        _compare(name, g, leaf[k].grad.numpy())
+    _compare("rgb", g2d["rgb"].cpu().numpy(), leaf["rgb"].grad.numpy())

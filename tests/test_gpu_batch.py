@@ -1,6 +1,11 @@
 """Batched multi-view rendering (gs_render_batched) on the GPU.
 
-The batched frame must equal per-view gs_rasterize_fwd frames bit for bit
+Against the FP64 oracle: every pixel of every view of a small ragged batch
+and sampled pixels of six views of the full 96-view workload (colour, T and
+blended counts at the forward's bar), and each view's key count against the
+oracle's tile count.
+
+The batched frame must also equal per-view gs_rasterize_fwd frames bit for bit
 (same per-tile lists, same blend code), including views of an empty scene and
 ragged resolutions; a captured HIP graph must reproduce the eager result on
 every replay, with eager work and synchronisations between replays. At the
@@ -11,8 +16,10 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import core as ocore
 from paper_2603_18707_amd import batch, render, scenes
 from tests import helpers as H
+from tests.test_gpu_forward import _check_pixels
 
 pytestmark = pytest.mark.gpu
 
@@ -116,3 +123,80 @@ def test_batched_equals_per_view_ellipse_box(kind, order, radius):
     br.render_fit()
     torch.cuda.synchronize()
     _compare(br, ref)
+
+
+# --- against the FP64 oracle ---------------------------------------------------
+
+def _oracle_view(scene, cam, cfg, pixels, dev_scene, kind, order, radius, params_kw=None):
+    """The oracle's projection and compositing of one view at `pixels`, with
+    the records the GPU projection holds (gs_preprocess runs the batch's
+    projection code; the certified choice between correct roundings is
+    taken from it, see helpers.records_chosen_by)."""
+    o = ocore.project(scene, cam, cfg)
+    exempt = (o["flags"] & ocore.SPLAT_EDGE_NEAR) != 0
+    assert not exempt.any()
+    if scene.n:
+        r = render.Rasterizer(H.gpu_kernel(kind, order, radius), H.gpu_params(**(params_kw or {})))
+        g = r.preprocess(dev_scene, cam)
+        torch.cuda.synchronize()
+        assert np.array_equal(g["rect"].cpu().numpy(), o["rect"])
+        rec, _ = H.records_chosen_by(o, g["means2d"].cpu().numpy(), g["conic_opacity"].cpu().numpy(),
+                                     o["tiles"] > 0)
+    else:
+        rec = ocore.round_records(o)
+    return o, ocore.render_pixels(rec, cfg, pixels)
+
+
+@pytest.mark.parametrize("kind,order,radius,rect_mode", [("poly", 1, "opacity", 0), ("exp", 1, "sigma3", 0),
+                                                         ("poly", 3, "universal", 1), ("exp", 1, "exp_opacity", 1)])
+def test_small_batch_against_oracle(kind, order, radius, rect_mode):
+    """Every pixel of every view of the ragged batch (an empty scene, partial
+    tiles, 16x16 up to 301x157) against the oracle, and each view's key
+    count against the oracle's tile count."""
+    sc, views = _small_batch()
+    dev = [render.to_device(s) for s in sc]
+    print(f"[gpu] batch vs oracle {kind}{order}/{radius} rect {rect_mode}", flush=True)
+    br = batch.BatchRenderer(dev, views, H.gpu_kernel(kind, order, radius), H.gpu_params(rect_mode=rect_mode))
+    K = br.render_fit()
+    torch.cuda.synchronize()
+    vk = br.view_keys.cpu().numpy()
+    assert int(vk.sum()) == K
+    cfg = H.oracle_cfg(kind, order, radius, rect_mode=rect_mode)
+    nflag_all = npix_all = 0
+    for i, (si, cam) in enumerate(views):
+        W, Hh = int(cam.width), int(cam.height)
+        pix = ocore.all_pixels(W, Hh)
+        o, ores = _oracle_view(sc[si], cam, cfg, pix, dev[si], kind, order, radius, {"rect_mode": rect_mode})
+        assert int(vk[i]) == int(o["tiles"].sum()), (i, int(vk[i]), int(o["tiles"].sum()))
+        gx, gy = (W + 15) // 16, (Hh + 15) // 16
+        nflag, err = _check_pixels(br.view_outputs(i), ores, pix, H.edge_flagged_tiles(o, gx, gy))
+        nflag_all, npix_all = nflag_all + nflag, npix_all + pix.shape[0]
+    # counted over the batch: its 16x16 view of 2000 splats flags a few percent
+    assert nflag_all <= H.flag_limit(kind, order, npix_all), nflag_all
+
+
+def test_full_size_batched_workload_against_oracle():
+    """The 96-view workload (6 scenes of 100k-2M splats): six views spread
+    over every scene and resolution, 2048 sampled pixels each, and their key
+    counts, against the oracle; the view key counts sum to K."""
+    sc, views = scenes.workload_batched()
+    dev = [render.to_device(s) for s in sc]
+    br = batch.BatchRenderer(dev, views, H.gpu_kernel("poly", 1, "opacity"), H.gpu_params())
+    K = br.render_fit()
+    torch.cuda.synchronize()
+    vk = br.view_keys.cpu().numpy()
+    assert int(vk.sum()) == K
+    cfg = H.oracle_cfg("poly", 1, "opacity")
+    pick = [7, 17, 34, 48, 66, 83]  # one view of each scene, every resolution
+    assert len({views[i][0] for i in pick}) == 6 and len({views[i][1].width for i in pick}) == 4
+    for i in pick:
+        si, cam = views[i]
+        W, Hh = int(cam.width), int(cam.height)
+        print(f"[gpu] batch view {i}: scene {si} ({sc[si].n} splats) {W}x{Hh}", flush=True)
+        pix = scenes.sample_pixels(W, Hh, 2048, seed=60 + i)
+        o, ores = _oracle_view(sc[si], cam, cfg, pix, dev[si], "poly", 1, "opacity")
+        assert int(vk[i]) == int(o["tiles"].sum()), (i, int(vk[i]), int(o["tiles"].sum()))
+        nflag, err = _check_pixels(br.view_outputs(i), ores, pix, H.edge_flagged_tiles(o, (W + 15) // 16,
+                                                                                        (Hh + 15) // 16))
+        assert nflag <= H.flag_limit("poly", 1, pix.shape[0]), (i, nflag)
+        assert float(np.abs(ores["color"]).max()) > 0.1

@@ -69,15 +69,27 @@ def _check_binning(g, o, gx, gy, exempt):
 
 
 def _check_pixels(g, ores, pix, bad_tiles, tol=2e-4):
-    """Compare GPU outputs at pixels pix [m,2] with oracle results for the same pixels."""
+    """Compare GPU outputs at pixels pix [m,2] with oracle results for the same pixels.
+
+    Unflagged pixels: colour and T within tol, n_contrib (and n_eval) equal.
+    Flagged pixels (a decision within the single-precision band of its
+    threshold, or a tile next to a rectangle edge on a tile boundary) may
+    take that decision either way: their colour and T must lie within the
+    oracle's reach of them (what those decisions can change) plus tol.
+    Returns (flagged count, max error on unflagged pixels)."""
     img, T, nc = _np(g["image"]), _np(g["final_T"]), _np(g["n_contrib"])
     x, y = pix[:, 0], pix[:, 1]
     flagged = (ores["flags"] != 0) | bad_tiles[y // 16, x // 16]
     good = ~flagged
     gi = img[:, y, x].T
     err = np.abs(gi - ores["color"]).max(axis=1)
+    terr = np.abs(T[y, x] - ores["T"])
     assert err[good].max(initial=0.0) <= tol, f"max-abs {err[good].max()} at {pix[good][err[good].argmax()]}"
-    assert np.abs(T[y, x] - ores["T"])[good].max(initial=0.0) <= tol
+    assert terr[good].max(initial=0.0) <= tol
+    over = (err > ores["reach"][:, 0] + tol) | (terr > ores["reach"][:, 1] + tol)
+    assert not (flagged & over).any(), \
+        f"flagged pixel beyond reach: {pix[flagged & over][:3]} err {err[flagged & over][:3]} " \
+        f"reach {ores['reach'][flagged & over][:3]}"
     assert np.array_equal(nc[y, x][good], ores["n_contrib"][good])
     if g.get("n_eval") is not None:
         ne = _np(g["n_eval"])
@@ -97,7 +109,7 @@ def test_tiny_full_frame(kind, order, radius):
     pix = ocore.all_pixels(128, 128)
     ores = ocore.render_pixels(rec, cfg, pix)
     nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, 8, 8))
-    assert nflag <= 0.002 * pix.shape[0]
+    assert nflag <= H.flag_limit(kind, order, pix.shape[0])
     assert float(np.abs(ores["color"]).max()) > 0.5  # not an empty frame
 
 
@@ -186,12 +198,23 @@ def test_background_colour():
     _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, 8, 8))
 
 
-@pytest.mark.parametrize("kind,order,radius", [("exp", 1, "sigma3"), ("poly", 1, "opacity"),
-                                               ("poly", 2, "opacity"), ("poly", 3, "opacity")])
-def test_scene_scale_sampled(kind, order, radius):
+# the whole kernel x radius sweep of the 1M-splat workload: every kernel with
+# every radius it can take (3 sigma, the polynomial's universal and
+# opacity-dependent radii, and exp's own opacity bound), and exp with the
+# polynomial radii (the artefact setting of Sec. 5.2)
+SCENE_SWEEP = KERNELS + [("poly", 2, "sigma3"), ("poly", 3, "sigma3"), ("exp", 1, "universal"), ("exp", 1, "opacity")]
+
+
+@pytest.fixture(scope="module")
+def scene_1m():
+    return scenes.workload_scene()
+
+
+@pytest.mark.parametrize("kind,order,radius", SCENE_SWEEP)
+def test_scene_scale_sampled(scene_1m, kind, order, radius):
     """1M splats, SH degree 3, 1920x1080: every rectangle and key bit-exact,
     4096 sampled pixels against the oracle."""
-    scene, cam = scenes.workload_scene()
+    scene, cam = scene_1m
     cfg = H.oracle_cfg(kind, order, radius)
     o = ocore.project(scene, cam, cfg)
     g = _gpu_frame(scene, cam, kind, order, radius)
@@ -204,7 +227,7 @@ def test_scene_scale_sampled(kind, order, radius):
     ores = ocore.render_pixels(rec, cfg, pix)
     nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, 120, 68))
     print(f"K={K} flagged={nflag} max_err={err:.3g}")
-    assert nflag <= 0.01 * pix.shape[0]
+    assert nflag <= H.flag_limit(kind, order, pix.shape[0])
 
 
 @pytest.mark.parametrize("kind,order,radius", [("poly", 1, "opacity"), ("exp", 1, "sigma3"), ("poly", 3, "opacity")])
@@ -270,8 +293,9 @@ def test_long_thin_footprints_every_pixel(kind, order, radius):
     good = ores["flags"] == 0
     err = np.abs(g["image"].reshape(3, -1).T - ores["color"]).max(axis=1)
     print(f"flagged={int((~good).sum())} max_err={err[good].max():.3g}")
-    assert (~good).sum() <= 0.01 * pix.shape[0]
+    assert (~good).sum() <= H.flag_limit(kind, order, pix.shape[0])
     assert err[good].max() <= 2e-4
+    assert np.all(err[~good] <= ores["reach"][~good, 0] + 2e-4)
     assert np.array_equal(g["n_contrib"].ravel()[good], ores["n_contrib"][good])
 
 
@@ -312,7 +336,7 @@ def test_ellipse_box_rectangles_full_frame(kind, order, radius):
     pix = ocore.all_pixels(128, 128)
     ores = ocore.render_pixels(rec, cfg, pix)
     nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, 8, 8))
-    assert nflag <= 0.002 * pix.shape[0]
+    assert nflag <= H.flag_limit(kind, order, pix.shape[0])
 
 
 @pytest.mark.parametrize("kind,order,radius", [("exp", 1, "sigma3"), ("poly", 1, "opacity")])
@@ -333,4 +357,4 @@ def test_ellipse_box_scene_scale_sampled(kind, order, radius):
     ores = ocore.render_pixels(rec, cfg, pix)
     nflag, err = _check_pixels(g, ores, pix, H.edge_flagged_tiles(o, 120, 68))
     print(f"K={K} flagged={nflag} max_err={err:.3g}")
-    assert nflag <= 0.01 * pix.shape[0]
+    assert nflag <= H.flag_limit(kind, order, pix.shape[0])

@@ -235,8 +235,10 @@ static int float_rounding_alt(double X, double w, double *alt) {
  * can round that entry apart, no others can. rec_alt [n][6] (may be NULL)
  * holds the float on the other side of that midpoint (the entry's own
  * float where the bit is clear): for such an entry both floats are correct. The thin footprints of large
- * anisotropic splats are where this matters: their conic comes from a
- * cancelling determinant (condition A00 A11 / det up to ~1e7). */
+ * anisotropic splats are where this matters: the anti-aliased determinant
+ * A00 A11 - S01^2 still cancels by up to ~1e5 (v bounds it), and the raw
+ * |Sigma'| by up to 1e11 and more, which is why |Sigma'| is evaluated as a
+ * sum of squares (below). */
 void orc_project(const orc_cfg *cfg, const orc_cam *cam, int64_t n,
                  const double *means3d, const double *scales, const double *quats,
                  const double *opacity, const double *sh, int32_t sh_degree,
@@ -328,8 +330,23 @@ void orc_project(const orc_cfg *cfg, const orc_cam *cam, int64_t n,
       }
     double sxy = 0.5 * (S2[0][1] + S2[1][0]);
 
-    /* anti-aliasing (Sec. 3.4) */
-    double det0 = S2[0][0] * S2[1][1] - sxy * sxy;
+    /* anti-aliasing (Sec. 3.4). |Sigma'| is the determinant of M M^T with
+     * M = TW Rq diag(s) (2x3); by Lagrange's identity that is the squared norm
+     * of the cross product of M's rows. A rotation commutes with the cross
+     * product and a diagonal scaling maps x cross y to (s1 s2, s0 s2, s0 s1)
+     * times it, so |Sigma'| = sum_k sig_k^2 n_k^2 with n = Rq^T (TW_0 x TW_1)
+     * and sig = (s1 s2, s0 s2, s0 s1): a sum of squares, which keeps its
+     * relative accuracy where S00 S11 - S01^2 cancels (thin footprints, whose
+     * opacity scale sqrt(|Sigma'| / |Sigma' + vI|) is otherwise lost). */
+    double cw[3] = {TW[0][1] * TW[1][2] - TW[0][2] * TW[1][1], TW[0][2] * TW[1][0] - TW[0][0] * TW[1][2],
+                    TW[0][0] * TW[1][1] - TW[0][1] * TW[1][0]};
+    double nl[3], sg[3] = {scales[3 * i + 1] * scales[3 * i + 2], scales[3 * i] * scales[3 * i + 2],
+                           scales[3 * i] * scales[3 * i + 1]};
+    double det0 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      nl[k] = Rq[0][k] * cw[0] + Rq[1][k] * cw[1] + Rq[2][k] * cw[2];
+      det0 += sg[k] * sg[k] * nl[k] * nl[k];
+    }
     double A00 = S2[0][0] + cfg->aa_v, A11 = S2[1][1] + cfg->aa_v;
     double deta = A00 * A11 - sxy * sxy;
     if (!(deta > 0.0)) continue;
@@ -440,8 +457,21 @@ void orc_project(const orc_cfg *cfg, const orc_cam *cam, int64_t n,
       const double exy = 0.5 * (eS2[0][1] + eS2[1][0]) + g * fabs(sxy);
       const double eA00 = eS2[0][0] + g * A00, eA11 = eS2[1][1] + g * A11;
       const double edeta = eA00 * A11 + A00 * eA11 + 2.0 * fabs(sxy) * exy + g * (A00 * A11 + sxy * sxy);
-      const double edet0 = eS2[0][0] * fabs(S2[1][1]) + fabs(S2[0][0]) * eS2[1][1] + 2.0 * fabs(sxy) * exy +
-                           g * (fabs(S2[0][0] * S2[1][1]) + sxy * sxy);
+      /* |Sigma'| as the sum of squares above: the cross product of TW's rows,
+       * its rotation into the splat's frame (rotation entries within 4 g) and
+       * the weighted squares (sig_k exact: a product of two floats) */
+      double ecw[3], edet0 = 3.0 * g * det0;
+      for (int k2 = 0; k2 < 3; ++k2) {
+        const int a2 = (k2 + 1) % 3, b2 = (k2 + 2) % 3;
+        ecw[k2] = eTW[0][a2] * aTW[1][b2] + fabs(TW[0][a2]) * eTW[1][b2] + eTW[0][b2] * aTW[1][a2] +
+                  fabs(TW[0][b2]) * eTW[1][a2] + g * (fabs(TW[0][a2] * TW[1][b2]) + fabs(TW[0][b2] * TW[1][a2]));
+      }
+      for (int k2 = 0; k2 < 3; ++k2) {
+        double en = 0.0;
+        for (int j2 = 0; j2 < 3; ++j2)
+          en += (fabs(Rq[j2][k2]) + 4.0 * g) * ecw[j2] + 4.0 * g * fabs(cw[j2]) + g * fabs(Rq[j2][k2] * cw[j2]);
+        edet0 += sg[k2] * sg[k2] * (2.0 * fabs(nl[k2]) * en + en * en);
+      }
       double E[6];
       E[0] = cam->fx * (etc[0] / az + fabs(tc[0]) * etc[2] / (az * az)) + g * (fabs(u) + fabs(cam->cx));
       E[1] = cam->fy * (etc[1] / az + fabs(tc[1]) * etc[2] / (az * az)) + g * (fabs(v) + fabs(cam->cy));

@@ -25,6 +25,7 @@
 
 #include "blend_common.h"
 #include "gs_internal.h"
+#include "project_common.h"
 
 namespace gs {
 
@@ -328,7 +329,9 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
     const double Sxx = TS_[0][0] * T2[0][0] + TS_[0][1] * T2[0][1] + TS_[0][2] * T2[0][2];
     const double Sxy = TS_[0][0] * T2[1][0] + TS_[0][1] * T2[1][1] + TS_[0][2] * T2[1][2];
     const double Syy = TS_[1][0] * T2[1][0] + TS_[1][1] * T2[1][1] + TS_[1][2] * T2[1][2];
-    const double det0 = Sxx * Syy - Sxy * Sxy;
+    // |S'| as the forward evaluates it (a sum of squares, accurate for thin
+    // footprints); its derivatives below are the cofactors of S'
+    const double det0 = proj_cov_det(T2, R, s[0], s[1], s[2]);
     const double Axx = Sxx + p.aa_v, Ayy = Syy + p.aa_v;
     const double deta = Axx * Ayy - Sxy * Sxy;
     const double ratio = det0 / deta;

@@ -133,6 +133,27 @@ __device__ inline float3 sh_colour(const float *__restrict__ sh, int64_t i, bool
   return make_float3(fmaxf(a0, 0.0f), fmaxf(a1, 0.0f), fmaxf(a2, 0.0f));
 }
 
+// |S'| for S' = M diag(s)^2 M^T, M = TW Rq: the squared norm of the cross
+// product of the rows of M diag(s) (Lagrange's identity), evaluated as
+// sum_k sig_k^2 n_k^2 with n = Rq^T (TW_0 x TW_1) (a rotation commutes with
+// the cross product) and sig = (s1 s2, s0 s2, s0 s1). A sum of squares keeps
+// its relative accuracy for thin footprints, where Sxx Syy - Sxy^2 cancels
+// completely and the anti-aliasing opacity scale would be rounding noise.
+__device__ inline double proj_cov_det(const double TW[2][3], const double Rq[3][3], double s0, double s1,
+                                      double s2) {
+  const double c0 = TW[0][1] * TW[1][2] - TW[0][2] * TW[1][1];
+  const double c1 = TW[0][2] * TW[1][0] - TW[0][0] * TW[1][2];
+  const double c2 = TW[0][0] * TW[1][1] - TW[0][1] * TW[1][0];
+  const double sg[3] = {s1 * s2, s0 * s2, s0 * s1};
+  double det = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double n = Rq[0][k] * c0 + Rq[1][k] * c1 + Rq[2][k] * c2;
+    det += (sg[k] * n) * (sg[k] * n);
+  }
+  return det;
+}
+
 // Projects splat i of a scene and writes output record o. Tile rows are
 // offset by row_base (non-zero when several views share one virtual grid).
 // Returns whether the splat survived the culls; then Y holds its SH basis
@@ -196,7 +217,7 @@ __device__ inline bool project_one(const PreParams &p, int64_t i, const float *_
     const double Syy = M[1][0] * M[1][0] * ss[0] + M[1][1] * M[1][1] * ss[1] + M[1][2] * M[1][2] * ss[2];
 
     // anti-aliasing: add v to the diagonal, scale opacity by sqrt(|S'| / |S'+vI|)
-    const double det0 = Sxx * Syy - Sxy * Sxy;
+    const double det0 = proj_cov_det(TW, Rq, s0, s1, s2);
     const double Axx = Sxx + p.aa_v, Ayy = Syy + p.aa_v;
     const double deta = Axx * Ayy - Sxy * Sxy;
     if (!(deta > 0.0)) break;

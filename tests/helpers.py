@@ -88,9 +88,22 @@ def ulp_distance(a, b):
     return np.abs(ia - ib)
 
 
-# largest ulp distance from the oracle's own float that an entry the oracle
-# flags may take (its interval may be far wider: E is a first-order bound)
+# largest distance from the oracle's own float that an entry the oracle flags
+# may take, in ulps of the entry (u, v, a, c, o') or of the conic's scale
+# sqrt(a c) (b, which cancels when the footprint's axes lie near the image
+# axes): the oracle's intervals span at most that many floats
+# (test_bound_width_in_floats), thin footprints included
 MAX_RECORD_ULPS = 2
+
+
+def record_ulps(got, own, conic_scale):
+    """Distance of record entries (columns u, v, a, b, c, o') from the
+    oracle's floats in the units of MAX_RECORD_ULPS."""
+    d = ulp_distance(got, own).astype(np.float64)
+    db = np.abs(got[:, 3].astype(np.float64) - own[:, 3].astype(np.float64)) / np.spacing(
+        np.asarray(conic_scale, np.float32)).astype(np.float64)
+    d[:, 3] = db
+    return d
 
 
 def records_chosen_by(o, g_means2d, g_conic_opacity, live):
@@ -103,7 +116,7 @@ def records_chosen_by(o, g_means2d, g_conic_opacity, live):
     oracle's own float; inside, usually also one neighbour (the oracle's
     alternative), more where E is wide. Each entry of a live splat must lie
     in its interval, and within MAX_RECORD_ULPS ulps of the oracle's own
-    float, else this fails. Returns the oracle's projection with
+    float (b: of the conic's scale), else this fails. Returns the oracle's projection with
     the records set to those members of the oracle's intervals (held as
     float64) and the number of entries that are not the oracle's own float.
     """
@@ -122,8 +135,9 @@ def records_chosen_by(o, g_means2d, g_conic_opacity, live):
                              f"first: splat {i} entry {'uvabco'[k]} gpu {got[i, k]!r} oracle {own[i, k]!r} "
                              f"interval [{lo[i, k]!r}, {hi[i, k]!r}] ambiguous {bool(amb[i, k])}")
     if other.any():
-        ulps = int(ulp_distance(got[other], own[other]).max())
-        print(f"[proj] {int(other.sum())} record entries took another correct float, at most {ulps} ulp away")
+        d = record_ulps(got, own, np.sqrt(np.abs(X[:, 2] * X[:, 4])))[other]
+        ulps = float(d.max())
+        print(f"[proj] {int(other.sum())} record entries took another correct float, at most {ulps:.3g} ulp away")
         assert ulps <= MAX_RECORD_ULPS, f"a record entry {ulps} ulps from the oracle's float"
     chosen = np.where(other, got, own).astype(np.float64)
     rec = ocore.round_records(o)

@@ -38,7 +38,7 @@ typedef enum {
   GS_OK = 0,
   GS_EINVAL = -1,        /* bad argument, nothing enqueued */
   GS_EUNSUPPORTED = -2,  /* valid but unsupported setting, nothing enqueued */
-  GS_ECAPACITY = -3,     /* reserved for callers that read the overflow flag */
+  GS_ECAPACITY = -3,     /* the call needs more scratch memory than the library holds (gs_bin_sort_noalloc) */
   GS_EHIP = -4           /* a HIP runtime call or launch failed */
 } gs_status;
 
@@ -217,6 +217,29 @@ gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const 
                       int32_t grid_w, int32_t grid_h, int64_t key_capacity, void *workspace,
                       size_t workspace_bytes, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
                       uint32_t *tile_order, int64_t *num_keys, int32_t *overflow, void *stream);
+
+/* Largest workspace gs_bin_sort_noalloc serves: 128 MiB, enough for 1M splats
+ * with a key capacity of 4M at 1920x1080 (gs_bin_sort_workspace gives ~112 MiB). */
+#define GS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): gs_bin_sort
+ * with its workspace taken from a static device array of
+ * GS_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends. Arguments, outputs and errors are those of
+ * gs_bin_sort without the workspace; the stream must belong to the current
+ * device. Returns GS_ECAPACITY, enqueueing nothing, when
+ * gs_bin_sort_workspace(n, key_capacity, grid_w * grid_h) exceeds
+ * GS_NOALLOC_SCRATCH_BYTES. Calls no hipMalloc, hipFree or allocating library
+ * routine; the first call on a device looks the array's address up once
+ * (hipGetSymbolAddress). Every call on one GPU shares that GPU's array, whose
+ * contents are undefined between calls (the binning clears what must start
+ * at zero itself): calls that may overlap in time on one GPU (other streams,
+ * unordered host threads) race and give undefined results. */
+gs_status gs_bin_sort_noalloc(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles_touched,
+                              int32_t grid_w, int32_t grid_h, int64_t key_capacity, uint64_t *keys, uint32_t *vals,
+                              uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys, int32_t *overflow,
+                              void *stream);
 
 /* Tile binning with per-tile culling (the tile test of StopThePop that the
  * paper adds to every renderer it evaluates, Sec. 2.1 and Sec. 4; App. A

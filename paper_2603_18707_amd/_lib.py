@@ -13,6 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgs.so")
 
 GS_OK, GS_EINVAL, GS_EUNSUPPORTED, GS_ECAPACITY, GS_EHIP = 0, -1, -2, -3, -4
+# scratch held by gs_bin_sort_noalloc (GS_NOALLOC_SCRATCH_BYTES in gs.h)
+GS_NOALLOC_SCRATCH_BYTES = 128 << 20
 KERNEL_EXP, KERNEL_POLY = 0, 1
 RADIUS_SIGMA3, RADIUS_POLY_UNIVERSAL, RADIUS_POLY_OPACITY, RADIUS_EXP_OPACITY = 0, 1, 2, 3
 RECT_SQUARE, RECT_ELLIPSE_BOX = 0, 1
@@ -57,7 +59,7 @@ _lib = None
 
 EXPORTS = ("gs_version", "gs_last_error", "gs_kernel_default", "gs_kernel_order2_tile_range", "gs_kernel_root",
            "gs_params_default",
-           "gs_preprocess", "gs_bin_sort_workspace", "gs_bin_sort", "gs_bin_sort_culled", "gs_rasterize_fwd", "gs_rasterize_fwd_count",
+           "gs_preprocess", "gs_bin_sort_workspace", "gs_bin_sort", "gs_bin_sort_noalloc", "gs_bin_sort_culled", "gs_rasterize_fwd", "gs_rasterize_fwd_count",
            "gs_rasterize_bwd", "gs_preprocess_bwd", "gs_batch_layout", "gs_render_batched")
 
 
@@ -79,6 +81,7 @@ def lib():
         L.gs_preprocess.argtypes = [P, P, P, I64] + [P] * 5 + [I32] + [P] * 6 + [P]
         L.gs_bin_sort_workspace.argtypes = [I64, I64, I32, P]
         L.gs_bin_sort.argtypes = [I64, P, P, P, I32, I32, I64, P, ctypes.c_size_t] + [P] * 6 + [P]
+        L.gs_bin_sort_noalloc.argtypes = [I64, P, P, P, I32, I32, I64] + [P] * 6 + [P]
         L.gs_bin_sort_culled.argtypes = [P, P, I64, P, P, P, P, P, I32, I32, I64, P, ctypes.c_size_t] + [P] * 6 + [P]
         L.gs_rasterize_fwd.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 5 + [P]
         L.gs_rasterize_fwd_count.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 6 + [P]
@@ -191,6 +194,13 @@ def gs_bin_sort(n, depth, rect, tiles_touched, grid_w, grid_h, key_capacity, wor
     _check(lib().gs_bin_sort(int(n), _ptr(depth), _ptr(rect), _ptr(tiles_touched), int(grid_w), int(grid_h),
                              int(key_capacity), _ptr(workspace), int(workspace_bytes), _ptr(keys), _ptr(vals),
                              _ptr(ranges), _ptr(tile_order), _ptr(num_keys), _ptr(overflow), _stream(stream)))
+
+
+def gs_bin_sort_noalloc(n, depth, rect, tiles_touched, grid_w, grid_h, key_capacity, keys, vals, ranges, tile_order,
+                        num_keys, overflow, stream=None):
+    _check(lib().gs_bin_sort_noalloc(int(n), _ptr(depth), _ptr(rect), _ptr(tiles_touched), int(grid_w), int(grid_h),
+                                     int(key_capacity), _ptr(keys), _ptr(vals), _ptr(ranges), _ptr(tile_order),
+                                     _ptr(num_keys), _ptr(overflow), _stream(stream)))
 
 
 def gs_bin_sort_culled(kernel, params, n, depth, rect, tiles_touched, means2d, conic_opacity, grid_w, grid_h,

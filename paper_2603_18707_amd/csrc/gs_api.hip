@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "gs_coeffs.h"
 #include "gs_internal.h"
@@ -267,6 +268,52 @@ gs_status gs_bin_sort(int64_t n, const float *depth, const int32_t *rect, const 
                                   workspace_bytes, keys, vals, ranges, tile_order, num_keys, overflow,
                                   (hipStream_t)stream),
                    "gs_bin_sort launch");
+}
+
+// Workspace of gs_bin_sort_noalloc. In host code `scratch` names a host-side
+// stand-in, not device memory: kernels get the address looked up per device.
+static __device__ __align__(256) unsigned char scratch[GS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// the current device's copy of `scratch`, looked up on first use
+gs_status device_scratch(void **out) {
+  int dev = -1;
+  gs_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (st != GS_OK) return st;
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(GS_EUNSUPPORTED, "device %d beyond the %d supported", dev, MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if ((st = check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)")) != GS_OK)
+      return st;
+    if (!ptr) return fail(GS_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return GS_OK;
+}
+}  // namespace
+
+gs_status gs_bin_sort_noalloc(int64_t n, const float *depth, const int32_t *rect, const uint32_t *tiles_touched,
+                              int32_t grid_w, int32_t grid_h, int64_t key_capacity, uint64_t *keys, uint32_t *vals,
+                              uint32_t *ranges, uint32_t *tile_order, int64_t *num_keys, int32_t *overflow,
+                              void *stream) {
+  if (grid_w < 1 || grid_h < 1 || (int64_t)grid_w * grid_h > (1ll << 30))
+    return fail(GS_EINVAL, "tile grid %dx%d invalid", grid_w, grid_h);
+  size_t need = 0;
+  gs_status st = gs_bin_sort_workspace(n, key_capacity, grid_w * grid_h, &need);
+  if (st != GS_OK) return st;
+  if (need > GS_NOALLOC_SCRATCH_BYTES)
+    return fail(GS_ECAPACITY, "gs_bin_sort_noalloc needs %zu bytes of scratch, more than the %zu it holds", need,
+                (size_t)GS_NOALLOC_SCRATCH_BYTES);
+  void *ws = nullptr;
+  if ((st = device_scratch(&ws)) != GS_OK) return st;
+  return gs_bin_sort(n, depth, rect, tiles_touched, grid_w, grid_h, key_capacity, ws, GS_NOALLOC_SCRATCH_BYTES,
+                     keys, vals, ranges, tile_order, num_keys, overflow, stream);
 }
 
 // the kernel part of the blend parameters (no image size)

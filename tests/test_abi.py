@@ -121,6 +121,15 @@ def test_device_calls_reject_bad_arguments_on_host():
     _expect(L.GS_EINVAL, L.gs_bin_sort, 10, 256, 256, 256, 4, 4, 100, 256, 10, 256, 256, 256, None, 256, 256)
     _expect(L.GS_EINVAL, L.gs_bin_sort_workspace, 10, 1 << 33, 16)
     _expect(L.GS_EINVAL, L.gs_bin_sort, 10, 256, 256, 256, 0, 4, 100, 256, 1 << 30, 256, 256, 256, None, 256, 256)
+    # allocation-free bin sort: the grid check, and sizes beyond its scratch
+    # (checked before any HIP call)
+    _expect(L.GS_EINVAL, L.gs_bin_sort_noalloc, 10, 256, 256, 256, 0, 4, 100, 256, 256, 256, None, 256, 256)
+    big = _expect(L.GS_ECAPACITY, L.gs_bin_sort_noalloc, 1_000_000, 256, 256, 256, 120, 68, 20_000_000,
+                  256, 256, 256, None, 256, 256)
+    assert "scratch" in big
+    assert L.gs_bin_sort_workspace(1_000_000, 4_000_000, 120 * 68) <= L.GS_NOALLOC_SCRATCH_BYTES
+    src = open(os.path.join(ROOT, "include", "gs.h")).read()
+    assert "#define GS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)" in src
     # culled bin sort: the same checks, plus the records, the kernel and a grid below 2^22 tiles
     ws = L.gs_bin_sort_workspace(10, 100, 16)
     good = dict(depth=256, rect=256, tiles=256, m2=256, co=256)

@@ -87,8 +87,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
-    ap.add_argument("--only", default=None, metavar="KERNEL/RADIUS[/culled]",
-                    help="time one frame configuration, e.g. poly2/opacity or exp/sigma3/culled (for profiling); "
+    ap.add_argument("--only", default=None, metavar="KERNEL/RADIUS[/culled|/mfma]",
+                    help="time one frame configuration, e.g. poly2/opacity, exp/sigma3/culled or poly1/opacity/mfma "
+                         "(the matrix-core blend) (for profiling); "
                          "kernels exp|poly1|poly2|poly3, radii sigma3|universal|opacity|exp_opacity")
     ap.add_argument("--no-sweep", action="store_true", help="skip the kernel x culling sweep")
     ap.add_argument("--blend-threads", type=int, default=0, help="64|128|256; 0 = autotune")
@@ -125,13 +126,14 @@ RECT_NAMES = {"square": "bounding-square tile rectangles", "box": "ellipse-box t
 
 
 def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, threads=0, rect="box", cull=False,
-                count=True):
+                count=True, mfma=False):
     """Times `steps` frames with HIP events on the launch stream around each
     frame and each stage; frame and stage times are medians over the frames
     (the mean of the whole loop is kept beside them). threads = 0 lets the
     autotuner pick the blend launch shape during warm-up; cull bins with
     per-tile culling (gs_bin_sort_culled); count adds an untimed frame of the
-    counting blend (evaluations performed)."""
+    counting blend (evaluations performed); mfma blends with the matrix-core
+    blend (gs_rasterize_fwd_mfma; the counting frame stays the vector one's)."""
     from paper_2603_18707_amd import autotune
     r = render.Rasterizer(render.kernel_spec(kind, order, radius), tile_cull=cull)
     r.params.rect_mode = RECT_MODES[rect]
@@ -145,10 +147,11 @@ def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, t
     b0 = r.bin_sort(out["proj"], cam)  # re-size buffers for the final capacity outside the timed loop
     torch.cuda.synchronize()
     tuned = None
-    if threads:
-        r.params.blend_threads = threads
+    if threads or mfma:
+        r.params.blend_threads = threads or 256
     else:
         tuned = autotune.tune_blend(r, out["proj"], b0, cam)
+    r.mfma = mfma
     torch.cuda.synchronize()
 
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
@@ -175,6 +178,7 @@ def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, t
                K=int(b["num_keys"].item()), E=None, E_list=None, B=None, image=None, rast=r,
                threads=int(r.params.blend_threads), tuned=tuned)
     if count:
+        r.mfma = False
         # untimed frame of the counting build: E = kernel evaluations performed,
         # E_list = list entries a per-pixel walk without the box test would evaluate
         full = r.rasterize(proj, b, cam, want_eval=True, want_tested=True)
@@ -474,10 +478,11 @@ def parse_only(spec):
     parts = spec.split("/")
     names = {k[0]: k for k in SWEEP_KERNELS}
     if len(parts) not in (2, 3) or parts[0] not in names or parts[1] not in SWEEP_RADII or \
-            (len(parts) == 3 and parts[2] != "culled"):
-        raise SystemExit(f"--only {spec!r}: expected KERNEL/RADIUS[/culled]")
+            (len(parts) == 3 and parts[2] not in ("culled", "mfma")):
+        raise SystemExit(f"--only {spec!r}: expected KERNEL/RADIUS[/culled|/mfma]")
     _, kind, order = names[parts[0]]
-    return parts[0], kind, order, parts[1], len(parts) == 3
+    extra = parts[2] if len(parts) == 3 else ""
+    return parts[0], kind, order, parts[1], extra == "culled", extra == "mfma"
 
 
 def main():
@@ -513,9 +518,9 @@ def main():
     scene = render.to_device(scene_np)
     W, H = cam.width, cam.height
     if a.only:
-        name, kind, order, radius, cull = parse_only(a.only)
+        name, kind, order, radius, cull, mfma = parse_only(a.only)
         t = time_config(torch, render, scene, cam, kind, order, radius, a.steps, a.warmup, a.blend_threads, a.rect,
-                        cull)
+                        cull, mfma=mfma)
         print(json.dumps({"only": a.only, "rect": RECT_NAMES[a.rect], **summary(t, W, H)}), flush=True)
         return
     kernels = [("poly1", "poly", 1, "opacity"), ("exp", "exp", 1, "sigma3")]
@@ -580,6 +585,17 @@ def main():
         e["E"] * (OPS_8D["exp"] + TRANS_SLOTS["exp"]) / (e["blend_ms"] * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)
     out["speedup_vs_exp_sigma3"] = round(e["ms"] / ms, 4)
     done = {("poly1/opacity", False): hrow, ("exp/sigma3", False): out["exp_sigma3"]}
+
+    # the same frames with the quadric on the matrix cores (gs_rasterize_fwd_mfma)
+    mf = {"blend": "gs_rasterize_fwd_mfma (v_mfma_f32_32x32x2_f32 quadric, 256 threads per tile)"}
+    for name, kind, order, radius in kernels:
+        t = time_config(torch, render, scene, cam, kind, order, radius, a.steps, a.warmup, 256, a.rect, mfma=True,
+                        count=False)
+        mf[name] = summary(t, W, H)
+        mf[name]["blend_vs_vector_blend"] = round(t["blend_ms"] / res[name]["blend_ms"], 3)
+        print(f"[bench] {name} (mfma blend): {t['ms']:.4f} ms/frame, blend {t['blend_ms']:.4f}", file=sys.stderr,
+              flush=True)
+    out["mfma_blend"] = mf
 
     other = "square" if a.rect == "box" else "box"
     alt = {"rect": RECT_NAMES[other]}

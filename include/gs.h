@@ -298,6 +298,27 @@ gs_status gs_rasterize_fwd(const gs_camera *cam, const gs_kernel *kernel, const 
                            float *final_T, uint32_t *n_contrib, uint32_t *last_contrib, uint32_t *n_eval,
                            void *stream);
 
+/* gs_rasterize_fwd with the quadric on the matrix cores (Sec. 5.1: Q of a
+ * block of pixels against a batch of splats is a matrix product of the
+ * pixels' monomials (1, x, y, x^2, x y, y^2) and per-splat coefficient
+ * vectors). Each splat's coefficients expand t = x_e - Q about the centre of
+ * the 8x8 pixel block a wave shades, computed in double from the float record
+ * and rounded once; v_mfma_f32_32x32x2_f32 forms t for 32 splats x 32 pixels.
+ * Blending, early termination and the outputs are those of gs_rasterize_fwd
+ * (same arguments; blend_threads is ignored: 256 threads per tile), up to
+ * rounding: the quadric's rounding differs (a few 1e-5 in t where t is near
+ * 0), and each 32-splat step composites its two halves of 16 separately and
+ * combines them by the over operator's associativity, so images agree with
+ * gs_rasterize_fwd's within float rounding except at inclusion and
+ * termination decisions within that rounding of their thresholds. The lists
+ * must come from gs_bin_sort (per-tile culling bounds the vector blend's
+ * rounding, not this one's). */
+gs_status gs_rasterize_fwd_mfma(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
+                                const float *means2d, const float *conic_opacity, const float *rgb,
+                                const uint32_t *vals, const uint32_t *ranges, const uint32_t *tile_order,
+                                float *image, float *final_T, uint32_t *n_contrib, uint32_t *last_contrib,
+                                uint32_t *n_eval, void *stream);
+
 /* The work gs_rasterize_fwd performs, for measurement: the same blend with
  * the same outputs, plus n_tested [H,W] uint32 = kernel evaluations done for
  * the pixel (list entries its wave did not skip, while the pixel was alive,

@@ -59,7 +59,7 @@ _lib = None
 
 EXPORTS = ("gs_version", "gs_last_error", "gs_kernel_default", "gs_kernel_order2_tile_range", "gs_kernel_root",
            "gs_params_default",
-           "gs_preprocess", "gs_bin_sort_workspace", "gs_bin_sort", "gs_bin_sort_noalloc", "gs_bin_sort_culled", "gs_rasterize_fwd", "gs_rasterize_fwd_count",
+           "gs_preprocess", "gs_bin_sort_workspace", "gs_bin_sort", "gs_bin_sort_noalloc", "gs_bin_sort_culled", "gs_rasterize_fwd", "gs_rasterize_fwd_mfma", "gs_rasterize_fwd_count",
            "gs_rasterize_bwd", "gs_preprocess_bwd", "gs_batch_layout", "gs_render_batched")
 
 
@@ -84,6 +84,7 @@ def lib():
         L.gs_bin_sort_noalloc.argtypes = [I64, P, P, P, I32, I32, I64] + [P] * 6 + [P]
         L.gs_bin_sort_culled.argtypes = [P, P, I64, P, P, P, P, P, I32, I32, I64, P, ctypes.c_size_t] + [P] * 6 + [P]
         L.gs_rasterize_fwd.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 5 + [P]
+        L.gs_rasterize_fwd_mfma.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 5 + [P]
         L.gs_rasterize_fwd_count.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 6 + [P]
         L.gs_rasterize_bwd.argtypes = [P, P, P, I64] + [P] * 6 + [P] * 3 + [P] * 3 + [P]
         L.gs_preprocess_bwd.argtypes = [P, P, P, I64] + [P] * 5 + [I32] + [P] * 4 + [P] * 5 + [P]
@@ -218,6 +219,14 @@ def gs_rasterize_fwd(cam, kernel, params, n, means2d, conic_opacity, rgb, vals, 
                                   _ptr(means2d), _ptr(conic_opacity), _ptr(rgb), _ptr(vals), _ptr(ranges),
                                   _ptr(tile_order), _ptr(image), _ptr(final_T), _ptr(n_contrib), _ptr(last_contrib),
                                   _ptr(n_eval), _stream(stream)))
+
+
+def gs_rasterize_fwd_mfma(cam, kernel, params, n, means2d, conic_opacity, rgb, vals, ranges, tile_order, image,
+                          final_T, n_contrib, last_contrib, n_eval=None, stream=None):
+    _check(lib().gs_rasterize_fwd_mfma(ctypes.byref(cam), ctypes.byref(kernel), ctypes.byref(params), int(n),
+                                       _ptr(means2d), _ptr(conic_opacity), _ptr(rgb), _ptr(vals), _ptr(ranges),
+                                       _ptr(tile_order), _ptr(image), _ptr(final_T), _ptr(n_contrib),
+                                       _ptr(last_contrib), _ptr(n_eval), _stream(stream)))
 
 
 def gs_rasterize_fwd_count(cam, kernel, params, n, means2d, conic_opacity, rgb, vals, ranges, tile_order, image,

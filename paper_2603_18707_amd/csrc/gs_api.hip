@@ -396,6 +396,26 @@ gs_status gs_rasterize_fwd(const gs_camera *cam, const gs_kernel *kernel, const 
                    "gs_rasterize_fwd launch");
 }
 
+gs_status gs_rasterize_fwd_mfma(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
+                                const float *means2d, const float *conic_opacity, const float *rgb,
+                                const uint32_t *vals, const uint32_t *ranges, const uint32_t *tile_order,
+                                float *image, float *final_T, uint32_t *n_contrib, uint32_t *last_contrib,
+                                uint32_t *n_eval, void *stream) {
+  BlendParams b;
+  gs_status st = make_blend(cam, kernel, params, &b);
+  if (st != GS_OK) return st;
+  if (n < 0 || n >= (1ll << 31)) return fail(GS_EINVAL, "n outside [0, 2^31)");
+  b.n = (uint32_t)n;
+  if (!ranges || !image || !final_T || !n_contrib || !last_contrib) return fail(GS_EINVAL, "NULL argument");
+  if (n > 0 && (!means2d || !conic_opacity || !rgb || !vals)) return fail(GS_EINVAL, "NULL splat argument");
+  if ((means2d && !aligned(means2d, 8)) || (conic_opacity && !aligned(conic_opacity, 16)))
+    return fail(GS_EINVAL, "means2d needs 8-byte, conic_opacity 16-byte alignment");
+  BlendOut o{image, final_T, n_contrib, last_contrib, n_eval, nullptr};
+  return check_hip(
+      launch_blend_fwd_mfma(b, means2d, conic_opacity, rgb, vals, ranges, tile_order, o, (hipStream_t)stream),
+      "gs_rasterize_fwd_mfma launch");
+}
+
 gs_status gs_rasterize_fwd_count(const gs_camera *cam, const gs_kernel *kernel, const gs_params *params, int64_t n,
                                  const float *means2d, const float *conic_opacity, const float *rgb,
                                  const uint32_t *vals, const uint32_t *ranges, const uint32_t *tile_order,

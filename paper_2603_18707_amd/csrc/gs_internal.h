@@ -125,6 +125,11 @@ hipError_t launch_blend_fwd(const BlendParams &p, const float *means2d, const fl
                             const float *rgb, const uint32_t *vals, const uint32_t *ranges,
                             const uint32_t *tile_order, BlendOut out, hipStream_t s);
 
+// the same blend with the quadric as a matrix product on MFMA (256 threads per tile)
+hipError_t launch_blend_fwd_mfma(const BlendParams &p, const float *means2d, const float *conic_opacity,
+                                 const float *rgb, const uint32_t *vals, const uint32_t *ranges,
+                                 const uint32_t *tile_order, BlendOut out, hipStream_t s);
+
 hipError_t launch_blend_bwd(const BlendParams &p, int64_t n, const float *means2d, const float *conic_opacity,
                             const float *rgb, const uint32_t *vals, const uint32_t *ranges,
                             const uint32_t *tile_order,

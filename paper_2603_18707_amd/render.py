@@ -57,8 +57,13 @@ class Rasterizer:
     key capacity between frames (the capacity grows when a frame overflows)."""
 
     def __init__(self, kernel: L.GsKernel, params: L.GsParams = None, device="cuda", capacity: int = 0,
-                 reuse_buffers: bool = True, tile_cull=False):
+                 reuse_buffers: bool = True, tile_cull=False, mfma: bool = False):
         self.kernel = kernel
+        # True: blend with gs_rasterize_fwd_mfma (the quadric on the matrix
+        # cores); needs lists from gs_bin_sort, so it excludes tile culling
+        if mfma and tile_cull:
+            raise ValueError("the matrix-core blend takes lists binned without per-tile culling")
+        self.mfma = bool(mfma)
         # True: bin with gs_bin_sort_culled (copies only for reachable tiles); "auto": decided in
         # bin_sort_fit from the frame's rectangle tiles per visible splat
         if isinstance(tile_cull, str) and tile_cull != "auto":
@@ -142,7 +147,8 @@ class Rasterizer:
 
     def rasterize(self, proj: dict, binned: dict, cam, want_eval: bool = False, stream=None,
                   want_tested: bool = False) -> dict:
-        """gs_rasterize_fwd; with want_tested, its counting build
+        """gs_rasterize_fwd (gs_rasterize_fwd_mfma for a matrix-core
+        rasterizer); with want_tested, the vector blend's counting build
         gs_rasterize_fwd_count (adds n_tested, the evaluations performed)."""
         W, H = int(cam.width), int(cam.height)
         out = dict(image=self._buf("image", (3, H, W), torch.float32),
@@ -156,6 +162,8 @@ class Rasterizer:
         if want_tested:
             out["n_tested"] = self._buf("n_tested", (H, W), torch.int32)
             L.gs_rasterize_fwd_count(*args, out["n_tested"], stream)
+        elif self.mfma:
+            L.gs_rasterize_fwd_mfma(*args, stream)
         else:
             L.gs_rasterize_fwd(*args, stream)
         return out

@@ -108,7 +108,7 @@ def parse():
     return ap.parse_args()
 
 
-BLEND_SOURCES = ("rasterize.hip", "blend_common.h", "gs_internal.h")
+BLEND_SOURCES = ("rasterize.hip", "blend_common.h")
 
 
 def kernel_source_hash():

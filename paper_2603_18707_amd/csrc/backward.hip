@@ -1,9 +1,12 @@
 // Adjoint of blending (gs_rasterize_bwd) and of the projection (gs_preprocess_bwd).
 //
-// Blending adjoint: one wave per 16x16 tile, four pixels per lane, the same
-// lane layout, staged record and inclusion test as the forward, so every
-// (pixel, splat) decision matches the forward's. The tile's list is walked
-// back to front from the last blended position of any pixel. Per pixel the
+// Blending adjoint: one workgroup of 256 threads per 16x16 tile, one pixel
+// per lane, each wave an 8x8 block, with the forward's staged record,
+// inclusion test and per-wave box test, so every (pixel, splat) decision
+// matches the forward's and a wave visits only the records that can reach
+// its block. The tile's list is staged back to front in batches of 256 from
+// the last blended position of any pixel, and each wave walks its records
+// back to front from its own pixels' last position. Per pixel the
 // transmittance before a splat is recovered as T_i = T_{i+1} / (1 - alpha_i)
 // from the stored final T, and the colour behind it follows the recurrence
 // S_{i-1} = alpha_i c_i + (1 - alpha_i) S_i, so nothing per pair is stored.
@@ -13,9 +16,10 @@
 // and alpha = min(alpha_max, o' k(Q)) gives dL/do' and dL/dQ (zero when the
 // clamp is active); Q = d^T conic d gives the conic and mean gradients. An
 // included pair has alpha >= eps > 0, so a polynomial kernel is strictly
-// positive there: the ReLU kink never enters. Per splat the nine partial
-// gradients are summed over the lane's pixels, reduced across the wave, and
-// added to global memory by one lane.
+// positive there: the ReLU kink never enters. Each lane adds its pair's nine
+// partial gradients to the staged record's accumulators in LDS; after a
+// batch, one thread per record adds them to global memory, so a splat costs
+// nine global atomics per tile, whatever the number of pixels and waves.
 //
 // Projection adjoint: one thread per splat in double precision, the chain
 // rule through the SH colour, the opacity factor sqrt(|S'| / |S' + vI|), the
@@ -36,12 +40,6 @@ __global__ void zero_f32(float *p, int64_t m) {
   if (i < m) p[i] = 0.0f;
 }
 
-__device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // derivative of the polynomial at Q
 __device__ inline float dpoly(const BlendParams &p, int order, float Q) {
   if (order == 1) return p.c[1];
@@ -55,63 +53,71 @@ __device__ inline float poly(const BlendParams &p, int order, float Q) {
   return fmaf(fmaf(fmaf(p.c[3], Q, p.c[2]), Q, p.c[1]), Q, p.c[0]);
 }
 
+constexpr int BT = 256;            // threads per tile in the adjoint
+constexpr int BW = BT / WAVE;       // waves, each an 8x8 block
+constexpr int NG = 9;               // partial gradients per record
+
 template <int KIND>
-__global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__restrict__ means2d,
-                                                  const float *__restrict__ conic_opacity,
-                                                  const float *__restrict__ rgb, const uint32_t *__restrict__ vals,
-                                                  const uint32_t *__restrict__ ranges,
-                                                  const uint32_t *__restrict__ tile_order,
-                                                  const float *__restrict__ final_T,
-                                                  const uint32_t *__restrict__ last_contrib,
-                                                  const float *__restrict__ dL_dimage, float *__restrict__ dmeans2d,
-                                                  float *__restrict__ dconic, float *__restrict__ drgb) {
-  __shared__ float4 L0[WAVE], L1[WAVE], L2[WAVE];
-  __shared__ float2 L3[WAVE];  // (a, b) of the conic, for the gradients
-  __shared__ uint32_t Lid[WAVE];
+__global__ __launch_bounds__(BT) void blend_bwd(BlendParams p, const float *__restrict__ means2d,
+                                                const float *__restrict__ conic_opacity,
+                                                const float *__restrict__ rgb, const uint32_t *__restrict__ vals,
+                                                const uint32_t *__restrict__ ranges,
+                                                const uint32_t *__restrict__ tile_order,
+                                                const float *__restrict__ final_T,
+                                                const uint32_t *__restrict__ last_contrib,
+                                                const float *__restrict__ dL_dimage, float *__restrict__ dmeans2d,
+                                                float *__restrict__ dconic, float *__restrict__ drgb) {
+  __shared__ float4 L0[BT], L1[BT], L2[BT];
+  __shared__ float2 L3[BT];              // (a, b) of the conic, for the gradients
+  __shared__ uint32_t Lid[BT];
+  __shared__ float G[NG][BT];            // the staged records' gradient accumulators
+  __shared__ uint16_t lst[BW][BT];
+  __shared__ uint32_t wcnt[BW][BW];
+  __shared__ uint32_t wlast[BW];
   constexpr int ORDER = KIND == BLEND_POLY2 ? 2 : (KIND == BLEND_POLY3 ? 3 : 1);
   const int ntiles = p.gx * p.gy;
   if ((int)blockIdx.x >= ntiles) return;
   const int tile = tile_order ? (int)min(tile_order[blockIdx.x], (uint32_t)(ntiles - 1)) : (int)blockIdx.x;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x, wv = lane / WAVE, l64 = lane & (WAVE - 1);
+  const uint64_t lt = (1ull << l64) - 1ull;
   const int tx = tile % p.gx, ty = tile / p.gx;
-  const int px = tx * TS + (lane & (TS - 1));
-  const int py0 = ty * TS + (lane >> 4);
-  const float fx = (float)(lane & (TS - 1)) + 0.5f;  // pixel centres relative to the tile corner
+  const int wx0 = (wv & 1) * 8, wy0 = (wv >> 1) * 8;
+  const int px = tx * TS + wx0 + (l64 & 7), py = ty * TS + wy0 + (l64 >> 3);
+  const float fx = (float)(wx0 + (l64 & 7)) + 0.5f;  // pixel centre relative to the tile corner
+  const float fy = (float)(wy0 + (l64 >> 3)) + 0.5f;
   const size_t plane = (size_t)p.W * p.H;
-  float fy[PIX], T[PIX], Tf[PIX], S0[PIX], S1[PIX], S2[PIX], g0[PIX], g1[PIX], g2[PIX], bgg[PIX];
-  uint32_t lastc[PIX];
+  float Tf = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+  uint32_t lastc = 0u;
+  if (px < p.W && py < p.H) {
+    const size_t pix = (size_t)py * p.W + px;
+    Tf = final_T[pix];
+    lastc = last_contrib[pix];
+    g0 = dL_dimage[pix];
+    g1 = dL_dimage[plane + pix];
+    g2 = dL_dimage[2 * plane + pix];
+  }
+  float T = Tf, S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
+  const float bgg = p.bg[0] * g0 + p.bg[1] * g1 + p.bg[2] * g2;
+  // the last blended position of the wave's and the tile's pixels
+  uint32_t wmax = lastc;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, o, 64));
+  if (l64 == 0) wlast[wv] = wmax;
+  __syncthreads();
   uint32_t maxlast = 0;
 #pragma unroll
-  for (int k = 0; k < PIX; ++k) {
-    const int py = py0 + 4 * k;
-    fy[k] = (float)((lane >> 4) + 4 * k) + 0.5f;
-    S0[k] = S1[k] = S2[k] = 0.0f;
-    if (px < p.W && py < p.H) {
-      const size_t pix = (size_t)py * p.W + px;
-      Tf[k] = final_T[pix];
-      lastc[k] = last_contrib[pix];
-      g0[k] = dL_dimage[pix];
-      g1[k] = dL_dimage[plane + pix];
-      g2[k] = dL_dimage[2 * plane + pix];
-    } else {
-      Tf[k] = 1.0f;
-      lastc[k] = 0u;
-      g0[k] = g1[k] = g2[k] = 0.0f;
-    }
-    T[k] = Tf[k];
-    bgg[k] = p.bg[0] * g0[k] + p.bg[1] * g1[k] + p.bg[2] * g2[k];
-    maxlast = max(maxlast, lastc[k]);
-  }
-  // the wave starts at the last blended position of any of its pixels
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) maxlast = max(maxlast, (uint32_t)__shfl_xor((int)maxlast, o, 64));
+  for (int w = 0; w < BW; ++w) maxlast = max(maxlast, wlast[w]);
 
   const uint32_t start = ranges[2 * tile];
+  const float tile_x0 = (float)(tx * TS), tile_y0 = (float)(ty * TS);
   // positions are 1-based within the tile: pos = index - start + 1
-  for (int64_t hi = (int64_t)maxlast; hi > 0; hi -= WAVE) {
-    const int64_t lo = hi - WAVE > 0 ? hi - WAVE : 0;
+  for (int64_t hi = (int64_t)maxlast; hi > 0; hi -= BT) {
+    const int64_t lo = hi - BT > 0 ? hi - BT : 0;
     const int cnt = (int)(hi - lo);
     // stage positions lo+1 .. hi (list indices start+lo .. start+hi-1); lane j holds position lo+1+j
+    uint32_t mask = 0u;
+#pragma unroll
+    for (int k = 0; k < NG; ++k) G[k][lane] = 0.0f;
     if (lane < cnt) {
       uint32_t id = vals[start + lo + lane];
       if (id >= p.n) id = 0;  // never taken for a list built by gs_bin_sort over these n splats
@@ -119,94 +125,107 @@ __global__ __launch_bounds__(WAVE) void blend_bwd(BlendParams p, const float *__
       const float4 co = reinterpret_cast<const float4 *>(conic_opacity)[id];
       const float3 c = make_float3(rgb[3 * id], rgb[3 * id + 1], rgb[3 * id + 2]);
       float4 a0, a1, a2;
-      fold<KIND>(m, co, c, (float)(tx * TS), (float)(ty * TS), p, a0, a1, a2);
+      fold<KIND>(m, co, c, tile_x0, tile_y0, p, a0, a1, a2);
       L0[lane] = a0;
       L1[lane] = a1;
       L2[lane] = a2;
       L3[lane] = make_float2(co.x, co.y);
       Lid[lane] = id;
+      float hx, hy;
+      pass_box(co, a1.y, hx, hy);
+#pragma unroll
+      for (int w = 0; w < BW; ++w) {
+        const float bx = 0.5f + (float)((w & 1) * 8), by = 0.5f + (float)((w >> 1) * 8);
+        if (a0.x + hx >= bx && a0.x - hx <= bx + 7.0f && a0.y + hy >= by && a0.y - hy <= by + 7.0f) mask |= 1u << w;
+      }
+    }
+    uint64_t bal[BW];
+#pragma unroll
+    for (int w = 0; w < BW; ++w) bal[w] = __ballot((mask >> w) & 1u);
+    if (l64 == 0) {
+#pragma unroll
+      for (int w = 0; w < BW; ++w) wcnt[wv][w] = (uint32_t)__popcll(bal[w]);
     }
     __syncthreads();
-    for (int j = cnt - 1; j >= 0; --j) {
+#pragma unroll
+    for (int w = 0; w < BW; ++w) {
+      if ((mask >> w) & 1u) {
+        uint32_t off = (uint32_t)__popcll(bal[w] & lt);
+        for (int s = 0; s < wv; ++s) off += wcnt[s][w];
+        lst[w][off] = (uint16_t)lane;
+      }
+    }
+    uint32_t len = 0;
+#pragma unroll
+    for (int s = 0; s < BW; ++s) len += wcnt[s][wv];
+    __syncthreads();
+    // this wave's records, back to front
+    for (int q = (int)len - 1; q >= 0; --q) {
+      const int j = lst[wv][q];
       const uint32_t pos = (uint32_t)(lo + 1 + j);
+      if (pos > wmax) continue;  // beyond every pixel of the wave
       const float4 r0 = L0[j];
       const float4 r1 = L1[j];
-      const RowPart rp = row_part(r0, r1.y, fx);
-      float t[PIX];
-#pragma unroll
-      for (int k = 0; k < PIX; ++k) t[k] = t_at(rp, r1.x, fy[k]);
-      bool inc[PIX];
-      bool anyinc = false;
-#pragma unroll
-      for (int k = 0; k < PIX; ++k) {
-        inc[k] = t[k] >= 0.0f && pos <= lastc[k];
-        anyinc = anyinc || inc[k];
-      }
-      if (__ballot(anyinc) == 0ull) continue;
+      const float t = t_at(row_part(r0, r1.y, fx), r1.x, fy);
+      if (!(t >= 0.0f && pos <= lastc)) continue;
       const float4 r2 = L2[j];
       const float2 ab = L3[j];
       const float o = r1.w;
-      const float dx = fx - r0.x;
-      float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
-#pragma unroll
-      for (int k = 0; k < PIX; ++k) {
-        if (!inc[k]) continue;
-        const float a = alpha_from<KIND>(t[k], r1, p);
-        const float oma = 1.0f - a;
-        T[k] = T[k] / oma;  // transmittance before this splat
-        const float w = a * T[k];
-        gr = fmaf(w, g0[k], gr);
-        gg = fmaf(w, g1[k], gg);
-        gbl = fmaf(w, g2[k], gbl);
-        const float dLda = T[k] * ((r2.x - S0[k]) * g0[k] + (r2.y - S1[k]) * g1[k] + (r2.z - S2[k]) * g2[k]) -
-                           Tf[k] / oma * bgg[k];
-        S0[k] = fmaf(a, r2.x - S0[k], S0[k]);
-        S1[k] = fmaf(a, r2.y - S1[k], S1[k]);
-        S2[k] = fmaf(a, r2.z - S2[k], S2[k]);
-        // alpha = o' k(Q) unless clamped; Q from the same t the decisions used
-        const float dy = fy[k] - r0.y;
-        const float Q = r1.y - t[k];
-        float kq, dk;
-        if (KIND == BLEND_EXP) {
-          kq = __expf(-0.5f * Q);
-          dk = -0.5f * kq;
-        } else {
-          kq = poly(p, ORDER, Q);
-          dk = dpoly(p, ORDER, Q);
-        }
-        if (o * kq > p.alpha_max) continue;
-        go = fmaf(dLda, kq, go);
-        const float dLdQ = dLda * o * dk;
-        ga = fmaf(dLdQ, dx * dx, ga);
-        gb = fmaf(dLdQ, 2.0f * dx * dy, gb);
-        gc = fmaf(dLdQ, dy * dy, gc);
-        // Q depends on the mean through d = pixel - mean
-        gu = fmaf(dLdQ, -2.0f * (ab.x * dx + ab.y * dy), gu);
-        gv = fmaf(dLdQ, -2.0f * (ab.y * dx + r1.x * dy), gv);
+      const float a = alpha_from<KIND>(t, r1, p);
+      const float oma = 1.0f - a;
+      T = T / oma;  // transmittance before this splat
+      const float w = a * T;
+      const float dLda = T * ((r2.x - S0) * g0 + (r2.y - S1) * g1 + (r2.z - S2) * g2) - Tf / oma * bgg;
+      S0 = fmaf(a, r2.x - S0, S0);
+      S1 = fmaf(a, r2.y - S1, S1);
+      S2 = fmaf(a, r2.z - S2, S2);
+      atomicAdd(&G[6][j], w * g0);
+      atomicAdd(&G[7][j], w * g1);
+      atomicAdd(&G[8][j], w * g2);
+      // alpha = o' k(Q) unless clamped; Q from the same t the decisions used
+      const float Q = r1.y - t;
+      float kq, dk;
+      if (KIND == BLEND_EXP) {
+        kq = __expf(-0.5f * Q);
+        dk = -0.5f * kq;
+      } else {
+        kq = poly(p, ORDER, Q);
+        dk = dpoly(p, ORDER, Q);
       }
-      gu = wave_sum(gu);
-      gv = wave_sum(gv);
-      ga = wave_sum(ga);
-      gb = wave_sum(gb);
-      gc = wave_sum(gc);
-      go = wave_sum(go);
-      gr = wave_sum(gr);
-      gg = wave_sum(gg);
-      gbl = wave_sum(gbl);
-      if (lane == 0) {
-        const uint32_t id = Lid[j];
-        atomicAdd(&dmeans2d[2 * id], gu);
-        atomicAdd(&dmeans2d[2 * id + 1], gv);
-        atomicAdd(&dconic[4 * id], ga);
-        atomicAdd(&dconic[4 * id + 1], gb);
-        atomicAdd(&dconic[4 * id + 2], gc);
-        atomicAdd(&dconic[4 * id + 3], go);
-        atomicAdd(&drgb[3 * id], gr);
-        atomicAdd(&drgb[3 * id + 1], gg);
-        atomicAdd(&drgb[3 * id + 2], gbl);
-      }
+      if (o * kq > p.alpha_max) continue;
+      const float dx = fx - r0.x, dy = fy - r0.y;
+      const float dLdQ = dLda * o * dk;
+      atomicAdd(&G[5][j], dLda * kq);
+      atomicAdd(&G[2][j], dLdQ * dx * dx);
+      atomicAdd(&G[3][j], dLdQ * 2.0f * dx * dy);
+      atomicAdd(&G[4][j], dLdQ * dy * dy);
+      // Q depends on the mean through d = pixel - mean
+      atomicAdd(&G[0][j], dLdQ * -2.0f * (ab.x * dx + ab.y * dy));
+      atomicAdd(&G[1][j], dLdQ * -2.0f * (ab.y * dx + r1.x * dy));
     }
     __syncthreads();
+    if (lane < cnt) {
+      float gv[NG];
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < NG; ++k) {
+        gv[k] = G[k][lane];
+        any = any || gv[k] != 0.0f;
+      }
+      if (any) {
+        const uint32_t id = Lid[lane];
+        atomicAdd(&dmeans2d[2 * id], gv[0]);
+        atomicAdd(&dmeans2d[2 * id + 1], gv[1]);
+        atomicAdd(&dconic[4 * id], gv[2]);
+        atomicAdd(&dconic[4 * id + 1], gv[3]);
+        atomicAdd(&dconic[4 * id + 2], gv[4]);
+        atomicAdd(&dconic[4 * id + 3], gv[5]);
+        atomicAdd(&drgb[3 * id], gv[6]);
+        atomicAdd(&drgb[3 * id + 1], gv[7]);
+        atomicAdd(&drgb[3 * id + 2], gv[8]);
+      }
+    }
+    __syncthreads();  // the staging area is reused
   }
 }
 
@@ -442,7 +461,7 @@ hipError_t launch_blend_bwd(const BlendParams &p, int64_t n, const float *means2
     hipLaunchKernelGGL(zero_f32, dim3(ceil_div(4 * n, 256)), dim3(256), 0, s, dconic_opacity, 4 * n);
     hipLaunchKernelGGL(zero_f32, dim3(ceil_div(3 * n, 256)), dim3(256), 0, s, drgb, 3 * n);
   }
-  const dim3 grid(p.gx * p.gy), block(WAVE);
+  const dim3 grid(p.gx * p.gy), block(BT);
   switch (p.blend) {
     case BLEND_EXP:
       hipLaunchKernelGGL(blend_bwd<BLEND_EXP>, grid, block, 0, s, p, means2d, conic_opacity, rgb, vals, ranges,

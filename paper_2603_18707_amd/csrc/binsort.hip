@@ -800,14 +800,35 @@ __device__ inline int length_bucket(const uint32_t *ranges, int64_t t) {
   return 255 - (b < 255 ? b : 255);
 }
 
-__global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t *__restrict__ ranges, int64_t ntiles,
-                                                          uint32_t *__restrict__ order, uint32_t *__restrict__ split) {
+// One workgroup; each thread takes tiles tid + 1024 k in groups of ORD_ITEMS,
+// all of a group's range loads in flight together (the kernel is a few
+// dependent round trips to memory, so their number sets its time), and keeps
+// the buckets of the first group for the scatter.
+constexpr int ORD_THREADS = 1024, ORD_ITEMS = 8;
+
+__global__ __launch_bounds__(ORD_THREADS) void tile_order_kernel(const uint32_t *__restrict__ ranges, int64_t ntiles,
+                                                                 uint32_t *__restrict__ order,
+                                                                 uint32_t *__restrict__ split) {
   constexpr int NB = 256;
   __shared__ uint32_t hist[NB];
   __shared__ uint32_t wsum[NB / 64];
   if (threadIdx.x < NB) hist[threadIdx.x] = 0u;
   __syncthreads();
-  for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) atomicAdd(&hist[length_bucket(ranges, t)], 1u);
+  constexpr int64_t GROUP = (int64_t)ORD_THREADS * ORD_ITEMS;
+  int first[ORD_ITEMS];
+  for (int64_t g0 = 0; g0 < ntiles; g0 += GROUP) {
+    int b[ORD_ITEMS];
+#pragma unroll
+    for (int k = 0; k < ORD_ITEMS; ++k) {
+      const int64_t t = g0 + threadIdx.x + (int64_t)k * ORD_THREADS;
+      b[k] = t < ntiles ? length_bucket(ranges, t) : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < ORD_ITEMS; ++k) {
+      if (b[k] >= 0) atomicAdd(&hist[b[k]], 1u);
+      if (g0 == 0) first[k] = b[k];
+    }
+  }
   __syncthreads();
   uint32_t v = 0, inc = 0;
   if (threadIdx.x < NB) {
@@ -823,9 +844,20 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t *__rest
     if (split && threadIdx.x == 255 - WAVE_BUCKET) *split = off;  // first position of a list <= WAVE_MAX
   }
   __syncthreads();
-  for (int64_t t = threadIdx.x; t < ntiles; t += blockDim.x) {
-    const uint32_t pos = atomicAdd(&hist[length_bucket(ranges, t)], 1u);
-    if ((int64_t)pos < ntiles) order[pos] = (uint32_t)t;
+  for (int64_t g0 = 0; g0 < ntiles; g0 += GROUP) {
+    int b[ORD_ITEMS];
+#pragma unroll
+    for (int k = 0; k < ORD_ITEMS; ++k) {
+      const int64_t t = g0 + threadIdx.x + (int64_t)k * ORD_THREADS;
+      b[k] = g0 == 0 ? first[k] : (t < ntiles ? length_bucket(ranges, t) : -1);
+    }
+#pragma unroll
+    for (int k = 0; k < ORD_ITEMS; ++k) {
+      if (b[k] >= 0) {
+        const uint32_t pos = atomicAdd(&hist[b[k]], 1u);
+        if ((int64_t)pos < ntiles) order[pos] = (uint32_t)(g0 + threadIdx.x + (int64_t)k * ORD_THREADS);
+      }
+    }
   }
 }
 
@@ -1463,13 +1495,13 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
       hipLaunchKernelGGL(tile_ranges<true>, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, (const void *)keys,
                          count_dev, ntiles, ranges);
       if (tile_order)
-        hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order, (uint32_t *)nullptr);
+        hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(ORD_THREADS), 0, s, ranges, ntiles, tile_order, (uint32_t *)nullptr);
       return hipGetLastError();
     }
     hipLaunchKernelGGL(tile_ranges<false>, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, (const void *)w.tk[cur],
                        count_dev, ntiles, ranges);
     if (tile_order)
-      hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order, w.ctr + CTR_SPLIT);
+      hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(ORD_THREADS), 0, s, ranges, ntiles, tile_order, w.ctr + CTR_SPLIT);
     Seg g{};
     g.ranges = ranges;
     g.order = tile_order;
@@ -1489,7 +1521,7 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
   }
   // nothing emitted (or no room): ranges stay zero
   if (tile_order)
-    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, s, ranges, ntiles, tile_order, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(ORD_THREADS), 0, s, ranges, ntiles, tile_order, (uint32_t *)nullptr);
   return hipGetLastError();
 }
 }  // namespace

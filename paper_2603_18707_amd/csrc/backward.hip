@@ -233,49 +233,43 @@ __global__ __launch_bounds__(BT) void blend_bwd(BlendParams p, const float *__re
 // projection adjoint
 // ---------------------------------------------------------------------------
 
-// SH basis values and their gradients w.r.t. the unit direction (x, y, z)
-__device__ inline void sh_basis_grad(int deg, double x, double y, double z, double Y[16], double dY[16][3]) {
-  const double PI = 3.14159265358979323846;
-  for (int k = 0; k < 16; ++k) {
-    Y[k] = 0.0;
-    dY[k][0] = dY[k][1] = dY[k][2] = 0.0;
+// Gradients of the real SH basis (sh_basis, in the same single precision
+// and with the same constants) with respect to the unit direction (x, y, z)
+template <int DEG>
+__device__ inline void sh_basis_dir_grad(float x, float y, float z, float dY[16][3]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) dY[k][0] = dY[k][1] = dY[k][2] = 0.0f;
+  if (DEG >= 1) {
+    const float k1 = 0.48860251190291992f;
+    dY[1][1] = -k1;
+    dY[2][2] = k1;
+    dY[3][0] = -k1;
   }
-  Y[0] = sqrt(1.0 / (4.0 * PI));
-  if (deg >= 1) {
-    const double k1 = sqrt(3.0 / (4.0 * PI));
-    Y[1] = -k1 * y; dY[1][1] = -k1;
-    Y[2] = k1 * z; dY[2][2] = k1;
-    Y[3] = -k1 * x; dY[3][0] = -k1;
+  if (DEG >= 2) {
+    const float a = 1.0925484305920792f, b = 0.31539156525252005f, c = 0.54627421529603959f;
+    dY[4][0] = a * y; dY[4][1] = a * x;
+    dY[5][1] = -a * z; dY[5][2] = -a * y;
+    dY[6][0] = -2.0f * b * x; dY[6][1] = -2.0f * b * y; dY[6][2] = 4.0f * b * z;
+    dY[7][0] = -a * z; dY[7][2] = -a * x;
+    dY[8][0] = 2.0f * c * x; dY[8][1] = -2.0f * c * y;
   }
-  if (deg >= 2) {
-    const double a = sqrt(15.0 / (4.0 * PI)), b = sqrt(5.0 / (16.0 * PI)), c = sqrt(15.0 / (16.0 * PI));
-    Y[4] = a * x * y; dY[4][0] = a * y; dY[4][1] = a * x;
-    Y[5] = -a * y * z; dY[5][1] = -a * z; dY[5][2] = -a * y;
-    Y[6] = b * (2 * z * z - x * x - y * y); dY[6][0] = -2 * b * x; dY[6][1] = -2 * b * y; dY[6][2] = 4 * b * z;
-    Y[7] = -a * x * z; dY[7][0] = -a * z; dY[7][2] = -a * x;
-    Y[8] = c * (x * x - y * y); dY[8][0] = 2 * c * x; dY[8][1] = -2 * c * y;
-  }
-  if (deg >= 3) {
-    const double a = sqrt(35.0 / (32.0 * PI)), b = sqrt(105.0 / (4.0 * PI)), c = sqrt(21.0 / (32.0 * PI));
-    const double d = sqrt(7.0 / (16.0 * PI)), e = sqrt(105.0 / (16.0 * PI));
-    const double xx = x * x, yy = y * y, zz = z * z;
-    Y[9] = -a * y * (3 * xx - yy);
-    dY[9][0] = -6 * a * x * y; dY[9][1] = -a * (3 * xx - 3 * yy);
-    Y[10] = b * x * y * z;
+  if (DEG >= 3) {
+    const float a = 0.59004358992664352f, b = 2.8906114426405538f, c = 0.45704579946446572f;
+    const float d = 0.37317633259011540f, e = 1.4453057213202769f;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    dY[9][0] = -6.0f * a * x * y; dY[9][1] = -a * (3.0f * xx - 3.0f * yy);
     dY[10][0] = b * y * z; dY[10][1] = b * x * z; dY[10][2] = b * x * y;
-    Y[11] = -c * y * (4 * zz - xx - yy);
-    dY[11][0] = 2 * c * x * y; dY[11][1] = -c * (4 * zz - xx - 3 * yy); dY[11][2] = -8 * c * y * z;
-    Y[12] = d * z * (2 * zz - 3 * xx - 3 * yy);
-    dY[12][0] = -6 * d * x * z; dY[12][1] = -6 * d * y * z; dY[12][2] = d * (6 * zz - 3 * xx - 3 * yy);
-    Y[13] = -c * x * (4 * zz - xx - yy);
-    dY[13][0] = -c * (4 * zz - 3 * xx - yy); dY[13][1] = 2 * c * x * y; dY[13][2] = -8 * c * x * z;
-    Y[14] = e * z * (xx - yy);
-    dY[14][0] = 2 * e * x * z; dY[14][1] = -2 * e * y * z; dY[14][2] = e * (xx - yy);
-    Y[15] = -a * x * (xx - 3 * yy);
-    dY[15][0] = -a * (3 * xx - 3 * yy); dY[15][1] = 6 * a * x * y;
+    dY[11][0] = 2.0f * c * x * y; dY[11][1] = -c * (4.0f * zz - xx - 3.0f * yy); dY[11][2] = -8.0f * c * y * z;
+    dY[12][0] = -6.0f * d * x * z; dY[12][1] = -6.0f * d * y * z; dY[12][2] = d * (6.0f * zz - 3.0f * xx - 3.0f * yy);
+    dY[13][0] = -c * (4.0f * zz - 3.0f * xx - yy); dY[13][1] = 2.0f * c * x * y; dY[13][2] = -8.0f * c * x * z;
+    dY[14][0] = 2.0f * e * x * z; dY[14][1] = -2.0f * e * y * z; dY[14][2] = e * (xx - yy);
+    dY[15][0] = -a * (3.0f * xx - 3.0f * yy); dY[15][1] = 6.0f * a * x * y;
   }
 }
 
+// the SH degree is a template parameter so that the basis values and their
+// gradients stay in registers (fully unrolled, constant indices)
+template <int DEG>
 __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
     PreParams p, int64_t n, const float *__restrict__ means3d, const float *__restrict__ scales,
     const float *__restrict__ quats, const float *__restrict__ opac, const float *__restrict__ sh,
@@ -284,10 +278,11 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
     float *__restrict__ dquats, float *__restrict__ dopac, float *__restrict__ dsh) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int nsh = (p.sh_degree + 1) * (p.sh_degree + 1);
+  constexpr int nsh = (DEG + 1) * (DEG + 1);
   double gmu[3] = {0.0, 0.0, 0.0}, gs3[3] = {0.0, 0.0, 0.0}, gq[4] = {0.0, 0.0, 0.0, 0.0}, gop = 0.0;
   const bool live = tiles[i] != 0u;
   if (!live) {
+#pragma unroll
     for (int k = 0; k < nsh * 3; ++k) dsh[(size_t)i * nsh * 3 + k] = 0.0f;
   } else {
     const CamD &cam = p.cam;
@@ -295,31 +290,46 @@ __global__ __launch_bounds__(128) void preprocess_bwd_kernel(
     double t[3];
     for (int r = 0; r < 3; ++r) t[r] = cam.R[3 * r] * mx + cam.R[3 * r + 1] * my + cam.R[3 * r + 2] * mz + cam.t[r];
 
-    // ---- colour: rgb = max(sum_k Y_k(d) sh_k + 0.5, 0), d = (mu - campos) / |mu - campos|
+    // ---- colour: rgb = max(sum_k Y_k(d) sh_k + 0.5, 0), d = (mu - campos) / |mu - campos|, in
+    // single precision exactly as the forward evaluates it (same direction, basis and FMA order), so the
+    // clamp's pass-through decision is the forward's
     {
-      double v[3] = {mx - cam.campos[0], my - cam.campos[1], mz - cam.campos[2]};
-      const double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-      const double d[3] = {v[0] / vn, v[1] / vn, v[2] / vn};
-      double Y[16], dY[16][3];
-      sh_basis_grad(p.sh_degree, d[0], d[1], d[2], Y, dY);
+      const double v0 = mx - cam.campos[0], v1 = my - cam.campos[1], v2 = mz - cam.campos[2];
+      const double vn2 = v0 * v0 + v1 * v1 + v2 * v2;
+      const double dn = 1.0 / sqrt(vn2);
+      const float xf = (float)(v0 * dn), yf = (float)(v1 * dn), zf = (float)(v2 * dn);
+      float Y[16], dY[16][3];
+      sh_basis<DEG>(xf, yf, zf, Y);
+      sh_basis_dir_grad<DEG>(xf, yf, zf, dY);
       const float *shi = sh + (size_t)i * nsh * 3;
-      double acc[3] = {0.5, 0.5, 0.5};
+      float shv[nsh * 3];
+#pragma unroll
+      for (int k = 0; k < nsh * 3; ++k) shv[k] = shi[k];
+      float acc[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
       for (int k = 0; k < nsh; ++k)
-        for (int c = 0; c < 3; ++c) acc[c] += Y[k] * (double)shi[3 * k + c];
-      double ga[3];
-      for (int c = 0; c < 3; ++c) ga[c] = acc[c] > 0.0 ? (double)drgb[3 * i + c] : 0.0;
-      double gd[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = fmaf(Y[k], shv[3 * k + c], acc[c]);
+      float ga[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ga[c] = acc[c] > 0.0f ? drgb[3 * i + c] : 0.0f;
+      float gd[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
       for (int k = 0; k < nsh; ++k) {
-        double s = 0.0;
+        float sk = 0.0f;
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-          dsh[(size_t)i * nsh * 3 + 3 * k + c] = (float)(Y[k] * ga[c]);
-          s += (double)shi[3 * k + c] * ga[c];
+          dsh[(size_t)i * nsh * 3 + 3 * k + c] = Y[k] * ga[c];
+          sk = fmaf(shv[3 * k + c], ga[c], sk);
         }
-        for (int a = 0; a < 3; ++a) gd[a] += dY[k][a] * s;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gd[a] = fmaf(dY[k][a], sk, gd[a]);
       }
       // d = v / |v|: dL/dv = (gd - d (d . gd)) / |v|
+      const double d[3] = {v0 * dn, v1 * dn, v2 * dn};
       const double dd = d[0] * gd[0] + d[1] * gd[1] + d[2] * gd[2];
-      for (int a = 0; a < 3; ++a) gmu[a] += (gd[a] - d[a] * dd) / vn;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gmu[a] += (gd[a] - d[a] * dd) * dn;
     }
 
     // ---- geometry, recomputed as in the forward
@@ -489,8 +499,17 @@ hipError_t launch_preprocess_bwd(const PreParams &p, int64_t n, const float *mea
                                  float *dmeans3d, float *dscales, float *dquats, float *dopac, float *dsh,
                                  hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(preprocess_bwd_kernel, dim3(ceil_div(n, 128)), dim3(128), 0, s, p, n, means3d, scales, quats,
-                     opac, sh, tiles, dmeans2d, dconic_opacity, drgb, dmeans3d, dscales, dquats, dopac, dsh);
+  const dim3 grid(ceil_div(n, 128)), block(128);
+#define GS_PRE_BWD(D)                                                                                           \
+  hipLaunchKernelGGL(preprocess_bwd_kernel<D>, grid, block, 0, s, p, n, means3d, scales, quats, opac, sh, tiles, \
+                     dmeans2d, dconic_opacity, drgb, dmeans3d, dscales, dquats, dopac, dsh)
+  switch (p.sh_degree) {
+    case 0: GS_PRE_BWD(0); break;
+    case 1: GS_PRE_BWD(1); break;
+    case 2: GS_PRE_BWD(2); break;
+    default: GS_PRE_BWD(3); break;
+  }
+#undef GS_PRE_BWD
   return hipGetLastError();
 }
 

@@ -7,7 +7,9 @@ gs_preprocess -> gs_bin_sort -> gs_rasterize_fwd, inputs resident in HBM.
 
 Headline: poly order 1 with the opacity-dependent radius (Eq. 4); the same
 frame with the exponential kernel and 3-sigma culling is timed on the same GPU
-for comparison. Frame times are medians over the timed frames. The same JSON
+for comparison. `value` is whole-job throughput: K frames launched back to
+back with only a synchronised event pair around them; the medians of frames
+timed with events between the stages are reported beside it. The same JSON
 line carries the kernel x culling sweep of the frame (the analogue of the
 paper's Table 3 and Table 4), the heavy-tailed 4M-splat scene over 8 orbit
 poses, the batched multi-view frame and a training step, each with per-stage
@@ -173,8 +175,19 @@ def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, t
     total_ms = start.elapsed_time(stop)
     st = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])] for e in ev])
     frame = np.array([e[0].elapsed_time(e[3]) for e in ev])
+    # the same frames back to back with no event between them: whole-job
+    # throughput (an event recorded between stages costs the stream a few us)
+    start.record(stream)
+    for s in range(steps):
+        proj = r.preprocess(scene, cam)
+        b = r.bin_sort(proj, cam)
+        r.rasterize(proj, b, cam)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    clean_ms = start.elapsed_time(stop) / steps
     res = dict(ms=float(np.median(frame)), ms_mean=total_ms / steps, ms_min=float(frame.min()),
-               ms_max=float(frame.max()), stage_ms=np.median(st, axis=0).tolist(), blend_ms=float(np.median(st[:, 2])),
+               ms_max=float(frame.max()), ms_clean=clean_ms, stage_ms=np.median(st, axis=0).tolist(),
+               blend_ms=float(np.median(st[:, 2])),
                K=int(b["num_keys"].item()), E=None, E_list=None, B=None, image=None, rast=r,
                threads=int(r.params.blend_threads), tuned=tuned)
     if count:
@@ -191,7 +204,7 @@ def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, t
 def summary(t, W, H):
     """JSON row of a timed frame configuration."""
     ms = t["ms"]
-    row = {"ms_per_step": round(ms, 4), "ms_mean": round(t["ms_mean"], 4),
+    row = {"ms_per_step": round(ms, 4), "ms_mean": round(t["ms_mean"], 4), "ms_back_to_back": round(t["ms_clean"], 4),
            "Mpix_per_s": round(W * H / (ms * 1e-3) / 1e6, 2), "keys": t["K"],
            "stage_ms": {"preprocess": round(t["stage_ms"][0], 4), "bin_sort": round(t["stage_ms"][1], 4),
                         "blend": round(t["stage_ms"][2], 4)},
@@ -534,7 +547,8 @@ def main():
               f"E={r['E']} threads={r['threads']} tuned={r['tuned']}", file=sys.stderr, flush=True)
 
     head = res["poly1"]
-    ms = head["ms"]
+    # whole-job throughput: K frames back to back, bracketed by synchronisation
+    ms = head["ms_clean"]
     mpix = W * H / (ms * 1e-3) / 1e6
     evals = head["E"] / (ms * 1e-3)
     blend_s = head["blend_ms"] * 1e-3
@@ -566,8 +580,9 @@ def main():
                                + RECT_NAMES[a.rect],
                    "splats": scene.n, "width": W, "height": H, "kernel": "poly1", "radius": "opacity",
                    "rect": RECT_NAMES[a.rect], "blend_threads": head["threads"]},
-        "ms_per_step_mean": round(head["ms_mean"], 4),
+        "ms_per_step_median": round(head["ms"], 4),
         "ms_per_step_range": [round(head["ms_min"], 4), round(head["ms_max"], 4)],
+        "ms_per_step_mean_with_stage_events": round(head["ms_mean"], 4),
         "splat_pixel_evals_per_s": round(evals, 1),
         "keys": head["K"], "evals": head["E"], "list_entries": head["E_list"], "blended": head["B"],
         "scheduled_pairs_bound": head["K"] * 256,
@@ -583,7 +598,8 @@ def main():
     out["exp_sigma3"] = summary(e, W, H)
     out["exp_sigma3"]["roofline_frac"] = round(
         e["E"] * (OPS_8D["exp"] + TRANS_SLOTS["exp"]) / (e["blend_ms"] * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4)
-    out["speedup_vs_exp_sigma3"] = round(e["ms"] / ms, 4)
+    out["speedup_vs_exp_sigma3"] = round(e["ms_clean"] / ms, 4)
+    out["speedup_vs_exp_sigma3_medians"] = round(e["ms"] / head["ms"], 4)
     done = {("poly1/opacity", False): hrow, ("exp/sigma3", False): out["exp_sigma3"]}
 
     # the same frames with the quadric on the matrix cores (gs_rasterize_fwd_mfma)
@@ -627,6 +643,8 @@ def main():
         print(f"[bench] train: {out['train_step']}", file=sys.stderr, flush=True)
     if not a.no_cpu:
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
+        # the oracle is compared with the frame the counting build rendered
+        # (identical outputs to the timed blend)
         cb, err, nflag, m = cpu_baseline(scene_np, cam, head["image"].cpu().numpy(), a.cpu_seconds, RECT_MODES[a.rect])
         out["cpu_baseline"] = cb
         out["max_abs_err_vs_oracle"] = err

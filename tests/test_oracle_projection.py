@@ -139,3 +139,24 @@ def test_radius_uses_largest_eigenvalue():
         p = core.project(sc, cam, cfg)
         lmax = np.linalg.eigvalsh(_cov2d(p)).max()
         assert p["radius"][0] == pytest.approx(k * math.sqrt(lmax) * cfg.radius_pad, rel=1e-12)
+
+
+def test_sh_ordering_and_signs_against_complex_harmonics():
+    """The basis against the textbook definition built from SciPy's complex
+    spherical harmonics (Condon-Shortley phase included): band l, order
+    m = -l..l, real Y_lm = sqrt(2) Im Y_l^|m| for m < 0, Y_l^0 for m = 0,
+    sqrt(2) Re Y_l^m for m > 0. This fixes the ordering and every sign of the
+    colour basis independently of the closed forms the reference writes."""
+    from scipy.special import sph_harm_y
+    rng = np.random.default_rng(8)
+    d = rng.normal(size=(200, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    polar, azim = np.arccos(d[:, 2]), np.arctan2(d[:, 1], d[:, 0])
+    cols = []
+    for l in range(4):
+        for m in range(-l, l + 1):
+            c = sph_harm_y(l, abs(m), polar, azim)
+            cols.append(math.sqrt(2) * c.imag if m < 0 else (c.real if m == 0 else math.sqrt(2) * c.real))
+    ref = np.stack(cols, 1)
+    Y = core.sh_basis(3, d)
+    assert np.allclose(Y, ref, atol=1e-12)

@@ -189,7 +189,7 @@ def time_config(torch, render, scene, cam, kind, order, radius, steps, warmup, t
                ms_max=float(frame.max()), ms_clean=clean_ms, stage_ms=np.median(st, axis=0).tolist(),
                blend_ms=float(np.median(st[:, 2])),
                K=int(b["num_keys"].item()), E=None, E_list=None, B=None, image=None, rast=r,
-               threads=int(r.params.blend_threads), tuned=tuned)
+               threads=int(r.params.blend_threads), stage=int(r.params.blend_stage), tuned=tuned)
     if count:
         r.mfma = False
         # untimed frame of the counting build: E = kernel evaluations performed,
@@ -208,7 +208,7 @@ def summary(t, W, H):
            "Mpix_per_s": round(W * H / (ms * 1e-3) / 1e6, 2), "keys": t["K"],
            "stage_ms": {"preprocess": round(t["stage_ms"][0], 4), "bin_sort": round(t["stage_ms"][1], 4),
                         "blend": round(t["stage_ms"][2], 4)},
-           "blend_threads": t["threads"]}
+           "blend_threads": t["threads"], "blend_stage": t["stage"]}
     if t["E"] is not None:
         row.update(evals=t["E"], list_entries=t["E_list"], blended=t["B"],
                    splat_pixel_evals_per_s=round(t["E"] / (ms * 1e-3), 1))
@@ -324,7 +324,8 @@ def time_batched(torch, render, scenes, steps, rect):
             # low-resolution views hold more copies per pixel than the 1080p frame
             "keys_per_pixel": round(K / npix, 4), "Gkeys_per_s_graph": round(K / (graph_ms * 1e-3) / 1e9, 3),
             "tuned": {"blend_threads": int(br.params.blend_threads), "workgroups": int(br.workgroups),
-                      "candidates_ms": {f"{k[0]}x{k[1]}": round(v, 3) for k, v in tuned.items()}}}
+                      "blend_stage": int(br.params.blend_stage),
+                      "candidates_ms": {f"{k[0]}x{k[1]}x{k[2]}": round(v, 3) for k, v in tuned.items()}}}
 
 
 def time_heavy(torch, render, scenes, steps, rect, only=None):
@@ -579,7 +580,8 @@ def main():
         "config": {"workload": "1M splats (64 clusters, SH3), 1920x1080, poly-1 kernel, opacity-dependent radius, "
                                + RECT_NAMES[a.rect],
                    "splats": scene.n, "width": W, "height": H, "kernel": "poly1", "radius": "opacity",
-                   "rect": RECT_NAMES[a.rect], "blend_threads": head["threads"]},
+                   "rect": RECT_NAMES[a.rect], "blend_threads": head["threads"], "blend_stage": head["stage"],
+                   "blend_tuning_ms": head["tuned"]},
         "ms_per_step_median": round(head["ms"], 4),
         "ms_per_step_range": [round(head["ms_min"], 4), round(head["ms_max"], 4)],
         "ms_per_step_mean_with_stage_events": round(head["ms_mean"], 4),

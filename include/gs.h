@@ -106,6 +106,9 @@ typedef struct {
                             (4, 2 or 1 pixels per thread); 0 = the library's default. Results
                             do not depend on it. */
   int32_t rect_mode;     /* gs_rect_mode */
+  int32_t blend_stage;   /* records each blend thread stages in LDS per batch, 1 or 2 (a batch holds
+                            blend_threads x blend_stage records); 0 = the library's default (2).
+                            Results do not depend on it. */
 } gs_params;
 
 typedef struct {
@@ -147,7 +150,7 @@ gs_status gs_kernel_order2_tile_range(int32_t radius_mode, gs_kernel *out);
 gs_status gs_kernel_root(const gs_kernel *kernel, double *x0_out);
 
 /* eps 1/255, alpha_max 0.99, t_min 1e-4, aa_v 0.3, near_z 0.2,
- * radius_pad 1 + 2^-20, bg 0, tile 16, blend_threads 0, rect_mode SQUARE. */
+ * radius_pad 1 + 2^-20, bg 0, tile 16, blend_threads 0, rect_mode SQUARE, blend_stage 0. */
 gs_status gs_params_default(gs_params *out);
 
 /* ---------------------------------------------------------------------- */

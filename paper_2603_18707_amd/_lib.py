@@ -29,7 +29,7 @@ class GsParams(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_float), ("alpha_max", ctypes.c_float), ("t_min", ctypes.c_float),
                 ("aa_v", ctypes.c_float), ("near_z", ctypes.c_float), ("radius_pad", ctypes.c_float),
                 ("bg", ctypes.c_float * 3), ("tile", ctypes.c_int32), ("blend_threads", ctypes.c_int32),
-                ("rect_mode", ctypes.c_int32)]
+                ("rect_mode", ctypes.c_int32), ("blend_stage", ctypes.c_int32)]
 
 
 class GsCamera(ctypes.Structure):

@@ -1,9 +1,11 @@
 """Launch-shape autotuner.
 
 The blend's launch shape (threads per 16x16 tile: 64, 128 or 256, i.e. 4, 2 or
-1 pixels per thread) trades per-pixel arithmetic and LDS traffic against the
-parallelism available to a tile with a long splat list; the best choice
-depends on the splat-size distribution and resolution. ``tune_blend`` times
+1 pixels per thread, each wave shading a 16x16, 8x16 or 8x8 block; and the LDS
+batch, 1 or 2 records staged per thread) trades per-pixel arithmetic, LDS
+traffic and barriers against the parallelism available to a tile with a long
+splat list; the best choice depends on the splat-size distribution and
+resolution. ``tune_blend`` times
 every candidate on the frame at hand with HIP events and keeps the fastest;
 results are cached per (device, resolution, kernel, splat-count bucket) in
 memory and, when ``cache_path`` is given, in a JSON file. Outputs do not depend
@@ -18,6 +20,7 @@ import torch
 from . import _lib as L
 
 BLEND_THREADS = (64, 128, 256)
+BLEND_STAGES = (1, 2)  # records each thread stages per batch (the LDS batch is threads x stage)
 _cache = {}
 
 
@@ -38,28 +41,31 @@ def _save(cache_path):
             json.dump(_cache, f, indent=1, sort_keys=True)
 
 
-def tune_blend(r, proj, binned, cam, candidates=BLEND_THREADS, reps: int = 5, cache_path: str = None) -> dict:
-    """Times gs_rasterize_fwd for every candidate launch shape; sets the winner
-    on r.params.blend_threads and returns {threads: ms}."""
+def tune_blend(r, proj, binned, cam, candidates=BLEND_THREADS, stages=BLEND_STAGES, reps: int = 5,
+               cache_path: str = None) -> dict:
+    """Times gs_rasterize_fwd for every candidate launch shape (threads per
+    tile x records staged per thread); sets the winner on r.params
+    (blend_threads, blend_stage) and returns {"threads x stage": ms}."""
     _load(cache_path)
     key = _key(cam, r.kernel, proj["n"])
     if key in _cache:
-        r.params.blend_threads = int(_cache[key]["best"])
+        r.params.blend_threads, r.params.blend_stage = (int(v) for v in _cache[key]["best"])
         return _cache[key]["ms"]
     stream = torch.cuda.current_stream()
     times = {}
     for nt in candidates:
-        r.params.blend_threads = int(nt)
-        r.rasterize(proj, binned, cam)  # warm
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(reps):
-            r.rasterize(proj, binned, cam)
-        b.record(stream)
-        torch.cuda.synchronize()
-        times[int(nt)] = a.elapsed_time(b) / reps
+        for sb in stages:
+            r.params.blend_threads, r.params.blend_stage = int(nt), int(sb)
+            r.rasterize(proj, binned, cam)  # warm
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                r.rasterize(proj, binned, cam)
+            b.record(stream)
+            torch.cuda.synchronize()
+            times[(int(nt), int(sb))] = a.elapsed_time(b) / reps
     best = min(times, key=times.get)
-    r.params.blend_threads = int(best)
-    _cache[key] = {"best": int(best), "ms": {str(k): v for k, v in times.items()}}
+    r.params.blend_threads, r.params.blend_stage = best
+    _cache[key] = {"best": list(best), "ms": {f"{k[0]}x{k[1]}": v for k, v in times.items()}}
     _save(cache_path)
-    return times
+    return _cache[key]["ms"]

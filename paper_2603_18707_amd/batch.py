@@ -109,22 +109,25 @@ class BatchRenderer:
                     last_contrib=self.last_contrib[po:po + W * H].view(H, W))
 
 
-def tune_batch(br: BatchRenderer, threads=(64, 128, 256), workgroups=(1024, 2048, 4096), reps: int = 3) -> dict:
-    """Times every (threads per tile, persistent workgroups) pair on the batch
-    (eager launches) and keeps the fastest; returns {(threads, wgs): ms}."""
+def tune_batch(br: BatchRenderer, threads=(64, 128, 256), workgroups=(1024, 2048, 4096), stages=(1, 2),
+               reps: int = 3) -> dict:
+    """Times every (threads per tile, persistent workgroups, records staged
+    per thread) triple on the batch (eager launches) and keeps the fastest;
+    returns {(threads, wgs, stage): ms}."""
     stream = torch.cuda.current_stream()
     res = {}
     for nt in threads:
         for wg in workgroups:
-            br.params.blend_threads, br.workgroups = int(nt), int(wg)
-            br.render()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            for _ in range(reps):
+            for sb in stages:
+                br.params.blend_threads, br.workgroups, br.params.blend_stage = int(nt), int(wg), int(sb)
                 br.render()
-            b.record(stream)
-            torch.cuda.synchronize()
-            res[(int(nt), int(wg))] = a.elapsed_time(b) / reps
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                for _ in range(reps):
+                    br.render()
+                b.record(stream)
+                torch.cuda.synchronize()
+                res[(int(nt), int(wg), int(sb))] = a.elapsed_time(b) / reps
     best = min(res, key=res.get)
-    br.params.blend_threads, br.workgroups = best
+    br.params.blend_threads, br.workgroups, br.params.blend_stage = best
     return res

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(64) void batch_preprocess(PreParams base, SceneTabl
   out.rgb[3 * o + 2] = c.z;
 }
 
-template <int KIND, int NT>
+template <int KIND, int NT, int SB>
 __global__ __launch_bounds__(NT) void batch_blend(BlendParams base, const ViewInfo *__restrict__ info,
                                                   const uint32_t *__restrict__ row_view, int grid_w,
                                                   uint32_t nitems, const uint32_t *__restrict__ ranges,
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(NT) void batch_blend(BlendParams base, const ViewIn
     p.gy = in.gy;
     const BlendOut out{images + in.image_offset, final_T + in.pixel_offset, n_contrib + in.pixel_offset,
                        last_contrib + in.pixel_offset, nullptr, nullptr};
-    blend_tile<KIND, NT>(p, (int)tx, (int)vrow - in.row_base, ranges[2 * (size_t)tile], ranges[2 * (size_t)tile + 1],
+    blend_tile<KIND, NT, false, SB>(p, (int)tx, (int)vrow - in.row_base, ranges[2 * (size_t)tile], ranges[2 * (size_t)tile + 1],
                          means2d, conic_opacity, rgb, vals, out);
   }
 }
@@ -232,21 +232,31 @@ size_t carve_batch(void *base, int nviews, int64_t pairs, int gw, int gh, int64_
   return o;
 }
 
-template <int KIND>
-void launch_batch_blend(int nt, unsigned wgs, const BlendParams &b, const BatchWs &w, int gw, uint32_t nitems,
-                        float *images, float *final_T, uint32_t *n_contrib, uint32_t *last_contrib, hipStream_t s) {
+template <int KIND, int SB>
+void launch_batch_blend_stage(int nt, unsigned wgs, const BlendParams &b, const BatchWs &w, int gw, uint32_t nitems,
+                              float *images, float *final_T, uint32_t *n_contrib, uint32_t *last_contrib,
+                              hipStream_t s) {
   if (nt == 64)
-    hipLaunchKernelGGL((batch_blend<KIND, 64>), dim3(wgs), dim3(64), 0, s, b, w.info, w.row_view, gw, nitems,
+    hipLaunchKernelGGL((batch_blend<KIND, 64, SB>), dim3(wgs), dim3(64), 0, s, b, w.info, w.row_view, gw, nitems,
                        w.ranges, w.order, w.means2d, w.conic_opacity, w.rgb, w.vals, images, final_T, n_contrib,
                        last_contrib, w.counter);
   else if (nt == 128)
-    hipLaunchKernelGGL((batch_blend<KIND, 128>), dim3(wgs), dim3(128), 0, s, b, w.info, w.row_view, gw, nitems,
+    hipLaunchKernelGGL((batch_blend<KIND, 128, SB>), dim3(wgs), dim3(128), 0, s, b, w.info, w.row_view, gw, nitems,
                        w.ranges, w.order, w.means2d, w.conic_opacity, w.rgb, w.vals, images, final_T, n_contrib,
                        last_contrib, w.counter);
   else
-    hipLaunchKernelGGL((batch_blend<KIND, 256>), dim3(wgs), dim3(256), 0, s, b, w.info, w.row_view, gw, nitems,
+    hipLaunchKernelGGL((batch_blend<KIND, 256, SB>), dim3(wgs), dim3(256), 0, s, b, w.info, w.row_view, gw, nitems,
                        w.ranges, w.order, w.means2d, w.conic_opacity, w.rgb, w.vals, images, final_T, n_contrib,
                        last_contrib, w.counter);
+}
+
+template <int KIND>
+void launch_batch_blend(int nt, unsigned wgs, const BlendParams &b, const BatchWs &w, int gw, uint32_t nitems,
+                        float *images, float *final_T, uint32_t *n_contrib, uint32_t *last_contrib, hipStream_t s) {
+  if (b.stage == 1)
+    launch_batch_blend_stage<KIND, 1>(nt, wgs, b, w, gw, nitems, images, final_T, n_contrib, last_contrib, s);
+  else
+    launch_batch_blend_stage<KIND, 2>(nt, wgs, b, w, gw, nitems, images, final_T, n_contrib, last_contrib, s);
 }
 
 }  // namespace

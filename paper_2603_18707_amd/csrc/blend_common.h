@@ -187,7 +187,7 @@ __device__ inline void pass_box(const float4 &co, float xe_f, float &hx, float &
 // pixels) over its sorted list [start, end) of splat indices into `out`
 // (pointers to this image's planes). Called by NT threads of a workgroup.
 //
-// Splats are staged NT at a time. Each staged record gets a bit per wave of
+// Splats are staged NT x SB at a time (SB per thread). Each staged record gets a bit per wave of
 // the workgroup telling whether its pass box meets the pixel block that wave
 // shades; every wave then walks a compacted list of its records, still in
 // list order, so splats that cannot reach a wave's pixels cost it nothing.
@@ -195,7 +195,7 @@ __device__ inline void pass_box(const float4 &co, float xe_f, float &hx, float &
 // COUNT adds a per-pixel count of the kernel evaluations performed (entries
 // of the wave's list while the pixel is alive, the one that stops it
 // included), written to out.n_tested: a measurement build, not for rendering.
-template <int KIND, int NT, bool COUNT = false>
+template <int KIND, int NT, bool COUNT = false, int SB = 1>
 __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t start, uint32_t end,
                                   const float *__restrict__ means2d, const float *__restrict__ conic_opacity,
                                   const float *__restrict__ rgb, const uint32_t *__restrict__ vals,
@@ -208,10 +208,11 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
   constexpr int WY = TS * TS / NW / WX;
   constexpr int RS = WAVE / WX;     // row stride between a lane's pixels
   constexpr int G = 8;              // splats tested per step
+  constexpr int NB = NT * SB;       // records staged per batch (SB per thread)
   static_assert(NT % G == 0 && G == 8, "a staged batch holds whole steps of eight 16-bit slots");
-  __shared__ float4 L0[NT + 1], L1[NT + 1], L2[NT + 1];   // slot NT: neutral record
-  __shared__ __align__(16) uint16_t lst[NW][NT + G];  // rows of 16-byte multiples, read 8 slots at a time
-  __shared__ uint32_t wcnt[NW][NW];                      // [staging wave][shading wave]
+  __shared__ float4 L0[NB + 1], L1[NB + 1], L2[NB + 1];   // slot NB: neutral record
+  __shared__ __align__(16) uint16_t lst[NW][NB + G];  // rows of 16-byte multiples, read 8 slots at a time
+  __shared__ uint32_t wcnt[SB][NW][NW];                  // [staging round][staging wave][shading wave]
   const int lane = threadIdx.x, wv = lane / WAVE;
   const uint64_t lt = (1ull << (lane & (WAVE - 1))) - 1ull;
   const int wx0 = (wv % (TS / WX)) * WX, wy0 = (wv / (TS / WX)) * WY;
@@ -234,60 +235,77 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
   }
   if (lane == 0) {
     // zero quadric and threshold -1: t = -1 everywhere
-    L0[NT] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    L1[NT] = make_float4(0.0f, -1.0f, 0.0f, 0.0f);
+    L0[NB] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    L1[NB] = make_float4(0.0f, -1.0f, 0.0f, 0.0f);
   }
   const float tile_x0 = (float)(tx * TS), tile_y0 = (float)(ty * TS);
 
-  for (uint32_t b = start; b < end; b += NT) {
+  for (uint32_t b = start; b < end; b += NB) {
     bool any = false;
 #pragma unroll
     for (int k = 0; k < P; ++k) any = any || alive[k];
     if (__syncthreads_or(any) == 0) break;  // every pixel of the tile has terminated
-    const uint32_t idx = b + lane;
-    uint32_t mask = 0u;
-    if (idx < end) {
-      uint32_t id = vals[idx];
-      if (id >= p.n) id = 0;  // never taken for a list built by gs_bin_sort over these n splats
-      const float2 m = reinterpret_cast<const float2 *>(means2d)[id];
-      const float4 co = reinterpret_cast<const float4 *>(conic_opacity)[id];
-      const float3 c = make_float3(rgb[3 * id], rgb[3 * id + 1], rgb[3 * id + 2]);
-      float4 a0, a1, a2;
-      fold<KIND>(m, co, c, tile_x0, tile_y0, p, a0, a1, a2);
-      L0[lane] = a0;
-      L1[lane] = a1;
-      L2[lane] = a2;
-      float hx, hy;
-      pass_box(co, a1.y, hx, hy);
+    uint32_t mask[SB];
 #pragma unroll
-      for (int w = 0; w < NW; ++w) {
-        // first pixel centre of wave w's block, tile-local like the record
-        const float bx = 0.5f + (float)((w % (TS / WX)) * WX), by = 0.5f + (float)((w / (TS / WX)) * WY);
-        if (a0.x + hx >= bx && a0.x - hx <= bx + (float)(WX - 1) && a0.y + hy >= by &&
-            a0.y - hy <= by + (float)(WY - 1))
-          mask |= 1u << w;
+    for (int r = 0; r < SB; ++r) {
+      const int slot = lane + r * NT;  // list order: slot b + slot
+      const uint32_t idx = b + slot;
+      mask[r] = 0u;
+      if (idx < end) {
+        uint32_t id = vals[idx];
+        if (id >= p.n) id = 0;  // never taken for a list built by gs_bin_sort over these n splats
+        const float2 m = reinterpret_cast<const float2 *>(means2d)[id];
+        const float4 co = reinterpret_cast<const float4 *>(conic_opacity)[id];
+        const float3 c = make_float3(rgb[3 * id], rgb[3 * id + 1], rgb[3 * id + 2]);
+        float4 a0, a1, a2;
+        fold<KIND>(m, co, c, tile_x0, tile_y0, p, a0, a1, a2);
+        L0[slot] = a0;
+        L1[slot] = a1;
+        L2[slot] = a2;
+        float hx, hy;
+        pass_box(co, a1.y, hx, hy);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          // first pixel centre of wave w's block, tile-local like the record
+          const float bx = 0.5f + (float)((w % (TS / WX)) * WX), by = 0.5f + (float)((w / (TS / WX)) * WY);
+          if (a0.x + hx >= bx && a0.x - hx <= bx + (float)(WX - 1) && a0.y + hy >= by &&
+              a0.y - hy <= by + (float)(WY - 1))
+            mask[r] |= 1u << w;
+        }
       }
     }
-    uint64_t bal[NW];
+    uint64_t bal[SB][NW];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) bal[w] = __ballot((mask >> w) & 1u);
+    for (int r = 0; r < SB; ++r)
+#pragma unroll
+      for (int w = 0; w < NW; ++w) bal[r][w] = __ballot((mask[r] >> w) & 1u);
     if ((lane & (WAVE - 1)) == 0) {
 #pragma unroll
-      for (int w = 0; w < NW; ++w) wcnt[wv][w] = (uint32_t)__popcll(bal[w]);
+      for (int r = 0; r < SB; ++r)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) wcnt[r][wv][w] = (uint32_t)__popcll(bal[r][w]);
     }
     __syncthreads();
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-      if ((mask >> w) & 1u) {
-        uint32_t off = (uint32_t)__popcll(bal[w] & lt);
-        for (int s = 0; s < wv; ++s) off += wcnt[s][w];
-        lst[w][off] = (uint16_t)lane;
+      uint32_t base = 0;  // shading wave w's records of the earlier rounds
+#pragma unroll
+      for (int r = 0; r < SB; ++r) {
+        if ((mask[r] >> w) & 1u) {
+          uint32_t off = base + (uint32_t)__popcll(bal[r][w] & lt);
+          for (int s = 0; s < wv; ++s) off += wcnt[r][s][w];
+          lst[w][off] = (uint16_t)(lane + r * NT);
+        }
+#pragma unroll
+        for (int s = 0; s < NW; ++s) base += wcnt[r][s][w];
       }
     }
     uint32_t len = 0;
 #pragma unroll
-    for (int s = 0; s < NW; ++s) len += wcnt[s][wv];
-    if ((lane & (WAVE - 1)) < G) lst[wv][len + (lane & (WAVE - 1))] = (uint16_t)NT;
+    for (int r = 0; r < SB; ++r)
+#pragma unroll
+      for (int s = 0; s < NW; ++s) len += wcnt[r][s][wv];
+    if ((lane & (WAVE - 1)) < G) lst[wv][len + (lane & (WAVE - 1))] = (uint16_t)NB;
     __syncthreads();
     if (any) {
       // G splats per step: all G records are read and tested before the one
@@ -317,7 +335,7 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
         if (COUNT && !(mx >= 0.0f)) {
           uint32_t nreal = 0;
 #pragma unroll
-          for (int q = 0; q < G; ++q) nreal += js[q] != NT;
+          for (int q = 0; q < G; ++q) nreal += js[q] != NB;
 #pragma unroll
           for (int k = 0; k < P; ++k) tested[k] += alive[k] ? nreal : 0u;
         }
@@ -333,7 +351,7 @@ __device__ inline void blend_tile(const BlendParams &p, int tx, int ty, uint32_t
             const uint32_t pos = b + (uint32_t)js[q] - start + 1;
 #pragma unroll
             for (int k = 0; k < P; ++k) {
-              if (COUNT && js[q] != NT && alive[k]) ++tested[k];
+              if (COUNT && js[q] != NB && alive[k]) ++tested[k];
               if (t[q][k] >= 0.0f && alive[k]) {  // the stop-or-blend choice below is by selects
                 const float a = alpha_from<KIND>(t[q][k], s1v[q], p);
                 const float Tn = T[k] * (1.0f - a);

@@ -81,6 +81,8 @@ gs_status check_params(const gs_params *p) {
     return fail(GS_EINVAL, "blend_threads %d must be 0, 64, 128 or 256", p->blend_threads);
   if (p->rect_mode != GS_RECT_SQUARE && p->rect_mode != GS_RECT_ELLIPSE_BOX)
     return fail(GS_EINVAL, "rect_mode %d must be 0 (square) or 1 (ellipse box)", p->rect_mode);
+  if (p->blend_stage < 0 || p->blend_stage > 2)
+    return fail(GS_EINVAL, "blend_stage %d must be 0, 1 or 2", p->blend_stage);
   return GS_OK;
 }
 
@@ -201,6 +203,7 @@ gs_status gs_params_default(gs_params *out) {
   out->tile = 16;
   out->blend_threads = 0;
   out->rect_mode = GS_RECT_SQUARE;
+  out->blend_stage = 0;
   return GS_OK;
 }
 
@@ -332,6 +335,7 @@ static gs_status make_kernel_params(const gs_kernel *kernel, const gs_params *pa
   b->t_min = params->t_min;
   for (int i = 0; i < 3; ++i) b->bg[i] = params->bg[i];
   b->threads = params->blend_threads ? params->blend_threads : 256;
+  b->stage = params->blend_stage ? params->blend_stage : 2;
   return GS_OK;
 }
 
@@ -598,6 +602,7 @@ gs_status gs_render_batched(const gs_kernel *kernel, const gs_params *params, co
   b.t_min = params->t_min;
   for (int i = 0; i < 3; ++i) b.bg[i] = params->bg[i];
   b.threads = params->blend_threads ? params->blend_threads : 256;
+  b.stage = params->blend_stage ? params->blend_stage : 2;
   return check_hip(launch_batch(p, b, scenes, num_scenes, views_device, num_views, pairs, gw, gh, key_capacity,
                                 workgroups, workspace, images, images_len, final_T, n_contrib, last_contrib,
                                 planes_len, num_keys, overflow, view_keys, (hipStream_t)stream),

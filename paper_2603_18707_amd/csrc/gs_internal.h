@@ -100,6 +100,7 @@ struct BlendParams {
   float eps, alpha_max, t_min;
   float log2_eps;        // log2(eps), for the exponential's threshold
   int threads;           // blend workgroup size per tile: 64, 128 or 256
+  int stage;             // records each thread stages per batch: 1 or 2
   float bg[3];
 };
 

@@ -4,9 +4,9 @@
 // tile, P = 256 / NT pixels per lane. Each wave shades a compact block of the
 // tile (an 8x8 quarter with 256 threads, an 8x16 half with 128, the whole
 // tile with 64); a lane's P pixels share a column. The tile's list is walked
-// in batches of NT; each lane gathers one splat record, folds the kernel's
-// constants into it and stages it in LDS, then every lane reads the batch by
-// broadcast.
+// in batches of NT x SB (SB = 1 or 2 records per lane, a launch parameter);
+// each lane gathers its records, folds the kernel's constants into them and
+// stages them in LDS, then every lane reads the batch by broadcast.
 //
 // Every kernel here is decreasing in the quadric Q on the part of its support
 // that matters, so "alpha >= eps" is the same decision as "Q <= x_e", where
@@ -36,7 +36,7 @@ namespace gs {
 
 namespace {
 
-template <int KIND, int NT, bool COUNT>
+template <int KIND, int NT, bool COUNT, int SB>
 __global__ __launch_bounds__(NT) void blend_fwd(BlendParams p, const float *__restrict__ means2d,
                                                 const float *__restrict__ conic_opacity,
                                                 const float *__restrict__ rgb, const uint32_t *__restrict__ vals,
@@ -45,24 +45,33 @@ __global__ __launch_bounds__(NT) void blend_fwd(BlendParams p, const float *__re
   const int ntiles = p.gx * p.gy;
   if ((int)blockIdx.x >= ntiles) return;
   const int tile = tile_order ? (int)min(tile_order[blockIdx.x], (uint32_t)(ntiles - 1)) : (int)blockIdx.x;
-  blend_tile<KIND, NT, COUNT>(p, tile % p.gx, tile / p.gx, ranges[2 * tile], ranges[2 * tile + 1], means2d, conic_opacity,
+  blend_tile<KIND, NT, COUNT, SB>(p, tile % p.gx, tile / p.gx, ranges[2 * tile], ranges[2 * tile + 1], means2d, conic_opacity,
                        rgb, vals, out);
+}
+
+template <int KIND, bool COUNT, int SB>
+void launch_stage(const BlendParams &p, const float *means2d, const float *conic_opacity, const float *rgb,
+                  const uint32_t *vals, const uint32_t *ranges, const uint32_t *order, BlendOut out, hipStream_t s) {
+  const dim3 grid(p.gx * p.gy);
+  if (p.threads == 64)
+    hipLaunchKernelGGL((blend_fwd<KIND, 64, COUNT, SB>), grid, dim3(64), 0, s, p, means2d, conic_opacity, rgb, vals,
+                       ranges, order, out);
+  else if (p.threads == 128)
+    hipLaunchKernelGGL((blend_fwd<KIND, 128, COUNT, SB>), grid, dim3(128), 0, s, p, means2d, conic_opacity, rgb,
+                       vals, ranges, order, out);
+  else
+    hipLaunchKernelGGL((blend_fwd<KIND, 256, COUNT, SB>), grid, dim3(256), 0, s, p, means2d, conic_opacity, rgb,
+                       vals, ranges, order, out);
 }
 
 template <int KIND, bool COUNT>
 hipError_t launch_shape(const BlendParams &p, const float *means2d, const float *conic_opacity, const float *rgb,
                         const uint32_t *vals, const uint32_t *ranges, const uint32_t *order, BlendOut out,
                         hipStream_t s) {
-  const dim3 grid(p.gx * p.gy);
-  if (p.threads == 64)
-    hipLaunchKernelGGL((blend_fwd<KIND, 64, COUNT>), grid, dim3(64), 0, s, p, means2d, conic_opacity, rgb, vals,
-                       ranges, order, out);
-  else if (p.threads == 128)
-    hipLaunchKernelGGL((blend_fwd<KIND, 128, COUNT>), grid, dim3(128), 0, s, p, means2d, conic_opacity, rgb, vals,
-                       ranges, order, out);
+  if (p.stage == 1)
+    launch_stage<KIND, COUNT, 1>(p, means2d, conic_opacity, rgb, vals, ranges, order, out, s);
   else
-    hipLaunchKernelGGL((blend_fwd<KIND, 256, COUNT>), grid, dim3(256), 0, s, p, means2d, conic_opacity, rgb, vals,
-                       ranges, order, out);
+    launch_stage<KIND, COUNT, 2>(p, means2d, conic_opacity, rgb, vals, ranges, order, out, s);
   return hipGetLastError();
 }
 

@@ -108,6 +108,9 @@ def test_device_calls_reject_bad_arguments_on_host():
     p2 = L.gs_params_default()
     p2.near_z = 0.0
     _expect(L.GS_EINVAL, L.gs_preprocess, cam, k, p2, 0, *null8, 0, *out6)
+    p2 = L.gs_params_default()
+    p2.blend_stage = 3
+    assert "blend_stage" in _expect(L.GS_EINVAL, L.gs_preprocess, cam, k, p2, 0, *null8, 0, *out6)
     c2 = L.make_camera(_Cam())
     c2.width = 0
     _expect(L.GS_EINVAL, L.gs_preprocess, c2, k, p, 0, *null8, 0, *out6)

@@ -232,13 +232,15 @@ def test_scene_scale_sampled(scene_1m, kind, order, radius):
 
 @pytest.mark.parametrize("kind,order,radius", [("poly", 1, "opacity"), ("exp", 1, "sigma3"), ("poly", 3, "opacity")])
 def test_launch_shape_does_not_change_results(kind, order, radius):
-    """The blend's threads-per-tile launch parameter (the autotuner's knob) gives bit-identical outputs."""
+    """The blend's launch parameters (the autotuner's knobs: threads per tile
+    and records staged per thread) give bit-identical outputs."""
     scene, cam = scenes.workload_tiny()
     scene.scales *= 2.0
     outs = []
     for nt in (64, 128, 256):
-        g = _gpu_frame(scene, cam, kind, order, radius, params=H.gpu_params(blend_threads=nt))
-        outs.append([_np(g[k]).copy() for k in ("image", "final_T", "n_contrib", "last_contrib", "n_eval")])
+        for sb in (1, 2):
+            g = _gpu_frame(scene, cam, kind, order, radius, params=H.gpu_params(blend_threads=nt, blend_stage=sb))
+            outs.append([_np(g[k]).copy() for k in ("image", "final_T", "n_contrib", "last_contrib", "n_eval")])
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)

@@ -684,23 +684,48 @@ __global__ __launch_bounds__(BS) void cull_count(uint32_t n, const uint32_t *__r
 // esum -> exclusive prefix in place (one workgroup, each thread a contiguous
 // chunk: its loads are independent and overlap); K, overflow and the key
 // counter from the total
-__global__ __launch_bounds__(BS) void cull_scan(uint64_t *__restrict__ esum, uint32_t parts, uint64_t capacity,
-                                                uint32_t *__restrict__ ctr, int64_t *num_keys, int32_t *overflow) {
-  const uint32_t per = (parts + BS - 1) / BS, b = threadIdx.x * per, e = b + per < parts ? b + per : parts;
-  uint64_t sum = 0;
-  for (uint32_t i = b; i < e; ++i) sum += esum[i];
-  uint64_t total;
-  uint64_t off = block_exclusive<uint64_t>(sum, total);
-  for (uint32_t i = b; i < e; ++i) {
-    const uint64_t v = esum[i];
-    esum[i] = off;
-    off += v;
+// One workgroup of CS_THREADS scans the partition sums in tiles of
+// CS_THREADS x CS_ITEMS consecutive sums, all of a tile's loads in flight
+// together, carrying the running total from tile to tile.
+constexpr int CS_THREADS = 1024, CS_ITEMS = 4;
+
+__global__ __launch_bounds__(CS_THREADS) void cull_scan(uint64_t *__restrict__ esum, uint32_t parts,
+                                                        uint64_t capacity, uint32_t *__restrict__ ctr,
+                                                        int64_t *num_keys, int32_t *overflow) {
+  __shared__ uint64_t wsum[CS_THREADS / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint64_t carry = 0;
+  for (uint32_t t0 = 0; t0 < parts; t0 += CS_THREADS * CS_ITEMS) {
+    const uint32_t b = t0 + threadIdx.x * CS_ITEMS;
+    uint64_t v[CS_ITEMS], sum = 0;
+#pragma unroll
+    for (int j = 0; j < CS_ITEMS; ++j) {
+      v[j] = b + j < parts ? esum[b + j] : 0ull;
+      sum += v[j];
+    }
+    const uint64_t inc = wave_inclusive<uint64_t>(sum);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint64_t off = carry + inc - sum, tot = 0;
+#pragma unroll
+    for (int k = 0; k < CS_THREADS / 64; ++k) {
+      const uint64_t x = wsum[k];
+      if (k < w) off += x;
+      tot += x;
+    }
+    __syncthreads();  // wsum is reused by the next tile
+#pragma unroll
+    for (int j = 0; j < CS_ITEMS; ++j) {
+      if (b + j < parts) esum[b + j] = off;
+      off += v[j];
+    }
+    carry += tot;
   }
   if (threadIdx.x == 0) {
-    const bool over = total > capacity;
-    *num_keys = (int64_t)total;
+    const bool over = carry > capacity;
+    *num_keys = (int64_t)carry;
     *overflow = over ? 1 : 0;
-    ctr[CTR_KEYS] = over ? 0u : (uint32_t)total;
+    ctr[CTR_KEYS] = over ? 0u : (uint32_t)carry;
   }
 }
 
@@ -1430,7 +1455,7 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
     const unsigned egrid = ceil_div(n, EPART), cgrid = ceil_div(n, BS);
     if (cu) {
       hipLaunchKernelGGL(cull_count, dim3(cgrid), dim3(BS), 0, s, (uint32_t)n, perm, tiles, rect, *cu, w.esum);
-      hipLaunchKernelGGL(cull_scan, dim3(1), dim3(BS), 0, s, w.esum, cgrid, (uint64_t)capacity, w.ctr, num_keys,
+      hipLaunchKernelGGL(cull_scan, dim3(1), dim3(CS_THREADS), 0, s, w.esum, cgrid, (uint64_t)capacity, w.ctr, num_keys,
                          overflow);
     } else {
       hipLaunchKernelGGL(emit_sums, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, tiles, perm, w.esum,

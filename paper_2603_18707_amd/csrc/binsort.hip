@@ -8,7 +8,7 @@
 //     stable LSD radix sort on the ceil(log2 tiles) tile bits only (two 7-bit
 //     passes at 1080p), so inside a tile they stay in index order;
 //  2. each tile's list is sorted stably by depth bits: by one wave when it
-//     holds at most 254 copies, by a workgroup in LDS up to 1024 copies (2048
+//     holds at most 510 copies, by a workgroup in LDS up to 1024 copies (2048
 //     when the capacity holds 512 or more per tile) and in chunks of that
 //     size through global memory beyond, all in one kernel (longest lists
 //     dispatched first, so they overlap the rest). Keys are offset by the
@@ -378,13 +378,61 @@ struct Emit {
 
 // Offsets from the partition sums before this one, then every copy of the
 // partition written by the whole workgroup (consecutive threads write
-// consecutive keys), counting the tile digits as they are written.
+// consecutive keys), counting the tile digits as they are written. The
+// copies are taken EWIN at a time: each splat marks the window position of
+// its first copy with its local index, and an inclusive max-scan over the
+// window gives every position its splat (splats in order, so the last mark
+// at or before a position is its splat), one LDS read per copy instead of a
+// binary search.
+constexpr int EWIN = BS * 8;            // copies per window
+static_assert(EPART <= 65536, "local splat indices are 16-bit");
+
+// inclusive max-scan over m[0..EWIN) (8 consecutive entries per thread),
+// starting from `carry`; returns the window's last value
+__device__ inline uint32_t window_max_scan(uint16_t *m, uint32_t carry, uint32_t *wmax) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint4 raw = reinterpret_cast<uint4 *>(m)[threadIdx.x];
+  uint32_t v[8] = {raw.x & 0xFFFFu, raw.x >> 16, raw.y & 0xFFFFu, raw.y >> 16,
+                   raw.z & 0xFFFFu, raw.z >> 16, raw.w & 0xFFFFu, raw.w >> 16};
+#pragma unroll
+  for (int i = 1; i < 8; ++i) v[i] = max(v[i], v[i - 1]);
+  uint32_t inc = v[7];
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)inc, o, 64);
+    if (lane >= o) inc = max(inc, y);
+  }
+  if (lane == 63) wmax[w] = inc;
+  uint32_t before = (uint32_t)__shfl_up((int)inc, 1, 64);
+  if (lane == 0) before = 0u;
+  __syncthreads();
+  uint32_t pre = carry;
+#pragma unroll
+  for (int k = 0; k < BS / 64; ++k)
+    if (k < w) pre = max(pre, wmax[k]);
+  pre = max(pre, before);
+  uint32_t last = carry;
+#pragma unroll
+  for (int k = 0; k < BS / 64; ++k) last = max(last, wmax[k]);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = max(v[i], pre);
+  raw.x = v[0] | (v[1] << 16);
+  raw.y = v[2] | (v[3] << 16);
+  raw.z = v[4] | (v[5] << 16);
+  raw.w = v[6] | (v[7] << 16);
+  reinterpret_cast<uint4 *>(m)[threadIdx.x] = raw;
+  return last;
+}
+
 __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
-  __shared__ uint32_t loff[EPART + 1];   // local exclusive offsets of the partition's splats
+  __shared__ uint32_t loff[EPART];       // local exclusive offsets of the partition's splats
   __shared__ uint32_t sbits[EPART];
   __shared__ int32_t sx[EPART], sy[EPART], sw[EPART];
+  __shared__ float sinv[EPART];          // 1 / width
   __shared__ uint32_t ssp[EPART];        // splat of each emission position
   __shared__ uint32_t th[MAX_TILE_PASSES * RADIX];
+  __shared__ __align__(16) uint16_t owner[EWIN];
+  __shared__ uint32_t wmax[BS / 64];
   const uint32_t nparts = (uint32_t)(((uint64_t)a.n + EPART - 1) / EPART);
   const uint32_t part = blockIdx.x;
   for (int j = threadIdx.x; j < MAX_TILE_PASSES * RADIX; j += BS) th[j] = 0u;
@@ -411,10 +459,12 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
     *a.overflow = over ? 1 : 0;
     a.ctr[CTR_KEYS] = over ? 0u : (uint32_t)K;
   }
+  uint32_t first[EIPT];  // local offset of each of this thread's splats
 #pragma unroll
   for (int j = 0; j < EIPT; ++j) {
     const int ls = threadIdx.x * EIPT + j;
-    loff[ls] = (uint32_t)off;  // only used when the partition fits the capacity (< 2^32)
+    first[j] = (uint32_t)off;  // only used when the partition fits the capacity (< 2^32)
+    loff[ls] = (uint32_t)off;
     off += c[j];
     if (c[j]) {
       const int4 r = reinterpret_cast<const int4 *>(a.rect)[sp[j]];
@@ -423,33 +473,49 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
       sx[ls] = r.x;
       sy[ls] = r.y;
       sw[ls] = r.z - r.x + 1;
+      sinv[ls] = r.z >= r.x ? 1.0f / (float)(r.z - r.x + 1) : 0.0f;
     }
   }
-  if (threadIdx.x == BS - 1) loff[EPART] = (uint32_t)off;
-  __syncthreads();
-  if (pre + total > a.capacity || total == 0) return;  // an overflowing call writes no key
+  if (pre + total > a.capacity || total == 0) return;  // an overflowing call writes no key (uniform)
   const uint32_t T = (uint32_t)total;
   const uint32_t dmask = (1u << a.tile_bits) - 1u;
-  for (uint32_t k = threadIdx.x; k < T; k += BS) {
-    uint32_t lo = 0, hi = EPART;  // loff[lo] <= k < loff[hi]
+  uint32_t carry = 0;
+  for (uint32_t k0 = 0; k0 < T; k0 += EWIN) {  // uniform trip count
+    reinterpret_cast<uint4 *>(owner)[threadIdx.x] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();  // also orders the staging above before its readers
 #pragma unroll
-    for (int it = 0; it < 10; ++it) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (loff[mid] <= k) lo = mid; else hi = mid;
+    for (int j = 0; j < EIPT; ++j)
+      if (c[j] && first[j] >= k0 && first[j] - k0 < (uint32_t)EWIN)
+        owner[first[j] - k0] = (uint16_t)(threadIdx.x * EIPT + j);
+    __syncthreads();
+    carry = window_max_scan(owner, carry, wmax);
+    __syncthreads();
+    const uint32_t m = T - k0 < (uint32_t)EWIN ? T - k0 : (uint32_t)EWIN;
+    for (uint32_t i = threadIdx.x; i < m; i += BS) {
+      const uint32_t ls = owner[i];
+      const uint32_t r = k0 + i - loff[ls];
+      const int32_t wdt = sw[ls];
+      if (wdt <= 0) continue;  // counts that disagree with the rectangle
+      // r / wdt: below 2^22 the float product is within 1/2 of the quotient,
+      // so one correction step makes it exact
+      uint32_t q;
+      if (r < (1u << 22)) {
+        q = (uint32_t)((float)r * sinv[ls]);
+        if (q * (uint32_t)wdt > r) --q;
+        else if ((q + 1u) * (uint32_t)wdt <= r) ++q;
+      } else {
+        q = r / (uint32_t)wdt;
+      }
+      const uint32_t tile = (uint32_t)(sy[ls] + (int32_t)q) * (uint32_t)a.grid_w +
+                            (uint32_t)(sx[ls] + (int32_t)(r - q * (uint32_t)wdt));
+      const uint64_t pos = pre + k0 + i;
+      a.tkey[pos] = tile;
+      a.tval[pos] = ssp[ls];
+      a.tbits[pos] = sbits[ls];
+      for (int p = 0; p < a.tile_passes; ++p) atomicAdd(&th[p * RADIX + ((tile >> (p * a.tile_bits)) & dmask)], 1u);
     }
-    const uint32_t r = k - loff[lo];
-    const int32_t wdt = sw[lo];
-    if (wdt <= 0) continue;  // counts that disagree with the rectangle
-    const uint32_t q = r / (uint32_t)wdt;
-    const uint32_t tile = (uint32_t)(sy[lo] + (int32_t)q) * (uint32_t)a.grid_w +
-                          (uint32_t)(sx[lo] + (int32_t)(r - q * (uint32_t)wdt));
-    const uint64_t pos = pre + k;
-    a.tkey[pos] = tile;
-    a.tval[pos] = ssp[lo];
-    a.tbits[pos] = sbits[lo];
-    for (int p = 0; p < a.tile_passes; ++p) atomicAdd(&th[p * RADIX + ((tile >> (p * a.tile_bits)) & dmask)], 1u);
+    __syncthreads();  // the window's readers are done before it is cleared
   }
-  __syncthreads();
   const int stripe = blockIdx.x % STRIPES;
   for (int j = threadIdx.x; j < a.tile_passes * RADIX; j += BS) {
     const uint32_t v = th[j];
@@ -812,15 +878,16 @@ __global__ void tile_ranges(const void *__restrict__ tkey, const uint32_t *__res
   if (k + 1 == K || at(k + 1) != t) ranges[2 * (size_t)t + 1] = (uint32_t)(k + 1);
 }
 
-// Lists of at most WAVE_MAX copies are sorted by one wave alone. Length
-// buckets are floor(16 log2(len + 1)): 254 copies fall in bucket 127 and
-// 255 in bucket 128, so in the longest-first order every longer list comes
-// before every such one, and the order kernel records where they start.
-constexpr uint32_t WAVE_MAX = 254;
-constexpr int WAVE_BUCKET = 127;
+// Lists of at most WAVE_MAX copies are sorted by one wave alone (four
+// copies per lane up to WAVE_SHORT, else eight). Length buckets are
+// floor(16 log2(len + 1)): 510 copies fall in bucket 143 and 511 in bucket
+// 144, so in the longest-first order every longer list comes before every
+// such one, and the order kernel records where they start.
+constexpr uint32_t WAVE_MAX = 510;
+constexpr int WAVE_BUCKET = 143;
+constexpr uint32_t WAVE_SHORT = 256;
 
-__device__ inline int length_bucket(const uint32_t *ranges, int64_t t) {
-  const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+__device__ inline int bucket_of_length(uint32_t len) {
   const int b = (int)(log2f((float)len + 1.0f) * 16.0f);
   return 255 - (b < 255 ? b : 255);
 }
@@ -828,7 +895,7 @@ __device__ inline int length_bucket(const uint32_t *ranges, int64_t t) {
 // One workgroup; each thread takes tiles tid + 1024 k in groups of ORD_ITEMS,
 // all of a group's range loads in flight together (the kernel is a few
 // dependent round trips to memory, so their number sets its time), and keeps
-// the buckets of the first group for the scatter.
+// the ranges and buckets of the first group for the scatter.
 constexpr int ORD_THREADS = 1024, ORD_ITEMS = 8;
 
 __global__ __launch_bounds__(ORD_THREADS) void tile_order_kernel(const uint32_t *__restrict__ ranges, int64_t ntiles,
@@ -841,17 +908,23 @@ __global__ __launch_bounds__(ORD_THREADS) void tile_order_kernel(const uint32_t 
   __syncthreads();
   constexpr int64_t GROUP = (int64_t)ORD_THREADS * ORD_ITEMS;
   int first[ORD_ITEMS];
+  uint2 frng[ORD_ITEMS];
   for (int64_t g0 = 0; g0 < ntiles; g0 += GROUP) {
-    int b[ORD_ITEMS];
+    uint2 rg[ORD_ITEMS];
 #pragma unroll
     for (int k = 0; k < ORD_ITEMS; ++k) {
       const int64_t t = g0 + threadIdx.x + (int64_t)k * ORD_THREADS;
-      b[k] = t < ntiles ? length_bucket(ranges, t) : -1;
+      rg[k] = t < ntiles ? make_uint2(ranges[2 * t], ranges[2 * t + 1]) : make_uint2(0u, 0u);
     }
 #pragma unroll
     for (int k = 0; k < ORD_ITEMS; ++k) {
-      if (b[k] >= 0) atomicAdd(&hist[b[k]], 1u);
-      if (g0 == 0) first[k] = b[k];
+      const int64_t t = g0 + threadIdx.x + (int64_t)k * ORD_THREADS;
+      const int b = t < ntiles ? bucket_of_length(rg[k].y - rg[k].x) : -1;
+      if (b >= 0) atomicAdd(&hist[b], 1u);
+      if (g0 == 0) {
+        first[k] = b;
+        frng[k] = rg[k];
+      }
     }
   }
   __syncthreads();
@@ -871,10 +944,17 @@ __global__ __launch_bounds__(ORD_THREADS) void tile_order_kernel(const uint32_t 
   __syncthreads();
   for (int64_t g0 = 0; g0 < ntiles; g0 += GROUP) {
     int b[ORD_ITEMS];
+    uint2 rg[ORD_ITEMS];
 #pragma unroll
     for (int k = 0; k < ORD_ITEMS; ++k) {
       const int64_t t = g0 + threadIdx.x + (int64_t)k * ORD_THREADS;
-      b[k] = g0 == 0 ? first[k] : (t < ntiles ? length_bucket(ranges, t) : -1);
+      if (g0 == 0) {
+        b[k] = first[k];
+        rg[k] = frng[k];
+      } else {
+        rg[k] = t < ntiles ? make_uint2(ranges[2 * t], ranges[2 * t + 1]) : make_uint2(0u, 0u);
+        b[k] = t < ntiles ? bucket_of_length(rg[k].y - rg[k].x) : -1;
+      }
     }
 #pragma unroll
     for (int k = 0; k < ORD_ITEMS; ++k) {
@@ -1154,13 +1234,13 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The same stable LSD sort as sort_list for a list of n <= WAVE_MAX copies,
+// The same stable LSD sort as sort_list for a list of n <= 64 IPT copies,
 // by one wave and without workgroup barriers: copy i = r * 64 + lane is held
 // by lane `lane` in round r, rounds are ranked in order (earlier copies
 // first, so equal keys keep their order), and the 256 digit counts are
 // scanned by the wave, four per lane.
+template <int IPT>
 __device__ inline void sort_list_wave(const Seg &a, uint32_t t, uint32_t start, uint32_t n, WaveLds &wl) {
-  constexpr int IPT = 4;
   const int lane = threadIdx.x & 63;
   const uint64_t lt = (1ull << lane) - 1ull;
   const uint32_t R = (n + 63) / 64;
@@ -1305,7 +1385,10 @@ __global__ __launch_bounds__(BS) void segment_sort(Seg a) {
       __syncthreads();  // the LDS is reused
     }
   }
-  if (nn[w] > 0u && nn[w] <= WAVE_MAX) sort_list_wave(a, tt[w], st[w], nn[w], lds.wl[w]);
+  if (nn[w] > 0u && nn[w] <= WAVE_SHORT)
+    sort_list_wave<WAVE_SHORT / 64>(a, tt[w], st[w], nn[w], lds.wl[w]);
+  else if (nn[w] > WAVE_SHORT && nn[w] <= WAVE_MAX)
+    sort_list_wave<(WAVE_MAX + 63) / 64>(a, tt[w], st[w], nn[w], lds.wl[w]);
 }
 
 // ---------------------------------------------------------------------------

@@ -168,3 +168,24 @@ def test_hot_tiles_on_the_per_tile_route():
         assert g["overflow"] == 0 and g["K"] == K
         assert np.array_equal(g["keys"], keys) and np.array_equal(g["vals"], vals)
         assert np.array_equal(g["ranges"], ranges)
+
+
+def test_splats_with_millions_of_tiles():
+    """A splat whose rectangle holds more than 2^22 tiles: the emission's copy
+    index within a splat leaves the range where a float quotient by the
+    rectangle's width is exact to within one, and takes the integer division."""
+    gw, gh = 4096, 1100
+    rect = np.array([[0, 0, gw - 1, gh - 1], [17, 3, 3016, 1099], [5, 7, 9, 8], [0, 0, -1, -1],
+                     [4095, 1099, 4095, 1099]], np.int32)
+    depth = np.array([3.0, 2.0, 3.0, 1.0, 0.5], np.float32)
+    w = np.maximum(rect[:, 2] - rect[:, 0] + 1, 0)
+    h = np.maximum(rect[:, 3] - rect[:, 1] + 1, 0)
+    tiles = (w * h).astype(np.uint32)
+    keys, vals, ranges = binning.bin_and_sort_fast(rect, depth, gw, gh)
+    K = keys.shape[0]
+    assert tiles.max() > (1 << 22)
+    print(f"[gpu] bin_sort millions of tiles K={K}", flush=True)
+    g = _run(depth, rect, tiles, gw, gh, K)
+    assert g["overflow"] == 0 and g["K"] == K
+    assert np.array_equal(g["keys"], keys) and np.array_equal(g["vals"], vals)
+    assert np.array_equal(g["ranges"], ranges)

@@ -8,12 +8,11 @@
 //     stable LSD radix sort on the ceil(log2 tiles) tile bits only (two 7-bit
 //     passes at 1080p), so inside a tile they stay in index order;
 //  2. each tile's list is sorted stably by depth bits: by one wave when it
-//     holds at most 510 copies, by a workgroup in LDS up to 1024 copies (2048
-//     when the capacity holds 512 or more per tile) and in chunks of that
-//     size through global memory beyond, all in one kernel (longest lists
-//     dispatched first, so they overlap the rest). Keys are offset by the
-//     tile's smallest depth, so only the bits that vary inside the tile are
-//     sorted (usually 3 of 4 bytes).
+//     holds at most 510 copies, by a workgroup in LDS up to 2048 copies and
+//     in chunks of that size through global memory beyond, all in one
+//     kernel (longest lists dispatched first, so they overlap the rest).
+//     Keys are offset by the tile's smallest depth, so only the bits that
+//     vary inside the tile are sorted (usually 3 of 4 bytes).
 // With a capacity of 2048 or more copies per tile, the splats are instead
 // sorted by depth first and their copies emitted in that order, so the tile
 // passes alone give the final order. With per-tile culling, the copies come
@@ -51,16 +50,14 @@ constexpr int SPART = BS * SIPT;        // items per sort partition
 constexpr int LONG_SIPT = 8;            // the same on the long lists' route
 constexpr int EIPT = 4;                 // splats per thread in an emission partition
 constexpr int EPART = BS * EIPT;        // splats per emission partition
-static_assert(EPART == 1024, "the emission's binary search takes 10 steps");
 constexpr int RADIX = 256;              // max buckets per pass (8-bit digits)
 static_assert(BS == RADIX, "per-digit steps give one digit to each thread");
 constexpr int MAX_TILE_PASSES = 4;      // tile ids < 2^30 need at most four digits of <= 8 bits
 constexpr int STRIPES = 8;              // copies of the digit totals
-constexpr int SEG_IPT = 4;              // copies per thread of a workgroup's list sort (1024 in LDS)
-constexpr int LONG_SEG_IPT = 8;         // the same for long lists (2048 in LDS)
-// Average list length (capacity per tile) from which the per-tile sort keeps
-// up to 2048 copies in LDS: fewer lists take the chunked path through global
-// memory, at some cost in registers for the shorter lists
+constexpr int SEG_IPT = 8;              // copies per thread of a workgroup's list sort (2048 in LDS)
+// Average list length (capacity per tile) from which the tile passes take
+// partitions of BS * LONG_SIPT keys, so each digit leaves a partition in
+// longer runs
 constexpr int64_t LONG_SEG_MIN_AVG = 512;
 constexpr int DEPTH_PASSES = 4;         // 8-bit digits of a float's bits
 // Average list length from which the splats are sorted by depth before the
@@ -1621,10 +1618,7 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
     g.keys = keys;
     g.vout = vals;
     g.split = tile_order ? w.ctr + CTR_SPLIT : nullptr;
-    if (capacity >= LONG_SEG_MIN_AVG * ntiles)
-      hipLaunchKernelGGL(segment_sort<LONG_SEG_IPT>, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
-    else
-      hipLaunchKernelGGL(segment_sort<SEG_IPT>, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
+    hipLaunchKernelGGL(segment_sort<SEG_IPT>, dim3((unsigned)ntiles), dim3(BS), 0, s, g);
     return hipGetLastError();
   }
   // nothing emitted (or no room): ranges stay zero

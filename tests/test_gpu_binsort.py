@@ -124,8 +124,8 @@ def test_bin_sort_without_tile_order():
 def test_depth_first_and_per_tile_sorts_agree(n, gw, gh, seed, big):
     """Both routes to the sorted keys, forced by the capacity (a capacity of
     2048 copies per tile or more sorts the splats by depth before emitting
-    their copies; a smaller one sorts each tile's list, keeping up to 2048
-    copies in LDS from 512 copies per tile, else 1024), give the oracle's
+    their copies; a smaller one sorts each tile's list, and from 512 copies
+    per tile the tile passes take larger partitions), give the oracle's
     keys, values and ranges."""
     depth, rect, tiles = scenes.binning_inputs(n, gw, gh, seed, big=big)
     keys, vals, ranges = binning.bin_and_sort_fast(rect, depth, gw, gh)
@@ -148,14 +148,14 @@ def test_depth_first_and_per_tile_sorts_agree(n, gw, gh, seed, big):
 def test_hot_tiles_on_the_per_tile_route():
     """A few very long lists beside short ones, at an average below the
     depth-first route's threshold: lists sorted in LDS up to 2048 copies and
-    in 2048-copy chunks beyond (a capacity of 512+ copies per tile), and in
-    1024-copy pieces (a smaller capacity), ties included, give the oracle's
-    keys, values and ranges."""
+    in 2048-copy chunks beyond, with both partition sizes of the tile passes
+    (capacities below and above 512 copies per tile), ties included, give
+    the oracle's keys, values and ranges."""
     gw, gh, n = 16, 1, 8000
     rng = np.random.default_rng(8)
     tx = rng.integers(0, gw, size=n)
     tx[:5200] = 0                      # a hot tile: 5200+ copies
-    tx[5200:6700] = 1                  # 1500+ copies: in LDS only with 2048 slots
+    tx[5200:6700] = 1                  # 1500+ copies: a workgroup's sort in LDS
     rect = np.stack([tx, np.zeros(n, np.int64), tx, np.zeros(n, np.int64)], 1).astype(np.int32)
     depth = rng.choice(np.linspace(1.0, 50.0, 3000), size=n).astype(np.float32)  # many ties
     tiles = np.ones(n, np.uint32)

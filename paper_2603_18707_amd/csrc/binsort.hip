@@ -793,20 +793,33 @@ __global__ __launch_bounds__(CS_THREADS) void cull_scan(uint64_t *__restrict__ e
 }
 
 // The kept copies of the workgroup's splats, in emission order (splats in
-// order, each one's tiles row-major): row items BS at a time, each writing
-// its row's run of tiles at the place a workgroup scan of the runs' lengths
-// gives it; nothing when the call overflows. Counts the tile digits.
+// order, each one's tiles row-major), nothing when the call overflows. Row
+// items BS at a time: each takes its row's run of tiles and its place from a
+// workgroup scan of the runs' lengths, and counts the run's tile digits (the
+// lowest digit as a range of bins, in a difference array, the higher ones
+// per value, a few per run); then the round's copies are written by
+// consecutive threads to consecutive keys, each copy finding its row by a
+// max-scan over window marks (as in emit_copies). Per-copy stores from one
+// thread per run would scatter every store instruction over 64 runs, and
+// per-copy digit atomics would put a run's equal high digits on one LDS word.
 __global__ __launch_bounds__(BS) void cull_emit(Emit a, Cull cu) {
   __shared__ CullLds L;
   __shared__ uint32_t th[MAX_TILE_PASSES * RADIX];
+  __shared__ uint32_t d0[RADIX + 1];  // lowest digit: difference array of the runs' bin ranges
+  __shared__ uint32_t all0;           // whole cycles of the lowest digit (one copy in every bin)
+  __shared__ uint32_t rloc[BS], rtile[BS], rsp[BS], rbits[BS];  // the round's rows: place, first tile, splat, bits
+  __shared__ __align__(16) uint16_t owner[EWIN];
+  __shared__ uint32_t wmax[BS / 64];
   for (int j = threadIdx.x; j < MAX_TILE_PASSES * RADIX; j += BS) th[j] = 0u;
+  for (int j = threadIdx.x; j <= RADIX; j += BS) d0[j] = 0u;
+  if (threadIdx.x == 0) all0 = 0u;
   // the row items of the rectangles alone first: whether cull_count saved the runs
-  uint32_t R = cull_stage(a.n, a.perm, a.tiles, a.rect, a.depth, cu, L, false);  // orders th's reset too
+  uint32_t R = cull_stage(a.n, a.perm, a.tiles, a.rect, a.depth, cu, L, false);  // orders the resets too
   if (*a.overflow) return;  // uniform: written before this launch
   const bool save = R <= cu.rcap;
   const SpanSlots saved = span_slots(cu, blockIdx.x);
   if (!save) R = cull_stage(a.n, a.perm, a.tiles, a.rect, a.depth, cu, L);  // recompute the runs
-  const uint32_t dmask = (1u << a.tile_bits) - 1u;
+  const uint32_t R0 = 1u << a.tile_bits, dmask = R0 - 1u;
   uint64_t carry = a.esum[blockIdx.x];
   for (uint32_t base = 0; base < R; base += BS) {  // uniform trip count
     const uint32_t k = base + threadIdx.x;
@@ -819,17 +832,68 @@ __global__ __launch_bounds__(BS) void cull_emit(Emit a, Cull cu) {
         row_span(L, j, ty, ta, tb);
       }
     }
+    const uint32_t len = ta <= tb ? (uint32_t)(tb - ta + 1) : 0u;
     uint32_t chunk;
-    uint64_t o = carry + block_exclusive<uint32_t>(ta <= tb ? (uint32_t)(tb - ta + 1) : 0u, chunk);
-    // both kernels take the same decisions; the bound only guards the writes
-    for (int tx = ta; tx <= tb && o < a.capacity; ++tx, ++o) {
-      const uint32_t tile = (uint32_t)ty * (uint32_t)a.grid_w + (uint32_t)tx;
-      a.tkey[o] = tile;
-      a.tval[o] = L.sp[j];
-      a.tbits[o] = L.bits[j];
-      for (int p = 0; p < a.tile_passes; ++p) atomicAdd(&th[p * RADIX + ((tile >> (p * a.tile_bits)) & dmask)], 1u);
+    const uint32_t loc = block_exclusive<uint32_t>(len, chunk);  // ends with a barrier
+    if (len) {
+      const uint32_t t0 = (uint32_t)ty * (uint32_t)a.grid_w + (uint32_t)ta, t1 = t0 + len - 1u;
+      rloc[threadIdx.x] = loc;
+      rtile[threadIdx.x] = t0;
+      rsp[threadIdx.x] = L.sp[j];
+      rbits[threadIdx.x] = L.bits[j];
+      // lowest digit: len consecutive tile ids, so every bin gets len >> bits
+      // copies and the len & mask bins from t0's on get one more
+      if (len >> a.tile_bits) atomicAdd(&all0, len >> a.tile_bits);
+      const uint32_t rem = len & dmask, s0 = t0 & dmask, e0 = s0 + rem;
+      if (rem) {
+        atomicAdd(&d0[s0], 1u);
+        if (e0 <= R0) {
+          atomicSub(&d0[e0], 1u);
+        } else {
+          atomicSub(&d0[R0], 1u);
+          atomicAdd(&d0[0], 1u);
+          atomicSub(&d0[e0 - R0], 1u);
+        }
+      }
+      // higher digits: the values of t >> (p bits) over the run, with their overlaps
+      for (int pp = 1; pp < a.tile_passes; ++pp) {
+        const int sh = pp * a.tile_bits;
+        for (uint32_t v = t0 >> sh; v <= (t1 >> sh); ++v) {
+          const uint32_t lo = max(t0, v << sh), hi = min(t1, ((v + 1u) << sh) - 1u);
+          atomicAdd(&th[pp * RADIX + (v & dmask)], hi - lo + 1u);
+        }
+      }
+    }
+    // the round's copies, consecutive threads on consecutive keys
+    uint32_t wcarry = 0;
+    for (uint32_t k0 = 0; k0 < chunk; k0 += EWIN) {  // uniform trip count
+      reinterpret_cast<uint4 *>(owner)[threadIdx.x] = make_uint4(0u, 0u, 0u, 0u);
+      __syncthreads();  // also orders the round's row table before its readers
+      if (len && loc >= k0 && loc - k0 < (uint32_t)EWIN) owner[loc - k0] = (uint16_t)threadIdx.x;
+      __syncthreads();
+      wcarry = window_max_scan(owner, wcarry, wmax);
+      __syncthreads();
+      const uint32_t m = chunk - k0 < (uint32_t)EWIN ? chunk - k0 : (uint32_t)EWIN;
+      for (uint32_t i = threadIdx.x; i < m; i += BS) {
+        const uint32_t r = owner[i], c = k0 + i;
+        const uint64_t o = carry + c;
+        if (o < a.capacity) {  // always, when the counts are consistent
+          a.tkey[o] = rtile[r] + (c - rloc[r]);
+          a.tval[o] = rsp[r];
+          a.tbits[o] = rbits[r];
+        }
+      }
+      __syncthreads();  // the window and the row table are reused
     }
     carry += chunk;
+  }
+  __syncthreads();
+  {  // lowest digit counts: the difference array's prefix plus the whole cycles
+    const uint32_t d = threadIdx.x;  // BS == RADIX
+    uint32_t unused;
+    const uint32_t v = d <= dmask ? d0[d] : 0u;
+    const uint32_t inc = block_exclusive<uint32_t>(v, unused) + v;
+    if (d <= dmask) th[d] += inc + all0;
   }
   __syncthreads();
   const int stripe = blockIdx.x % STRIPES;

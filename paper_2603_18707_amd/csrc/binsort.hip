@@ -188,7 +188,10 @@ __global__ __launch_bounds__(BS) void count_pass(const uint32_t *__restrict__ ke
   __syncthreads();
   const uint32_t R = 1u << nbits, mask = R - 1u;
   const int w = threadIdx.x >> 6;
-  const uint64_t base = (uint64_t)blockIdx.x * PART + threadIdx.x;
+  // consecutive partitions on one XCD: the column stores of neighbouring
+  // partitions share cache lines, which then merge in that XCD's L2
+  const uint32_t part = xcd_partition(blockIdx.x, nparts);
+  const uint64_t base = (uint64_t)part * PART + threadIdx.x;
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     const uint64_t i = base + (uint64_t)r * BS;
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(BS) void count_pass(const uint32_t *__restrict__ ke
     uint32_t v = 0;
 #pragma unroll
     for (int ww = 0; ww < BS / 64; ++ww) v += h[ww][d];
-    C[(size_t)d * c_stride + blockIdx.x] = v;
+    C[(size_t)d * c_stride + part] = v;
   }
 }
 
@@ -924,19 +927,32 @@ __global__ __launch_bounds__(BS) void depth_hist(const float *__restrict__ depth
 
 // ranges from the tile-grouped copies: tile ids in 32-bit keys, or in the
 // high half of the final 64-bit keys (WIDE)
+// each thread takes RIPT consecutive keys (and their neighbours), all
+// loaded at once
+constexpr int RIPT = 4;
+
 template <bool WIDE>
-__global__ void tile_ranges(const void *__restrict__ tkey, const uint32_t *__restrict__ ctr, int64_t ntiles,
-                            uint32_t *__restrict__ ranges) {
+__global__ __launch_bounds__(BS) void tile_ranges(const void *__restrict__ tkey, const uint32_t *__restrict__ ctr,
+                                                  int64_t ntiles, uint32_t *__restrict__ ranges) {
   const uint32_t K = ctr[CTR_KEYS];
-  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= K) return;
+  const uint64_t k0 = ((uint64_t)blockIdx.x * BS + threadIdx.x) * RIPT;
+  if (k0 >= K) return;
   auto at = [&](uint64_t i) -> uint32_t {
     return WIDE ? (uint32_t)(reinterpret_cast<const uint64_t *>(tkey)[i] >> 32) : reinterpret_cast<const uint32_t *>(tkey)[i];
   };
-  const uint32_t t = at(k);
-  if ((int64_t)t >= ntiles) return;
-  if (k == 0 || at(k - 1) != t) ranges[2 * (size_t)t] = (uint32_t)k;
-  if (k + 1 == K || at(k + 1) != t) ranges[2 * (size_t)t + 1] = (uint32_t)(k + 1);
+  uint32_t t[RIPT + 2];  // keys k0 - 1 .. k0 + RIPT (0xFFFFFFFF outside [0, K))
+#pragma unroll
+  for (int j = 0; j < RIPT + 2; ++j) {
+    const int64_t i = (int64_t)k0 - 1 + j;
+    t[j] = i >= 0 && i < (int64_t)K ? at((uint64_t)i) : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int j = 1; j <= RIPT; ++j) {
+    const uint64_t k = k0 - 1 + j;
+    if (k >= K || (int64_t)t[j] >= ntiles) continue;
+    if (t[j - 1] != t[j]) ranges[2 * (size_t)t[j]] = (uint32_t)k;
+    if (t[j + 1] != t[j]) ranges[2 * (size_t)t[j] + 1] = (uint32_t)(k + 1);
+  }
 }
 
 // Lists of at most WAVE_MAX copies are sorted by one wave alone (four
@@ -1661,13 +1677,13 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
     }
     // 3. per-tile ranges, longest-first order, then (in index order) each tile's list by depth
     if (presort) {
-      hipLaunchKernelGGL(tile_ranges<true>, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, (const void *)keys,
+      hipLaunchKernelGGL(tile_ranges<true>, dim3(ceil_div(capacity, BS * RIPT)), dim3(BS), 0, s, (const void *)keys,
                          count_dev, ntiles, ranges);
       if (tile_order)
         hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(ORD_THREADS), 0, s, ranges, ntiles, tile_order, (uint32_t *)nullptr);
       return hipGetLastError();
     }
-    hipLaunchKernelGGL(tile_ranges<false>, dim3(ceil_div(capacity, 256)), dim3(256), 0, s, (const void *)w.tk[cur],
+    hipLaunchKernelGGL(tile_ranges<false>, dim3(ceil_div(capacity, BS * RIPT)), dim3(BS), 0, s, (const void *)w.tk[cur],
                        count_dev, ntiles, ranges);
     if (tile_order)
       hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(ORD_THREADS), 0, s, ranges, ntiles, tile_order, w.ctr + CTR_SPLIT);

@@ -390,3 +390,29 @@ def test_culled_without_tile_order():
     assert int(ov.item()) == 0 and int(nk.item()) == K
     assert torch.equal(keys[:K], a["keys"][:K]) and torch.equal(vals[:K], a["vals"][:K])
     assert torch.equal(ranges, a["ranges"])
+
+
+def test_runs_longer_than_a_digit_cycle():
+    """Long horizontal footprints on a wide grid (128 x 4 tiles: two 5-bit tile
+    digits), so kept runs cover the lowest digit's 32 values more than once
+    (the emission counts a run's lowest digits as whole cycles plus a range of
+    bins, which may wrap): keys equal to the oracle's culled lists, images
+    equal to the unculled ones."""
+    W, Hh = 2048, 64
+    cam = scenes.tiny_camera(W, Hh)
+    rng = np.random.default_rng(23)
+    n = 300
+    sx, sy = rng.uniform(150, 500, n), rng.uniform(0.8, 3.0, n)
+    m2 = np.stack([rng.uniform(0, W, n), rng.uniform(0, Hh, n)], 1)
+    rec = dict(means2d=m2, conic=np.stack([1 / sx**2, np.zeros(n), 1 / sy**2], 1), opac=rng.uniform(0.3, 0.99, n),
+               rgb=rng.uniform(0, 1, (n, 3)), depth32=rng.permutation(np.arange(1, n + 1)).astype(np.float32),
+               rect=np.tile(np.array([0, 0, W // 16 - 1, Hh // 16 - 1], np.int32), (n, 1)),
+               flags=np.zeros(n, np.uint8))
+    for k in ("means2d", "conic", "opac", "rgb"):
+        rec[k] = rec[k].astype(np.float32).astype(np.float64)
+    g, g0 = _records_frames(rec, cam, "poly", 1, "opacity")
+    K, Kbox = _check_culled_binning(g, rec, H.oracle_cfg("poly", 1, "opacity"), W // 16, Hh // 16)
+    print(f"K={K} box={Kbox}")
+    assert 0 < K < Kbox
+    for k in ("image", "final_T", "n_contrib"):
+        assert torch.equal(g[k], g0[k]), k

@@ -16,7 +16,7 @@
 // With a capacity of 2048 or more copies per tile, the splats are instead
 // sorted by depth first and their copies emitted in that order, so the tile
 // passes alone give the final order. With per-tile culling, the copies come
-// from the culling kernels (cull_count, cull_scan, cull_emit) and then take
+// from the culling kernels (cull_count, sums_scan, cull_emit) and then take
 // the same route.
 // A radix pass of step 1 is three kernels and no workgroup ever waits on
 // another (a hand-off between workgroups costs ~0.5 us through memory, and
@@ -374,7 +374,14 @@ struct Emit {
   int tile_passes, tile_bits;            // digits per key and bits per digit
   int64_t *num_keys;
   int32_t *overflow;
+  bool scanned;                          // esum holds exclusive prefixes and K is set (sums_scan ran)
 };
+
+// From this many emission partitions the partition sums are scanned once
+// (sums_scan) instead of each workgroup adding up the sums before its own,
+// which costs O(partitions^2) loads (3 ms at the 84k partitions of the
+// 96-view batch, a few us below this).
+constexpr uint32_t EMIT_SCAN_MIN_PARTS = 4096;
 
 // Offsets from the partition sums before this one, then every copy of the
 // partition written by the whole workgroup (consecutive threads write
@@ -437,9 +444,14 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
   const uint32_t part = blockIdx.x;
   for (int j = threadIdx.x; j < MAX_TILE_PASSES * RADIX; j += BS) th[j] = 0u;
   // copies before this partition
-  uint64_t part_sum = 0, pre;
-  for (uint32_t q = threadIdx.x; q < part; q += BS) part_sum += a.esum[q];
-  block_exclusive<uint64_t>(part_sum, pre);
+  uint64_t pre;
+  if (a.scanned) {  // uniform
+    pre = a.esum[part];
+  } else {
+    uint64_t part_sum = 0;
+    for (uint32_t q = threadIdx.x; q < part; q += BS) part_sum += a.esum[q];
+    block_exclusive<uint64_t>(part_sum, pre);
+  }
   const uint64_t s0 = (uint64_t)part * EPART + (uint64_t)threadIdx.x * EIPT;
   uint32_t c[EIPT];
   uint64_t sum = 0;
@@ -452,7 +464,7 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
   }
   uint64_t total;
   uint64_t off = block_exclusive<uint64_t>(sum, total);
-  if (threadIdx.x == 0 && part == nparts - 1) {
+  if (!a.scanned && threadIdx.x == 0 && part == nparts - 1) {
     const uint64_t K = pre + total;
     const bool over = K > a.capacity;
     *a.num_keys = (int64_t)K;
@@ -747,15 +759,15 @@ __global__ __launch_bounds__(BS) void cull_count(uint32_t n, const uint32_t *__r
   if (threadIdx.x == 0) esum[blockIdx.x] = total;
 }
 
-// esum -> exclusive prefix in place (one workgroup, each thread a contiguous
-// chunk: its loads are independent and overlap); K, overflow and the key
-// counter from the total
-// One workgroup of CS_THREADS scans the partition sums in tiles of
+// esum -> exclusive prefix in place; K, overflow and the key counter from
+// the total. One workgroup of CS_THREADS scans the partition sums in tiles of
 // CS_THREADS x CS_ITEMS consecutive sums, all of a tile's loads in flight
-// together, carrying the running total from tile to tile.
+// together, carrying the running total from tile to tile. The culled
+// emission's sums always take it, the plain emission's from
+// EMIT_SCAN_MIN_PARTS partitions on.
 constexpr int CS_THREADS = 1024, CS_ITEMS = 4;
 
-__global__ __launch_bounds__(CS_THREADS) void cull_scan(uint64_t *__restrict__ esum, uint32_t parts,
+__global__ __launch_bounds__(CS_THREADS) void sums_scan(uint64_t *__restrict__ esum, uint32_t parts,
                                                         uint64_t capacity, uint32_t *__restrict__ ctr,
                                                         int64_t *num_keys, int32_t *overflow) {
   __shared__ uint64_t wsum[CS_THREADS / 64];
@@ -1039,6 +1051,87 @@ __global__ __launch_bounds__(ORD_THREADS) void tile_order_kernel(const uint32_t 
         const uint32_t pos = atomicAdd(&hist[b[k]], 1u);
         if ((int64_t)pos < ntiles) order[pos] = (uint32_t)(g0 + threadIdx.x + (int64_t)k * ORD_THREADS);
       }
+    }
+  }
+}
+
+// The same order for large grids (the stacked views of a batch): a bucket
+// histogram per chunk of ORD_CHUNK tiles, an exclusive scan over the
+// bucket-major [bucket][chunk] counts, and a scatter through per-chunk bucket
+// cursors in LDS; one workgroup would take hundreds of microseconds.
+constexpr int64_t ORD_MULTI_MIN = 65536;  // tiles from which the order takes these three kernels
+constexpr int ORD_CHUNK = BS * 8;         // tiles per workgroup there
+
+inline uint32_t order_chunks(int64_t ntiles) { return (uint32_t)((ntiles + ORD_CHUNK - 1) / ORD_CHUNK); }
+
+__global__ __launch_bounds__(BS) void order_hist(const uint32_t *__restrict__ ranges, int64_t ntiles,
+                                                 uint32_t *__restrict__ H, uint32_t G) {
+  __shared__ uint32_t h[RADIX];
+  h[threadIdx.x] = 0u;  // BS == RADIX
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * ORD_CHUNK + threadIdx.x;
+  uint32_t len[ORD_CHUNK / BS];
+#pragma unroll
+  for (int j = 0; j < ORD_CHUNK / BS; ++j) {
+    const int64_t t = t0 + (int64_t)j * BS;
+    len[j] = t < ntiles ? ranges[2 * t + 1] - ranges[2 * t] : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < ORD_CHUNK / BS; ++j)
+    if (t0 + (int64_t)j * BS < ntiles) atomicAdd(&h[bucket_of_length(len[j])], 1u);
+  __syncthreads();
+  H[(size_t)threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of H[0..m) in place, one workgroup, CS_THREADS x 4 entries per step with a carry
+__global__ __launch_bounds__(1024) void order_offsets(uint32_t *__restrict__ H, uint32_t m) {
+  constexpr int NT = 1024, IT = 4;
+  __shared__ uint32_t wsum[NT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (uint32_t t0 = 0; t0 < m; t0 += NT * IT) {
+    const uint32_t b = t0 + threadIdx.x * IT;
+    uint32_t v[IT], sum = 0;
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      v[j] = b + j < m ? H[b + j] : 0u;
+      sum += v[j];
+    }
+    const uint32_t inc = wave_inclusive<uint32_t>(sum);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = carry + inc - sum, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) {
+      const uint32_t x = wsum[k];
+      if (k < w) off += x;
+      tot += x;
+    }
+    __syncthreads();  // wsum is reused by the next step
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      if (b + j < m) H[b + j] = off;
+      off += v[j];
+    }
+    carry += tot;
+  }
+}
+
+__global__ __launch_bounds__(BS) void order_scatter(const uint32_t *__restrict__ ranges, int64_t ntiles,
+                                                    const uint32_t *__restrict__ H, uint32_t G,
+                                                    uint32_t *__restrict__ order, uint32_t *__restrict__ split) {
+  __shared__ uint32_t cur[RADIX];
+  cur[threadIdx.x] = H[(size_t)threadIdx.x * G + blockIdx.x];
+  // first position of a list <= WAVE_MAX: where that bucket starts, in chunk 0
+  if (split && blockIdx.x == 0 && threadIdx.x == 255 - WAVE_BUCKET) *split = cur[threadIdx.x];
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * ORD_CHUNK + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < ORD_CHUNK / BS; ++j) {
+    const int64_t t = t0 + (int64_t)j * BS;
+    if (t < ntiles) {
+      const uint32_t pos = atomicAdd(&cur[bucket_of_length(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+      if ((int64_t)pos < ntiles) order[pos] = (uint32_t)t;
     }
   }
 }
@@ -1490,6 +1583,7 @@ struct Workspace {
   uint32_t *tC;                          // tile passes' counts [pass][1 << bits][key partitions]
   uint32_t *dk[2], *dv[2];               // depth passes ping-pong [n]: depth bits, splat
   uint32_t *dC;                          // a depth pass's counts [256][splat partitions]
+  uint32_t *oH;                          // large grids' tile order: [bucket][chunk] counts, then offsets
   // zeroed at the start of every call, contiguous:
   uint32_t *ctr;                         // counters
   uint32_t *ttot;                        // tile digit totals [stripe][pass][256]
@@ -1527,6 +1621,7 @@ size_t carve(void *base, int64_t n, int64_t cap, int64_t ntiles, Workspace *w) {
   }
   t.dstride = (size_t)ceil_div((int64_t)N, SPART);
   t.dC = (uint32_t *)take(4 * (size_t)RADIX * t.dstride);
+  t.oH = ntiles >= ORD_MULTI_MIN ? (uint32_t *)take(4 * (size_t)RADIX * order_chunks(ntiles)) : nullptr;
   const size_t z0 = o;
   t.ctr = (uint32_t *)take(4 * CTR_SLOTS);
   t.ttot = (uint32_t *)take(4 * (size_t)STRIPES * MAX_TILE_PASSES * RADIX);
@@ -1544,6 +1639,20 @@ size_t binsort_workspace_bytes(int64_t n, int64_t capacity, int32_t num_tiles) {
 }
 
 namespace {
+// the longest-first tile order (and the split) from the ranges
+void launch_tile_order(const uint32_t *ranges, int64_t ntiles, uint32_t *order, uint32_t *split, const Workspace &w,
+                       hipStream_t s) {
+  if (ntiles >= ORD_MULTI_MIN && w.oH) {
+    const uint32_t G = order_chunks(ntiles);
+    hipLaunchKernelGGL(order_hist, dim3(G), dim3(BS), 0, s, ranges, ntiles, w.oH, G);
+    hipLaunchKernelGGL(order_offsets, dim3(1), dim3(1024), 0, s, w.oH, (uint32_t)(RADIX * G));
+    hipLaunchKernelGGL(order_scatter, dim3(G), dim3(BS), 0, s, ranges, ntiles, (const uint32_t *)w.oH, G, order,
+                       split);
+  } else {
+    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(ORD_THREADS), 0, s, ranges, ntiles, order, split);
+  }
+}
+
 // count, scan and scatter of one stable digit pass over the keys of `a`
 // (count in device memory), in partitions of BS * IPT items
 template <int IPT>
@@ -1615,11 +1724,14 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
     const unsigned egrid = ceil_div(n, EPART), cgrid = ceil_div(n, BS);
     if (cu) {
       hipLaunchKernelGGL(cull_count, dim3(cgrid), dim3(BS), 0, s, (uint32_t)n, perm, tiles, rect, *cu, w.esum);
-      hipLaunchKernelGGL(cull_scan, dim3(1), dim3(CS_THREADS), 0, s, w.esum, cgrid, (uint64_t)capacity, w.ctr, num_keys,
+      hipLaunchKernelGGL(sums_scan, dim3(1), dim3(CS_THREADS), 0, s, w.esum, cgrid, (uint64_t)capacity, w.ctr, num_keys,
                          overflow);
     } else {
       hipLaunchKernelGGL(emit_sums, dim3(egrid), dim3(BS), 0, s, (uint32_t)n, tiles, perm, w.esum,
                          presort ? (uint4 *)nullptr : (uint4 *)w.zero_begin, nz16, ranges, nr, num_keys, overflow);
+      if (egrid >= EMIT_SCAN_MIN_PARTS)
+        hipLaunchKernelGGL(sums_scan, dim3(1), dim3(CS_THREADS), 0, s, w.esum, egrid, (uint64_t)capacity, w.ctr,
+                           num_keys, overflow);
     }
     Emit e{};
     e.n = (uint32_t)n;
@@ -1639,6 +1751,7 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
     e.tile_bits = tp.bits;
     e.num_keys = num_keys;
     e.overflow = overflow;
+    e.scanned = !cu && egrid >= EMIT_SCAN_MIN_PARTS;
     if (cu)
       hipLaunchKernelGGL(cull_emit, dim3(cgrid), dim3(BS), 0, s, e, *cu);
     else
@@ -1680,13 +1793,13 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
       hipLaunchKernelGGL(tile_ranges<true>, dim3(ceil_div(capacity, BS * RIPT)), dim3(BS), 0, s, (const void *)keys,
                          count_dev, ntiles, ranges);
       if (tile_order)
-        hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(ORD_THREADS), 0, s, ranges, ntiles, tile_order, (uint32_t *)nullptr);
+        launch_tile_order(ranges, ntiles, tile_order, (uint32_t *)nullptr, w, s);
       return hipGetLastError();
     }
     hipLaunchKernelGGL(tile_ranges<false>, dim3(ceil_div(capacity, BS * RIPT)), dim3(BS), 0, s, (const void *)w.tk[cur],
                        count_dev, ntiles, ranges);
     if (tile_order)
-      hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(ORD_THREADS), 0, s, ranges, ntiles, tile_order, w.ctr + CTR_SPLIT);
+      launch_tile_order(ranges, ntiles, tile_order, w.ctr + CTR_SPLIT, w, s);
     Seg g{};
     g.ranges = ranges;
     g.order = tile_order;
@@ -1703,7 +1816,7 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
   }
   // nothing emitted (or no room): ranges stay zero
   if (tile_order)
-    hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(ORD_THREADS), 0, s, ranges, ntiles, tile_order, (uint32_t *)nullptr);
+    launch_tile_order(ranges, ntiles, tile_order, (uint32_t *)nullptr, w, s);
   return hipGetLastError();
 }
 }  // namespace

@@ -51,6 +51,7 @@ CASES = [  # n, grid_w, grid_h, seed, share of big splats
     (3000, 8192, 2100, 7, 0.0),       # 25 tile bits: four 7-bit passes
     (20_000, 4, 4, 11, 0.0),          # lists up to ~6k: longer than a workgroup sorts in LDS
     (60_000, 3, 2, 12, 0.0),          # lists up to ~29k: many chunks per depth pass
+    (4_300_000, 160, 90, 14, 0.0),    # over 4096 emission partitions: their sums scanned once
 ]
 
 

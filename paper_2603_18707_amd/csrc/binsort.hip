@@ -375,6 +375,7 @@ struct Emit {
   int64_t *num_keys;
   int32_t *overflow;
   bool scanned;                          // esum holds exclusive prefixes and K is set (sums_scan ran)
+  bool row_digits;                       // count the tile digits per rectangle row, not per copy
 };
 
 // From this many emission partitions the partition sums are scanned once
@@ -382,6 +383,49 @@ struct Emit {
 // which costs O(partitions^2) loads (3 ms at the 84k partitions of the
 // 96-view batch, a few us below this).
 constexpr uint32_t EMIT_SCAN_MIN_PARTS = 4096;
+
+// Tile digits of a run of len consecutive tile ids from t0, counted per run:
+// the lowest digit takes len >> bits copies in every bin (all0) and one more
+// in the len & mask bins from t0's on (a range, possibly wrapping, kept in the
+// difference array d0); each higher digit takes the overlap of the run with
+// every value of t >> (p bits) it spans, a few per run. Counting per copy
+// instead puts a run's equal high digits, from consecutive threads, on one
+// LDS word.
+__device__ inline void count_run_digits(uint32_t t0, uint32_t len, int bits, int passes, uint32_t *th, uint32_t *d0,
+                                        uint32_t *all0) {
+  const uint32_t R0 = 1u << bits, dmask = R0 - 1u, t1 = t0 + len - 1u;
+  if (len >> bits) atomicAdd(all0, len >> bits);
+  const uint32_t rem = len & dmask, s0 = t0 & dmask, e0 = s0 + rem;
+  if (rem) {
+    atomicAdd(&d0[s0], 1u);
+    if (e0 <= R0) {
+      atomicSub(&d0[e0], 1u);
+    } else {
+      atomicSub(&d0[R0], 1u);
+      atomicAdd(&d0[0], 1u);
+      atomicSub(&d0[e0 - R0], 1u);
+    }
+  }
+  for (int pp = 1; pp < passes; ++pp) {
+    const int sh = pp * bits;
+    for (uint32_t v = t0 >> sh; v <= (t1 >> sh); ++v) {
+      const uint32_t lo = max(t0, v << sh), hi = min(t1, ((v + 1u) << sh) - 1u);
+      atomicAdd(&th[pp * RADIX + (v & dmask)], hi - lo + 1u);
+    }
+  }
+}
+
+// adds the lowest digit's counts (prefix of d0 plus all0) into th[0..R0);
+// every thread of the workgroup calls it after the last count
+__device__ inline void flush_lowest_digit(uint32_t *th, const uint32_t *d0, const uint32_t *all0, int bits) {
+  __syncthreads();
+  const uint32_t d = threadIdx.x, dmask = (1u << bits) - 1u;  // BS == RADIX
+  uint32_t unused;
+  const uint32_t v = d <= dmask ? d0[d] : 0u;
+  const uint32_t inc = block_exclusive<uint32_t>(v, unused) + v;
+  if (d <= dmask) th[d] += inc + *all0;
+  __syncthreads();
+}
 
 // Offsets from the partition sums before this one, then every copy of the
 // partition written by the whole workgroup (consecutive threads write
@@ -438,11 +482,14 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
   __shared__ float sinv[EPART];          // 1 / width
   __shared__ uint32_t ssp[EPART];        // splat of each emission position
   __shared__ uint32_t th[MAX_TILE_PASSES * RADIX];
+  __shared__ uint32_t d0[RADIX + 1], all0;  // lowest digit, counted per run (count_run_digits)
   __shared__ __align__(16) uint16_t owner[EWIN];
   __shared__ uint32_t wmax[BS / 64];
   const uint32_t nparts = (uint32_t)(((uint64_t)a.n + EPART - 1) / EPART);
   const uint32_t part = blockIdx.x;
   for (int j = threadIdx.x; j < MAX_TILE_PASSES * RADIX; j += BS) th[j] = 0u;
+  for (int j = threadIdx.x; j <= RADIX; j += BS) d0[j] = 0u;
+  if (threadIdx.x == 0) all0 = 0u;
   // copies before this partition
   uint64_t pre;
   if (a.scanned) {  // uniform
@@ -491,6 +538,24 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
   if (pre + total > a.capacity || total == 0) return;  // an overflowing call writes no key (uniform)
   const uint32_t T = (uint32_t)total;
   const uint32_t dmask = (1u << a.tile_bits) - 1u;
+  __syncthreads();  // the resets above before the counts
+  // With long rows (the depth-first route's large splats) the tile digits of
+  // this thread's splats are counted once per rectangle row (the copies below
+  // take the rows in the same way: copy r of a splat is column r % w of row
+  // r / w); with short ones, per copy as the copies are written (per row,
+  // each thread walks its splats' rows alone: 14.5 -> 22 us at 1M splats).
+#pragma unroll
+  for (int j = 0; j < EIPT; ++j) {
+    const int ls = threadIdx.x * EIPT + j;
+    if (!a.row_digits || !c[j] || sw[ls] <= 0) continue;
+    const uint32_t wdt = (uint32_t)sw[ls], rows = c[j] / wdt, rest = c[j] - rows * wdt;
+    for (uint32_t q = 0; q <= rows; ++q) {
+      const uint32_t len = q < rows ? wdt : rest;
+      if (len)
+        count_run_digits((uint32_t)(sy[ls] + (int32_t)q) * (uint32_t)a.grid_w + (uint32_t)sx[ls], len, a.tile_bits,
+                         a.tile_passes, th, d0, &all0);
+    }
+  }
   uint32_t carry = 0;
   for (uint32_t k0 = 0; k0 < T; k0 += EWIN) {  // uniform trip count
     reinterpret_cast<uint4 *>(owner)[threadIdx.x] = make_uint4(0u, 0u, 0u, 0u);
@@ -524,10 +589,12 @@ __global__ __launch_bounds__(BS) void emit_copies(Emit a) {
       a.tkey[pos] = tile;
       a.tval[pos] = ssp[ls];
       a.tbits[pos] = sbits[ls];
-      for (int p = 0; p < a.tile_passes; ++p) atomicAdd(&th[p * RADIX + ((tile >> (p * a.tile_bits)) & dmask)], 1u);
+      if (!a.row_digits)
+        for (int p = 0; p < a.tile_passes; ++p) atomicAdd(&th[p * RADIX + ((tile >> (p * a.tile_bits)) & dmask)], 1u);
     }
     __syncthreads();  // the window's readers are done before it is cleared
   }
+  if (a.row_digits) flush_lowest_digit(th, d0, &all0, a.tile_bits);  // uniform
   const int stripe = blockIdx.x % STRIPES;
   for (int j = threadIdx.x; j < a.tile_passes * RADIX; j += BS) {
     const uint32_t v = th[j];
@@ -834,7 +901,6 @@ __global__ __launch_bounds__(BS) void cull_emit(Emit a, Cull cu) {
   const bool save = R <= cu.rcap;
   const SpanSlots saved = span_slots(cu, blockIdx.x);
   if (!save) R = cull_stage(a.n, a.perm, a.tiles, a.rect, a.depth, cu, L);  // recompute the runs
-  const uint32_t R0 = 1u << a.tile_bits, dmask = R0 - 1u;
   uint64_t carry = a.esum[blockIdx.x];
   for (uint32_t base = 0; base < R; base += BS) {  // uniform trip count
     const uint32_t k = base + threadIdx.x;
@@ -851,33 +917,12 @@ __global__ __launch_bounds__(BS) void cull_emit(Emit a, Cull cu) {
     uint32_t chunk;
     const uint32_t loc = block_exclusive<uint32_t>(len, chunk);  // ends with a barrier
     if (len) {
-      const uint32_t t0 = (uint32_t)ty * (uint32_t)a.grid_w + (uint32_t)ta, t1 = t0 + len - 1u;
+      const uint32_t t0 = (uint32_t)ty * (uint32_t)a.grid_w + (uint32_t)ta;
       rloc[threadIdx.x] = loc;
       rtile[threadIdx.x] = t0;
       rsp[threadIdx.x] = L.sp[j];
       rbits[threadIdx.x] = L.bits[j];
-      // lowest digit: len consecutive tile ids, so every bin gets len >> bits
-      // copies and the len & mask bins from t0's on get one more
-      if (len >> a.tile_bits) atomicAdd(&all0, len >> a.tile_bits);
-      const uint32_t rem = len & dmask, s0 = t0 & dmask, e0 = s0 + rem;
-      if (rem) {
-        atomicAdd(&d0[s0], 1u);
-        if (e0 <= R0) {
-          atomicSub(&d0[e0], 1u);
-        } else {
-          atomicSub(&d0[R0], 1u);
-          atomicAdd(&d0[0], 1u);
-          atomicSub(&d0[e0 - R0], 1u);
-        }
-      }
-      // higher digits: the values of t >> (p bits) over the run, with their overlaps
-      for (int pp = 1; pp < a.tile_passes; ++pp) {
-        const int sh = pp * a.tile_bits;
-        for (uint32_t v = t0 >> sh; v <= (t1 >> sh); ++v) {
-          const uint32_t lo = max(t0, v << sh), hi = min(t1, ((v + 1u) << sh) - 1u);
-          atomicAdd(&th[pp * RADIX + (v & dmask)], hi - lo + 1u);
-        }
-      }
+      count_run_digits(t0, len, a.tile_bits, a.tile_passes, th, d0, &all0);
     }
     // the round's copies, consecutive threads on consecutive keys
     uint32_t wcarry = 0;
@@ -902,15 +947,7 @@ __global__ __launch_bounds__(BS) void cull_emit(Emit a, Cull cu) {
     }
     carry += chunk;
   }
-  __syncthreads();
-  {  // lowest digit counts: the difference array's prefix plus the whole cycles
-    const uint32_t d = threadIdx.x;  // BS == RADIX
-    uint32_t unused;
-    const uint32_t v = d <= dmask ? d0[d] : 0u;
-    const uint32_t inc = block_exclusive<uint32_t>(v, unused) + v;
-    if (d <= dmask) th[d] += inc + all0;
-  }
-  __syncthreads();
+  flush_lowest_digit(th, d0, &all0, a.tile_bits);
   const int stripe = blockIdx.x % STRIPES;
   for (int j = threadIdx.x; j < a.tile_passes * RADIX; j += BS) {
     const uint32_t v = th[j];
@@ -1752,6 +1789,7 @@ hipError_t binsort(int64_t n, const float *depth, const int32_t *rect, const uin
     e.num_keys = num_keys;
     e.overflow = overflow;
     e.scanned = !cu && egrid >= EMIT_SCAN_MIN_PARTS;
+    e.row_digits = presort;
     if (cu)
       hipLaunchKernelGGL(cull_emit, dim3(cgrid), dim3(BS), 0, s, e, *cu);
     else

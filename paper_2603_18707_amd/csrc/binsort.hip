@@ -1552,7 +1552,8 @@ __device__ inline void sort_list_wave(const Seg &a, uint32_t t, uint32_t start, 
 // whole workgroup when it is longer than WAVE_MAX, else by one wave; the
 // grid has one workgroup per tile and the spare ones exit.
 template <int IPT>
-__global__ __launch_bounds__(BS) void segment_sort(Seg a) {
+// at most 80 VGPRs: six waves per SIMD instead of five (no spills)
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(6, 6))) void segment_sort(Seg a) {
   __shared__ union {
     SortLds<IPT> sl;
     WaveLds wl[BS / 64];

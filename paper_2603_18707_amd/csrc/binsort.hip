@@ -84,6 +84,25 @@ __device__ inline T wave_inclusive(T v) {
   return v;
 }
 
+// The lanes of the wave whose digit d (its low `nbits` bits) equals this
+// lane's, among the lanes where `valid` holds: a ballot per bit, and from it
+// the lanes that agree with this lane's bit, peers & ~(ballot ^ s) with s
+// this lane's bit spread over the word, one three-input logic op per word
+// (v_bitop3_b32; its truth table is indexed by the operand bits as
+// 4 src0 + 2 src1 + src2, so f(a, b, c) = a & ~(b ^ c) is 0x90).
+constexpr int MATCH_LUT = 0x90;
+__device__ inline uint64_t match_digit(uint32_t d, int nbits, bool valid) {
+  const uint64_t v = __ballot(valid);
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  for (int b = 0; b < nbits; ++b) {
+    const uint32_t s = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, b, 1);  // all ones where bit b is set
+    const uint64_t bb = __builtin_amdgcn_uicmp(s, 0u, 33);  // ballot of s != 0 (33: not equal)
+    lo = __builtin_amdgcn_bitop3_b32(lo, (uint32_t)bb, s, MATCH_LUT);
+    hi = __builtin_amdgcn_bitop3_b32(hi, (uint32_t)(bb >> 32), s, MATCH_LUT);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // exclusive scan over the 256 threads of a workgroup; also returns the total
 template <typename T>
 __device__ inline T block_exclusive(T v, T &total) {
@@ -256,12 +275,7 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
   for (int r = 0; r < IPT; ++r) {
     const bool valid = base + (uint64_t)r * 64 < K;
     const uint32_t d = (key[r] >> a.shift) & mask;
-    uint64_t peers = __ballot(valid);
-    for (int b = 0; b < a.nbits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      peers &= bit ? bb : ~bb;
-    }
+    const uint64_t peers = match_digit(d, a.nbits, valid);
     const uint32_t before = wc[w][d];
     rk[r] = before + (uint32_t)__popcll(peers & lt);
     __builtin_amdgcn_wave_barrier();
@@ -1195,13 +1209,7 @@ __device__ inline void rank_chunk(const uint32_t (&key)[IPT], uint32_t (&rk)[IPT
     if ((uint32_t)r < R && wbase + (uint32_t)r * 64u < m) {  // uniform over the wave
       const bool valid = wbase + (uint32_t)r * 64u + (uint32_t)lane < m;
       const uint32_t d = (key[r] >> shift) & 255u;
-      uint64_t peers = __ballot(valid);
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bb = __ballot(bit);
-        peers &= bit ? bb : ~bb;
-      }
+      const uint64_t peers = match_digit(d, 8, valid);
       const uint32_t before = wc[w][d];
       rk[r] = before + (uint32_t)__popcll(peers & lt);
       __builtin_amdgcn_wave_barrier();
@@ -1483,13 +1491,7 @@ __device__ inline void sort_list_wave(const Seg &a, uint32_t t, uint32_t start, 
       if ((uint32_t)r < R) {  // uniform over the wave
         const bool valid = (uint32_t)r * 64u + (uint32_t)lane < n;
         const uint32_t d = (key[r] >> shift) & 255u;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const bool bit = (d >> b) & 1u;
-          const uint64_t bb = __ballot(bit);
-          peers &= bit ? bb : ~bb;
-        }
+        const uint64_t peers = match_digit(d, 8, valid);
         const uint32_t before = wl.wc[d];
         rk[r] = before + (uint32_t)__popcll(peers & lt);
         wave_sync();

@@ -103,6 +103,11 @@ __device__ inline uint64_t match_digit(uint32_t d, int nbits, bool valid) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// set bits of m below this lane: the lane's rank among the lanes of m
+__device__ inline uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // exclusive scan over the 256 threads of a workgroup; also returns the total
 template <typename T>
 __device__ inline T block_exclusive(T v, T &total) {
@@ -260,7 +265,6 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
   __syncthreads();
 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t lt = (1ull << lane) - 1ull;
   const uint64_t base = (uint64_t)part * PART + (uint64_t)w * (64 * IPT) + lane;
   uint32_t key[IPT], val[IPT], bits[IPT], rk[IPT];
 #pragma unroll
@@ -277,9 +281,10 @@ __global__ __launch_bounds__(BS) void scatter_pass(Pass a) {
     const uint32_t d = (key[r] >> a.shift) & mask;
     const uint64_t peers = match_digit(d, a.nbits, valid);
     const uint32_t before = wc[w][d];
-    rk[r] = before + (uint32_t)__popcll(peers & lt);
+    const uint32_t below = lanes_below(peers);
+    rk[r] = before + below;
     __builtin_amdgcn_wave_barrier();
-    if (valid && (peers & lt) == 0ull) wc[w][d] = before + (uint32_t)__popcll(peers);
+    if (valid && below == 0u) wc[w][d] = before + (uint32_t)__popcll(peers);
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
@@ -1201,7 +1206,6 @@ template <int IPT>
 __device__ inline void rank_chunk(const uint32_t (&key)[IPT], uint32_t (&rk)[IPT], uint32_t m, int shift,
                                   uint32_t (*wc)[RADIX]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t lt = (1ull << lane) - 1ull;
   const uint32_t R = chunk_rounds(m);
   const uint32_t wbase = (uint32_t)w * 64u * R;
 #pragma unroll
@@ -1211,9 +1215,10 @@ __device__ inline void rank_chunk(const uint32_t (&key)[IPT], uint32_t (&rk)[IPT
       const uint32_t d = (key[r] >> shift) & 255u;
       const uint64_t peers = match_digit(d, 8, valid);
       const uint32_t before = wc[w][d];
-      rk[r] = before + (uint32_t)__popcll(peers & lt);
+      const uint32_t below = lanes_below(peers);
+      rk[r] = before + below;
       __builtin_amdgcn_wave_barrier();
-      if (valid && (peers & lt) == 0ull) wc[w][d] = before + (uint32_t)__popcll(peers);
+      if (valid && below == 0u) wc[w][d] = before + (uint32_t)__popcll(peers);
       __builtin_amdgcn_wave_barrier();
     }
   }
@@ -1457,7 +1462,6 @@ __device__ inline void wave_sync() {
 template <int IPT>
 __device__ inline void sort_list_wave(const Seg &a, uint32_t t, uint32_t start, uint32_t n, WaveLds &wl) {
   const int lane = threadIdx.x & 63;
-  const uint64_t lt = (1ull << lane) - 1ull;
   const uint32_t R = (n + 63) / 64;
   uint32_t key[IPT], val[IPT], rk[IPT];
   uint32_t mn = 0xFFFFFFFFu, mx = 0u;
@@ -1493,9 +1497,10 @@ __device__ inline void sort_list_wave(const Seg &a, uint32_t t, uint32_t start, 
         const uint32_t d = (key[r] >> shift) & 255u;
         const uint64_t peers = match_digit(d, 8, valid);
         const uint32_t before = wl.wc[d];
-        rk[r] = before + (uint32_t)__popcll(peers & lt);
+        const uint32_t below = lanes_below(peers);
+        rk[r] = before + below;
         wave_sync();
-        if (valid && (peers & lt) == 0ull) wl.wc[d] = before + (uint32_t)__popcll(peers);
+        if (valid && below == 0u) wl.wc[d] = before + (uint32_t)__popcll(peers);
         wave_sync();
       }
     }

@@ -216,10 +216,25 @@ __global__ __launch_bounds__(BS) void count_pass(const uint32_t *__restrict__ ke
   // partitions share cache lines, which then merge in that XCD's L2
   const uint32_t part = xcd_partition(blockIdx.x, nparts);
   const uint64_t base = (uint64_t)part * PART + threadIdx.x;
+  uint32_t d[IPT];
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     const uint64_t i = base + (uint64_t)r * BS;
-    if (i < K) atomicAdd(&h[w][(keys[i] >> shift) & mask], 1u);
+    d[r] = i < K ? (keys[i] >> shift) & mask : 0u;
+  }
+  // keys often arrive in runs of equal digits (grouped by the lower digits):
+  // a wave whose digits are all equal adds its count once instead of
+  // serializing 64 atomics on one word (valid lanes are a prefix of the wave)
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const bool valid = base + (uint64_t)r * BS < K;
+    const uint32_t first = __builtin_amdgcn_readfirstlane(d[r]);
+    const uint64_t vm = __ballot(valid);
+    if (vm != 0ull && __ballot(valid && d[r] == first) == vm) {  // uniform
+      if ((threadIdx.x & 63) == 0) atomicAdd(&h[w][first], (uint32_t)__popcll(vm));
+    } else if (valid) {
+      atomicAdd(&h[w][d[r]], 1u);
+    }
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < R; d += BS) {

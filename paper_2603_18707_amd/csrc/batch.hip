@@ -42,13 +42,25 @@ struct ViewInfo {
   int32_t row_base, gx, gy, W, H, scene;
 };
 
+// The projection's work order: per scene, its views' 64-splat blocks in
+// groups, so that the views of a scene project the same block back to back on
+// one XCD (workgroup x runs on XCD x mod 8) and all but the first read the
+// splat's 236 bytes from that XCD's L2. Item j of scene s (from base) is
+// block (j / 8 / nv) * 8 + j % 8 of the scene's view sview[off + (j / 8) % nv];
+// a scene takes ceil(blocks / 8) * 8 * nv items.
+struct SceneWork {
+  int64_t base;
+  int32_t nv, off;
+};
+
 // Derives the per-view layout from the view table on the device. Views whose
 // entry fails the same bounds checks the host applied to its own copy (scene
 // index, image size, output ranges) are dropped: they get no pairs and no
 // tiles, so nothing is ever read or written out of range even if the device
 // table differs from the validated host table.
 __global__ void batch_setup(const gs_view *__restrict__ views, int nviews, SceneTable st, int nscenes, int tile,
-                            int gh, int64_t images_len, int64_t planes_len, ViewInfo *__restrict__ info,
+                            int gh, int64_t pairs, int64_t images_len, int64_t planes_len, ViewInfo *__restrict__ info,
+                            SceneWork *__restrict__ swork, int32_t *__restrict__ sview,
                             uint32_t *__restrict__ row_view, uint32_t *__restrict__ counter) {
   for (int r = threadIdx.x; r < gh; r += blockDim.x) row_view[r] = (uint32_t)nviews;  // sentinel: no view
   __syncthreads();
@@ -60,7 +72,8 @@ __global__ void batch_setup(const gs_view *__restrict__ views, int nviews, Scene
       const int64_t W = w.cam.width, H = w.cam.height;
       const bool ok = w.scene >= 0 && w.scene < nscenes && W >= 1 && H >= 1 && W <= 32768 && H <= 32768 &&
                       w.image_offset >= 0 && w.pixel_offset >= 0 && w.image_offset + 3 * W * H <= images_len &&
-                      w.pixel_offset + W * H <= planes_len;
+                      w.pixel_offset + W * H <= planes_len &&
+                      (blocks + (st.n[w.scene] + 63) / 64) * 64 <= pairs;  // the pair arrays hold its range
       ViewInfo in;
       in.scene = ok ? w.scene : 0;
       in.n = ok ? st.n[w.scene] : 0;
@@ -87,6 +100,22 @@ __global__ void batch_setup(const gs_view *__restrict__ views, int nviews, Scene
     end.image_offset = end.pixel_offset = 0;
     info[nviews] = end;
     *counter = 0u;
+    // the projection's work order (SceneWork)
+    int64_t base = 0;
+    int32_t off = 0;
+    for (int sc = 0; sc < nscenes; ++sc) {
+      int32_t nv = 0;
+      for (int v = 0; v < nviews; ++v)
+        if (info[v].n > 0 && info[v].scene == sc) sview[off + nv++] = v;
+      swork[sc].base = base;
+      swork[sc].nv = nv;
+      swork[sc].off = off;
+      base += nv > 0 ? (st.n[sc] + 511) / 512 * 8 * nv : 0;
+      off += nv;
+    }
+    swork[nscenes].base = base;
+    swork[nscenes].nv = 0;
+    swork[nscenes].off = off;
   }
   __syncthreads();
   // virtual tile row -> view
@@ -96,23 +125,24 @@ __global__ void batch_setup(const gs_view *__restrict__ views, int nviews, Scene
   }
 }
 
-__device__ inline int find_view_by_block(const ViewInfo *info, int nviews, int64_t b) {
-  int lo = 0, hi = nviews - 1;  // last view with block_off <= b
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (info[mid].block_off <= b) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
+// One workgroup per work item (SceneWork); the grid may hold spare items,
+// which return.
 template <int DEG>
 __global__ __launch_bounds__(64) void batch_preprocess(PreParams base, SceneTable st, const gs_view *__restrict__ views,
-                                                       const ViewInfo *__restrict__ info, int nviews, PreOut out) {
-  const int v = find_view_by_block(info, nviews, (int64_t)blockIdx.x);
+                                                       const ViewInfo *__restrict__ info,
+                                                       const SceneWork *__restrict__ swork,
+                                                       const int32_t *__restrict__ sview, int nscenes, PreOut out) {
+  const int64_t x = blockIdx.x;
+  int s = 0;
+  while (s < nscenes && swork[s + 1].base <= x) ++s;
+  if (s >= nscenes) return;
+  const SceneWork sw = swork[s];
+  const int64_t j = x - sw.base, y = j >> 3;
+  const int v = sview[sw.off + (int32_t)(y % sw.nv)];
+  const int64_t blk = y / sw.nv * 8 + (j & 7);
   const ViewInfo in = info[v];
-  const int s = in.scene;
-  const int64_t first = ((int64_t)blockIdx.x - in.block_off) * 64;
-  const int64_t i = first + threadIdx.x;
+  if (blk * 64 >= in.n) return;  // past the view's last block
+  const int64_t i = blk * 64 + threadIdx.x;
   const int64_t o = in.pair_off + i;
   float Y[16];
   bool live = false;
@@ -193,6 +223,8 @@ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BatchWs {
   ViewInfo *info;
+  SceneWork *swork;
+  int32_t *sview;
   uint32_t *row_view;
   float *means2d, *conic_opacity, *rgb, *depth;
   int32_t *rect;
@@ -214,6 +246,8 @@ size_t carve_batch(void *base, int nviews, int64_t pairs, int gw, int gh, int64_
   BatchWs t;
   const size_t P = (size_t)(pairs > 0 ? pairs : 1);
   t.info = (ViewInfo *)take(sizeof(ViewInfo) * (nviews + 1));
+  t.swork = (SceneWork *)take(sizeof(SceneWork) * (MAX_SCENES + 1));
+  t.sview = (int32_t *)take(4 * (size_t)(nviews > 0 ? nviews : 1));
   t.row_view = (uint32_t *)take(4 * (size_t)gh);
   t.means2d = (float *)take(8 * P);
   t.conic_opacity = (float *)take(16 * P);
@@ -282,23 +316,29 @@ hipError_t launch_batch(const PreParams &pre, const BlendParams &blend, const gs
     st.opac[i] = scenes[i].opacities;
     st.sh[i] = scenes[i].sh;
   }
-  hipLaunchKernelGGL(batch_setup, dim3(1), dim3(256), 0, s, views_dev, nviews, st, nscenes, pre.tile, gh, images_len,
-                     planes_len, w.info, w.row_view, w.counter);
+  hipLaunchKernelGGL(batch_setup, dim3(1), dim3(256), 0, s, views_dev, nviews, st, nscenes, pre.tile, gh, pairs,
+                     images_len, planes_len, w.info, w.swork, w.sview, w.row_view, w.counter);
   PreOut out{w.means2d, w.conic_opacity, w.rgb, w.depth, w.rect, w.tiles};
-  const unsigned blocks = (unsigned)(pairs / 64);
-  if (blocks > 0) {
+  // the work items: pairs / 64 blocks plus at most 7 spare per view (a
+  // scene's block count rounded up to a multiple of 8 for each of its views)
+  const unsigned items = pairs > 0 ? (unsigned)(pairs / 64 + 7 * (int64_t)nviews) : 0u;
+  if (items > 0) {
     switch (pre.sh_degree) {
       case 0:
-        hipLaunchKernelGGL(batch_preprocess<0>, dim3(blocks), dim3(64), 0, s, pre, st, views_dev, w.info, nviews, out);
+        hipLaunchKernelGGL(batch_preprocess<0>, dim3(items), dim3(64), 0, s, pre, st, views_dev, w.info, w.swork,
+                           w.sview, nscenes, out);
         break;
       case 1:
-        hipLaunchKernelGGL(batch_preprocess<1>, dim3(blocks), dim3(64), 0, s, pre, st, views_dev, w.info, nviews, out);
+        hipLaunchKernelGGL(batch_preprocess<1>, dim3(items), dim3(64), 0, s, pre, st, views_dev, w.info, w.swork,
+                           w.sview, nscenes, out);
         break;
       case 2:
-        hipLaunchKernelGGL(batch_preprocess<2>, dim3(blocks), dim3(64), 0, s, pre, st, views_dev, w.info, nviews, out);
+        hipLaunchKernelGGL(batch_preprocess<2>, dim3(items), dim3(64), 0, s, pre, st, views_dev, w.info, w.swork,
+                           w.sview, nscenes, out);
         break;
       default:
-        hipLaunchKernelGGL(batch_preprocess<3>, dim3(blocks), dim3(64), 0, s, pre, st, views_dev, w.info, nviews, out);
+        hipLaunchKernelGGL(batch_preprocess<3>, dim3(items), dim3(64), 0, s, pre, st, views_dev, w.info, w.swork,
+                           w.sview, nscenes, out);
         break;
     }
   }

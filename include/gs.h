@@ -412,7 +412,8 @@ gs_status gs_batch_layout(const gs_scene *scenes, int32_t num_scenes, const gs_v
  * queue. `views_device` must hold the same table in device memory: kernels
  * read it there, so the call enqueues kernels only (no host copies, no
  * allocation, no memset) and can be captured in a graph and replayed; a device
- * entry that fails the host's bounds checks renders nothing. Outputs equal
+ * entry that fails the host's bounds checks, or whose pairs would not fit the
+ * num_pairs slots sized from the host table, renders nothing. Outputs equal
  * gs_rasterize_fwd's for each view bit for bit. workgroups: persistent blend
  * workgroups (0 = library default). images_len / planes_len: lengths (in
  * elements) of the output buffers, checked against every view's range.

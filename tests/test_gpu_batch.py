@@ -95,6 +95,44 @@ def test_batch_overflow_reported():
     assert int(br.overflow.item()) == 1 and int(br.num_keys.item()) > 50
 
 
+def test_device_view_table_differing_from_the_host_one():
+    """The kernels read the view table from device memory. An entry there that
+    differs from the validated host copy must never reach memory outside the
+    batch's arrays: here view 2 (the empty scene on the host) names the
+    4500-splat scene on the device, so the device layout runs out of pair
+    slots at view 5 (the host sized them for its own table) and drops it (it
+    renders nothing), while every other view renders its device entry."""
+    import ctypes
+    from paper_2603_18707_amd import _lib as L
+    sc, views = _small_batch()
+    dev = [render.to_device(s) for s in sc]
+    kern = ("poly", 1, "opacity")
+    br = batch.BatchRenderer(dev, views, H.gpu_kernel(*kern), H.gpu_params())
+    br.capacity = 4 * br.render_fit() + 4096
+    br._layout()
+    table = (L.GsView * len(views))()
+    ctypes.memmove(table, br.c_views, ctypes.sizeof(table))
+    table[2].scene = 2
+    raw = bytes(ctypes.string_at(ctypes.addressof(table), ctypes.sizeof(table)))
+    br.views_dev.copy_(torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(br.device))
+    for t in (br.images, br.final_T):
+        t.fill_(-7.0)
+    for t in (br.n_contrib, br.last_contrib):
+        t.fill_(-7)
+    br.render()
+    torch.cuda.synchronize()
+    assert int(br.overflow.item()) == 0
+    rendered = [(i, (2, views[i][1]) if i == 2 else views[i]) for i in (0, 1, 2, 3, 4, 6)]
+    ref = _per_view(dev, [v for _, v in rendered], kern)
+    for (i, _), r in zip(rendered, ref):
+        o = br.view_outputs(i)
+        for k in r:
+            assert np.array_equal(o[k].cpu().numpy(), r[k]), (i, k)
+    o = br.view_outputs(5)  # dropped: untouched
+    assert bool((o["image"] == -7.0).all()) and bool((o["final_T"] == -7.0).all())
+    assert bool((o["n_contrib"] == -7).all()) and bool((o["last_contrib"] == -7).all())
+
+
 def test_full_size_batched_workload_sampled_views():
     """6 scenes (100k..2M splats, SH3), 96 views at 640x360..1920x1080."""
     sc, views = scenes.workload_batched()

@@ -53,6 +53,24 @@ __device__ inline float poly(const BlendParams &p, int order, float Q) {
   return fmaf(fmaf(fmaf(p.c[3], Q, p.c[2]), Q, p.c[1]), Q, p.c[0]);
 }
 
+// Sum of v over the 64 lanes of the wave, in the last lane (the other lanes
+// hold partial sums): pairs, quads, half rows and rows of 16 by DPP moves,
+// then row 0 into row 1 and row 2 into row 3 (row_bcast:15), then rows 0-1
+// into rows 2-3 (row_bcast:31). Every lane of the wave must be active.
+template <int CTRL, int ROWS>
+__device__ inline float dpp_term(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+__device__ inline float wave_sum_to_last_lane(float v) {
+  v += dpp_term<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_term<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_term<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_term<0x140, 0xF>(v);  // row_mirror
+  v += dpp_term<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_term<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 constexpr int BT = 256;            // threads per tile in the adjoint
 constexpr int BW = BT / WAVE;       // waves, each an 8x8 block
 constexpr int NG = 9;               // partial gradients per record
@@ -159,7 +177,9 @@ __global__ __launch_bounds__(BT) void blend_bwd(BlendParams p, const float *__re
 #pragma unroll
     for (int s = 0; s < BW; ++s) len += wcnt[s][wv];
     __syncthreads();
-    // this wave's records, back to front
+    // this wave's records, back to front; a record's nine partial gradients
+    // are summed over the wave's passing pixels (lanes that do not pass add
+    // zeros) and added to its LDS accumulators by one lane
     for (int q = (int)len - 1; q >= 0; --q) {
       const int j = lst[wv][q];
       const uint32_t pos = (uint32_t)(lo + 1 + j);
@@ -167,41 +187,55 @@ __global__ __launch_bounds__(BT) void blend_bwd(BlendParams p, const float *__re
       const float4 r0 = L0[j];
       const float4 r1 = L1[j];
       const float t = t_at(row_part(r0, r1.y, fx), r1.x, fy);
-      if (!(t >= 0.0f && pos <= lastc)) continue;
-      const float4 r2 = L2[j];
-      const float2 ab = L3[j];
-      const float o = r1.w;
-      const float a = alpha_from<KIND>(t, r1, p);
-      const float oma = 1.0f - a;
-      T = T / oma;  // transmittance before this splat
-      const float w = a * T;
-      const float dLda = T * ((r2.x - S0) * g0 + (r2.y - S1) * g1 + (r2.z - S2) * g2) - Tf / oma * bgg;
-      S0 = fmaf(a, r2.x - S0, S0);
-      S1 = fmaf(a, r2.y - S1, S1);
-      S2 = fmaf(a, r2.z - S2, S2);
-      atomicAdd(&G[6][j], w * g0);
-      atomicAdd(&G[7][j], w * g1);
-      atomicAdd(&G[8][j], w * g2);
-      // alpha = o' k(Q) unless clamped; Q from the same t the decisions used
-      const float Q = r1.y - t;
-      float kq, dk;
-      if (KIND == BLEND_EXP) {
-        kq = __expf(-0.5f * Q);
-        dk = -0.5f * kq;
-      } else {
-        kq = poly(p, ORDER, Q);
-        dk = dpoly(p, ORDER, Q);
+      const bool pass = t >= 0.0f && pos <= lastc;
+      if (__builtin_amdgcn_ballot_w64(pass) == 0ull) continue;  // uniform
+      float c[NG];
+#pragma unroll
+      for (int k = 0; k < NG; ++k) c[k] = 0.0f;
+      if (pass) {
+        const float4 r2 = L2[j];
+        const float2 ab = L3[j];
+        const float o = r1.w;
+        const float a = alpha_from<KIND>(t, r1, p);
+        const float oma = 1.0f - a;
+        const float ioma = 1.0f / oma;
+        T = T * ioma;  // transmittance before this splat
+        const float w = a * T;
+        const float dLda = T * ((r2.x - S0) * g0 + (r2.y - S1) * g1 + (r2.z - S2) * g2) - Tf * ioma * bgg;
+        S0 = fmaf(a, r2.x - S0, S0);
+        S1 = fmaf(a, r2.y - S1, S1);
+        S2 = fmaf(a, r2.z - S2, S2);
+        c[6] = w * g0;
+        c[7] = w * g1;
+        c[8] = w * g2;
+        // alpha = o' k(Q) unless clamped; Q from the same t the decisions used
+        const float Q = r1.y - t;
+        float kq, dk;
+        if (KIND == BLEND_EXP) {
+          kq = __expf(-0.5f * Q);
+          dk = -0.5f * kq;
+        } else {
+          kq = poly(p, ORDER, Q);
+          dk = dpoly(p, ORDER, Q);
+        }
+        if (!(o * kq > p.alpha_max)) {
+          const float dx = fx - r0.x, dy = fy - r0.y;
+          const float dLdQ = dLda * o * dk;
+          c[5] = dLda * kq;
+          c[2] = dLdQ * dx * dx;
+          c[3] = dLdQ * 2.0f * dx * dy;
+          c[4] = dLdQ * dy * dy;
+          // Q depends on the mean through d = pixel - mean
+          c[0] = dLdQ * -2.0f * (ab.x * dx + ab.y * dy);
+          c[1] = dLdQ * -2.0f * (ab.y * dx + r1.x * dy);
+        }
       }
-      if (o * kq > p.alpha_max) continue;
-      const float dx = fx - r0.x, dy = fy - r0.y;
-      const float dLdQ = dLda * o * dk;
-      atomicAdd(&G[5][j], dLda * kq);
-      atomicAdd(&G[2][j], dLdQ * dx * dx);
-      atomicAdd(&G[3][j], dLdQ * 2.0f * dx * dy);
-      atomicAdd(&G[4][j], dLdQ * dy * dy);
-      // Q depends on the mean through d = pixel - mean
-      atomicAdd(&G[0][j], dLdQ * -2.0f * (ab.x * dx + ab.y * dy));
-      atomicAdd(&G[1][j], dLdQ * -2.0f * (ab.y * dx + r1.x * dy));
+#pragma unroll
+      for (int k = 0; k < NG; ++k) c[k] = wave_sum_to_last_lane(c[k]);
+      if (l64 == WAVE - 1) {
+#pragma unroll
+        for (int k = 0; k < NG; ++k) atomicAdd(&G[k][j], c[k]);
+      }
     }
     __syncthreads();
     if (lane < cnt) {

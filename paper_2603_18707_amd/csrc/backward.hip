@@ -53,21 +53,18 @@ __device__ inline float poly(const BlendParams &p, int order, float Q) {
   return fmaf(fmaf(fmaf(p.c[3], Q, p.c[2]), Q, p.c[1]), Q, p.c[0]);
 }
 
-// Sum of v over the 64 lanes of the wave, in the last lane (the other lanes
-// hold partial sums): pairs, quads, half rows and rows of 16 by DPP moves,
-// then row 0 into row 1 and row 2 into row 3 (row_bcast:15), then rows 0-1
-// into rows 2-3 (row_bcast:31). Every lane of the wave must be active.
+// Sums of v over the four rows of 16 lanes of the wave, each in every lane of
+// its row: pairs, quads, half rows and rows by DPP moves (every lane of the
+// wave must be active).
 template <int CTRL, int ROWS>
 __device__ inline float dpp_term(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
 }
-__device__ inline float wave_sum_to_last_lane(float v) {
+__device__ inline float row_sum(float v) {
   v += dpp_term<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
   v += dpp_term<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
   v += dpp_term<0x141, 0xF>(v);  // row_half_mirror
   v += dpp_term<0x140, 0xF>(v);  // row_mirror
-  v += dpp_term<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_term<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
   return v;
 }
 
@@ -178,8 +175,9 @@ __global__ __launch_bounds__(BT) void blend_bwd(BlendParams p, const float *__re
     for (int s = 0; s < BW; ++s) len += wcnt[s][wv];
     __syncthreads();
     // this wave's records, back to front; a record's nine partial gradients
-    // are summed over the wave's passing pixels (lanes that do not pass add
-    // zeros) and added to its LDS accumulators by one lane
+    // are summed over each row of 16 lanes (lanes that do not pass add zeros)
+    // and added to its LDS accumulators by one lane per row with a passing
+    // pixel, instead of one float atomic per passing pixel on the same words
     for (int q = (int)len - 1; q >= 0; --q) {
       const int j = lst[wv][q];
       const uint32_t pos = (uint32_t)(lo + 1 + j);
@@ -188,7 +186,8 @@ __global__ __launch_bounds__(BT) void blend_bwd(BlendParams p, const float *__re
       const float4 r1 = L1[j];
       const float t = t_at(row_part(r0, r1.y, fx), r1.x, fy);
       const bool pass = t >= 0.0f && pos <= lastc;
-      if (__builtin_amdgcn_ballot_w64(pass) == 0ull) continue;  // uniform
+      const uint64_t pm = __builtin_amdgcn_ballot_w64(pass);
+      if (pm == 0ull) continue;  // uniform
       float c[NG];
 #pragma unroll
       for (int k = 0; k < NG; ++k) c[k] = 0.0f;
@@ -198,7 +197,7 @@ __global__ __launch_bounds__(BT) void blend_bwd(BlendParams p, const float *__re
         const float o = r1.w;
         const float a = alpha_from<KIND>(t, r1, p);
         const float oma = 1.0f - a;
-        const float ioma = 1.0f / oma;
+        const float ioma = __builtin_amdgcn_rcpf(oma);
         T = T * ioma;  // transmittance before this splat
         const float w = a * T;
         const float dLda = T * ((r2.x - S0) * g0 + (r2.y - S1) * g1 + (r2.z - S2) * g2) - Tf * ioma * bgg;
@@ -231,8 +230,8 @@ __global__ __launch_bounds__(BT) void blend_bwd(BlendParams p, const float *__re
         }
       }
 #pragma unroll
-      for (int k = 0; k < NG; ++k) c[k] = wave_sum_to_last_lane(c[k]);
-      if (l64 == WAVE - 1) {
+      for (int k = 0; k < NG; ++k) c[k] = row_sum(c[k]);
+      if ((l64 & 15) == 15 && ((pm >> (l64 & 48)) & 0xFFFFull) != 0ull) {
 #pragma unroll
         for (int k = 0; k < NG; ++k) atomicAdd(&G[k][j], c[k]);
       }

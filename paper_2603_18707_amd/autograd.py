@@ -45,10 +45,10 @@ def preprocess_backward(r: Rasterizer, scene: DeviceScene, frame: dict, cam, g2d
 
 class _Render(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means3d, scales, quats, opacities, sh, sh_degree, cam, r):
+    def forward(ctx, means3d, scales, quats, opacities, sh, sh_degree, cam, r, sync):
         scene = DeviceScene(means3d.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
                             opacities.detach().contiguous(), sh.detach().contiguous(), int(sh_degree))
-        frame = r.render(scene, cam)
+        frame = r.render(scene, cam, sync=sync)
         ctx.scene, ctx.frame, ctx.cam, ctx.r = scene, frame, cam, r
         return frame["image"]
 
@@ -56,14 +56,16 @@ class _Render(torch.autograd.Function):
     def backward(ctx, dL_dimage):
         g2d = rasterize_backward(ctx.r, ctx.frame, ctx.cam, dL_dimage)
         g3d = preprocess_backward(ctx.r, ctx.scene, ctx.frame, ctx.cam, g2d)
-        return g3d["means3d"], g3d["scales"], g3d["quats"], g3d["opacities"], g3d["sh"], None, None, None
+        return g3d["means3d"], g3d["scales"], g3d["quats"], g3d["opacities"], g3d["sh"], None, None, None, None
 
 
 def render(means3d, scales, quats, opacities, sh, sh_degree: int, cam, kernel: L.GsKernel,
-           params: L.GsParams = None, rasterizer: Rasterizer = None) -> torch.Tensor:
+           params: L.GsParams = None, rasterizer: Rasterizer = None, sync: bool = True) -> torch.Tensor:
     """Differentiable image [3, H, W] of the scene (activated parameters).
     Passing the same ``rasterizer`` (built with reuse_buffers=False) across
-    steps keeps its fitted key capacity."""
+    steps keeps its fitted key capacity; with sync=False the forward enqueues
+    without reading the overflow flag back (see Rasterizer.render), and the
+    caller checks rasterizer.check_overflow() once it has synchronised."""
     r = rasterizer if rasterizer is not None else Rasterizer(kernel, params, device=means3d.device,
                                                              reuse_buffers=False)
-    return _Render.apply(means3d, scales, quats, opacities, sh, sh_degree, cam, r)
+    return _Render.apply(means3d, scales, quats, opacities, sh, sh_degree, cam, r, sync)

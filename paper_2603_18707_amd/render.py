@@ -75,6 +75,7 @@ class Rasterizer:
         self.capacity = int(capacity)
         self.reuse = reuse_buffers  # False: every frame gets fresh outputs (autograd keeps them)
         self._bufs = {}
+        self._overflow_acc = None  # overflow flags of the frames binned without a readback (render(sync=False))
 
     # -- buffers ---------------------------------------------------------
     def _buf(self, name, shape, dtype):
@@ -168,8 +169,31 @@ class Rasterizer:
             L.gs_rasterize_fwd(*args, stream)
         return out
 
-    def render(self, scene: DeviceScene, cam, want_eval: bool = False, stream=None) -> dict:
+    def render(self, scene: DeviceScene, cam, want_eval: bool = False, stream=None, sync: bool = True) -> dict:
+        """One frame. sync=False bins with the current key capacity (fitted by an
+        earlier frame) without reading the overflow flag back, so the frame
+        enqueues with no host round trip; the flag is OR-ed into a device
+        accumulator that check_overflow() reads (a frame that overflowed has
+        no keys and must be redone with a larger capacity)."""
         proj = self.preprocess(scene, cam, stream)
-        binned = self.bin_sort_fit(proj, cam, stream)
+        if sync:
+            binned = self.bin_sort_fit(proj, cam, stream)
+        else:
+            binned = self.bin_sort(proj, cam, stream=stream)
+            if self._overflow_acc is None:
+                self._overflow_acc = torch.zeros(1, dtype=torch.int32, device=self.device)
+            self._overflow_acc.bitwise_or_(binned["overflow"])
         img = self.rasterize(proj, binned, cam, want_eval, stream)
         return dict(proj=proj, binned=binned, **img)
+
+    def check_overflow(self) -> int:
+        """Reads (and clears) the overflow flags of the frames rendered with
+        sync=False since the last check; raises when any frame overflowed."""
+        if self._overflow_acc is None:
+            return 0
+        flag = int(self._overflow_acc.item())
+        self._overflow_acc.zero_()
+        if flag:
+            raise RuntimeError(f"a frame rendered with sync=False overflowed (flags {flag}); "
+                               f"render it again with sync=True to fit the key capacity")
+        return flag

@@ -228,3 +228,38 @@ def test_multistage_record_gradients_match_reference(kind, order, radius, logit_
                        ("c", gc[:, 2], "c"), ("opacity", gc[:, 3], "opac")):
         _compare(name, g, leaf[k].grad.numpy())
     _compare("rgb", g2d["rgb"].cpu().numpy(), leaf["rgb"].grad.numpy())
+
+
+def test_sync_free_frames_match_and_report_overflow():
+    """Rasterizer.render(sync=False) (and autograd.render(sync=False)) bins
+    with the fitted key capacity without reading the overflow flag back: the
+    image and the gradients equal those of a fitted frame bit for bit, and a
+    frame whose keys do not fit raises at check_overflow()."""
+    scene, cam = _scene(4.0)
+    kern, params = H.gpu_kernel("poly", 1, "opacity"), H.gpu_params()
+    dev = {k: torch.tensor(np.asarray(getattr(scene, k), np.float32), device="cuda", requires_grad=True)
+           for k in ("means3d", "scales", "quats", "opacities", "sh")}
+    w = torch.as_tensor(np.random.default_rng(34).normal(size=(3, cam.height, cam.width)), dtype=torch.float32,
+                        device="cuda")
+    r = render.Rasterizer(kern, params, reuse_buffers=False)
+    grads, imgs = [], []
+    for sync in (True, False):
+        for t in dev.values():
+            t.grad = None
+        img = autograd.render(*[dev[k] for k in ("means3d", "scales", "quats", "opacities", "sh")],
+                              scene.sh_degree, cam, kern, params, rasterizer=r, sync=sync)
+        (img * w).sum().backward()
+        torch.cuda.synchronize()
+        imgs.append(img.detach().cpu().numpy())
+        grads.append({k: t.grad.cpu().numpy() for k, t in dev.items()})
+    assert r.check_overflow() == 0
+    assert np.array_equal(imgs[0], imgs[1])
+    # float atomics add the partial gradients in any order: equal up to rounding
+    for k in dev:
+        np.testing.assert_allclose(grads[1][k], grads[0][k], rtol=1e-5, atol=1e-6 * np.abs(grads[0][k]).max())
+    r.capacity = 16  # far fewer than the frame's keys
+    r.render(render.to_device(scene), cam, sync=False)
+    torch.cuda.synchronize()
+    with pytest.raises(RuntimeError, match="overflowed"):
+        r.check_overflow()
+    assert r.check_overflow() == 0  # cleared by the check

@@ -100,22 +100,27 @@ __global__ void batch_setup(const gs_view *__restrict__ views, int nviews, Scene
     end.image_offset = end.pixel_offset = 0;
     info[nviews] = end;
     *counter = 0u;
-    // the projection's work order (SceneWork)
+    // the projection's work order (SceneWork): the views with pairs, grouped
+    // by scene in view order (a counting sort over the scenes)
+    int32_t nv[MAX_SCENES], at[MAX_SCENES];
+    for (int sc = 0; sc < MAX_SCENES; ++sc) nv[sc] = 0;
+    for (int v = 0; v < nviews; ++v)
+      if (info[v].n > 0) ++nv[info[v].scene];
     int64_t base = 0;
     int32_t off = 0;
     for (int sc = 0; sc < nscenes; ++sc) {
-      int32_t nv = 0;
-      for (int v = 0; v < nviews; ++v)
-        if (info[v].n > 0 && info[v].scene == sc) sview[off + nv++] = v;
       swork[sc].base = base;
-      swork[sc].nv = nv;
+      swork[sc].nv = nv[sc];
       swork[sc].off = off;
-      base += nv > 0 ? (st.n[sc] + 511) / 512 * 8 * nv : 0;
-      off += nv;
+      at[sc] = off;
+      base += nv[sc] > 0 ? (st.n[sc] + 511) / 512 * 8 * nv[sc] : 0;
+      off += nv[sc];
     }
     swork[nscenes].base = base;
     swork[nscenes].nv = 0;
     swork[nscenes].off = off;
+    for (int v = 0; v < nviews; ++v)
+      if (info[v].n > 0) sview[at[info[v].scene]++] = v;
   }
   __syncthreads();
   // virtual tile row -> view
